@@ -1,0 +1,1002 @@
+/*
+ * pond_oracle.c -- plain, slow, FP64 CPU oracle of the finite-volume
+ * Particles-on-Demand (PonD) time step of Kallikounis, Dorschner & Karlin,
+ * "Particles on Demand for flows with strong discontinuities".
+ *
+ * TEST INFRASTRUCTURE. This is the reference the HIP library is checked against.
+ * Only the tests, the smoke check and the CPU-baseline leg of the benchmark may
+ * load it. It shares no code, header, table or constant with the GPU library.
+ *
+ * The step follows the paper's own summary of the finite-volume algorithm
+ * (Sec. III.B.4): a loop over cells that expresses every cell's populations in
+ * its co-moving frame, a loop over cells that forms phi-bar-plus, a loop over
+ * faces that runs the predictor-corrector frame iteration of Sec. III.B.3, and a
+ * loop over cells that converts the face fluxes into each cell's frame and applies
+ * the co-moving update of Sec. III.B.2. All arithmetic is IEEE double precision
+ * (no fast-math), written with explicit loops and full tensors in the paper's
+ * lab-frame notation (moments M_k, Grad coefficients a_k).
+ *
+ * Readings where the paper is silent (each repeated where it is used):
+ *  - gas constant R = 1, so p = rho T and C_v = 1/(gamma-1);
+ *  - tau = mu/p (Chapman-Enskog for single-relaxation BGK, Prandtl 1), and every
+ *    relaxation coefficient is written with eps = dt/tau = dt p/mu;
+ *  - the "overline" symmetrization of Sec. II.C sums the distinct index
+ *    permutations without a 1/n! factor;
+ *  - Van Leer limiter by default, minmod on request, zero on a sign change or zero;
+ *  - upwind cell is the left/lower one when the normal component v_i.n >= 0;
+ *  - frame convergence: max(|u^(k+1)-u^(k)|_inf / sqrt(T^(k+1)),
+ *    |T^(k+1)-T^(k)| / T^(k+1)) <= tol; the face keeps the moments of the last
+ *    reconstruction and the frame computed from them;
+ *  - seed of the first step: frame of the mean conserved variables of the two
+ *    cells next to the face; later steps: the face frame of the previous step;
+ *  - the face equilibrium used to recover phi from phi-bar is the co-moving
+ *    equilibrium of the face's final frame, applied to the moments;
+ *  - two ghost layers; x-ghosts are filled for the interior rows first, then the
+ *    y-ghosts of every column (so corner ghosts take the y rule of an x-ghost);
+ *  - a corrector frame with rho <= 0 or T <= 0 restarts the iteration once from
+ *    the frame of the mean conserved variables of the two neighbours; a second
+ *    such frame switches the face to the first-order upwind state assembled from
+ *    each neighbour's populations in that neighbour's own frame.
+ */
+#include "pond_oracle.h"
+
+#include <math.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define TL 1.0 /* lattice temperature of Table I */
+#define MAXD 2
+#define MAXQ 16
+#define NG 2 /* ghost layers */
+
+/* ------------------------------------------------------------------------- */
+/* lattice (Sec. II.A, Table I)                                              */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    int D, Q;
+    double c[MAXQ][MAXD];
+    double W[MAXQ];
+} lattice;
+
+/* D1Q4 nodes are the roots of the fourth Hermite polynomial, +-sqrt(3 -+ sqrt 6),
+ * with Gauss-Hermite weights (3 +- sqrt 6)/12; D2Q16 is their tensor product,
+ * W_i = w_ix w_iy. Index i = ix + 4 iy with nodes sorted ascending. */
+static void make_lattice(int D, lattice *L)
+{
+    const double r6 = sqrt(6.0);
+    const double c1[4] = {-sqrt(3.0 + r6), -sqrt(3.0 - r6), sqrt(3.0 - r6), sqrt(3.0 + r6)};
+    const double w1[4] = {(3.0 - r6) / 12.0, (3.0 + r6) / 12.0, (3.0 + r6) / 12.0,
+                          (3.0 - r6) / 12.0};
+    memset(L, 0, sizeof(*L));
+    L->D = D;
+    L->Q = (D == 1) ? 4 : 16;
+    for (int i = 0; i < L->Q; ++i) {
+        int ix = i % 4, iy = i / 4;
+        L->c[i][0] = c1[ix];
+        L->W[i] = w1[ix];
+        if (D == 2) {
+            L->c[i][1] = c1[iy];
+            L->W[i] *= w1[iy];
+        }
+    }
+}
+
+int orc_lattice(int dim, double *c, double *W)
+{
+    lattice L;
+    make_lattice(dim, &L);
+    for (int i = 0; i < L.Q; ++i) {
+        for (int a = 0; a < dim; ++a) c[i * dim + a] = L.c[i][a];
+        W[i] = L.W[i];
+    }
+    return L.Q;
+}
+
+/* particle velocities in frame lambda = {u, T}: v_i = sqrt(T/T_L) c_i + u (Sec. II.C) */
+static void velocities(const lattice *L, const double *u, double T, double v[MAXQ][MAXD])
+{
+    double s = sqrt(T / TL);
+    for (int i = 0; i < L->Q; ++i)
+        for (int a = 0; a < L->D; ++a) v[i][a] = s * L->c[i][a] + u[a];
+}
+
+/* ------------------------------------------------------------------------- */
+/* moment tensors and the Grad projection (Sec. II.C)                        */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double t0;
+    double t1[MAXD];
+    double t2[MAXD][MAXD];
+    double t3[MAXD][MAXD][MAXD];
+} tensors;
+
+static double kd(int a, int b) { return a == b ? 1.0 : 0.0; }
+
+/* M_k = sum_i f_i v_i (x) ... (x) v_i, k = 0..3, in the lab frame */
+static void moments(const lattice *L, const double *f, const double *u, double T, tensors *M)
+{
+    double v[MAXQ][MAXD];
+    const int D = L->D;
+    velocities(L, u, T, v);
+    memset(M, 0, sizeof(*M));
+    for (int i = 0; i < L->Q; ++i) {
+        M->t0 += f[i];
+        for (int a = 0; a < D; ++a) {
+            M->t1[a] += f[i] * v[i][a];
+            for (int b = 0; b < D; ++b) {
+                M->t2[a][b] += f[i] * v[i][a] * v[i][b];
+                for (int c = 0; c < D; ++c) M->t3[a][b][c] += f[i] * v[i][a] * v[i][b] * v[i][c];
+            }
+        }
+    }
+}
+
+/* Grad coefficients that make the projected populations reproduce M_0..M_order in
+ * the target frame {u', T'}: the closed forms for a_0, a_1, a_2, a_3 of Sec. II.C
+ * (with T_L = 1 kept explicit). */
+static void grad_coefficients(int D, int order, const tensors *M, const double *up, double Tp,
+                              tensors *a)
+{
+    const double th = Tp / TL;
+    const double sq = sqrt(th);
+    memset(a, 0, sizeof(*a));
+    a->t0 = M->t0;
+    for (int al = 0; al < D; ++al) a->t1[al] = (M->t1[al] - M->t0 * up[al]) / sq;
+    for (int al = 0; al < D; ++al)
+        for (int be = 0; be < D; ++be) {
+            double sym_u_a1 = up[al] * a->t1[be] + up[be] * a->t1[al];
+            a->t2[al][be] = (M->t2[al][be] - M->t0 * Tp * kd(al, be) - sq * sym_u_a1 -
+                             M->t0 * up[al] * up[be]) /
+                            th;
+        }
+    if (order < 3) return;
+    for (int al = 0; al < D; ++al)
+        for (int be = 0; be < D; ++be)
+            for (int ga = 0; ga < D; ++ga) {
+                /* sym(u' (x) (M0 T_L I + a2)) */
+                double s1 = up[al] * (M->t0 * TL * kd(be, ga) + a->t2[be][ga]) +
+                            up[be] * (M->t0 * TL * kd(al, ga) + a->t2[al][ga]) +
+                            up[ga] * (M->t0 * TL * kd(al, be) + a->t2[al][be]);
+                /* sym(a1 (x) I) */
+                double s2 = a->t1[al] * kd(be, ga) + a->t1[be] * kd(al, ga) + a->t1[ga] * kd(al, be);
+                /* sym(a1 (x) u' (x) u') */
+                double s3 = a->t1[al] * up[be] * up[ga] + a->t1[be] * up[al] * up[ga] +
+                            a->t1[ga] * up[al] * up[be];
+                a->t3[al][be][ga] = (M->t3[al][be][ga] - th * s1 - Tp * sq * s2 - sq * s3 -
+                                     M->t0 * up[al] * up[be] * up[ga]) /
+                                    (th * sq);
+            }
+}
+
+/* the Grad expansion of Sec. II.C: f_i = W_i (a0 + a1.c/T_L + a2:(cc - T_L I)/(2 T_L^2)
+ * + a3:(ccc - T_L sym(c (x) I))/(6 T_L^3)); order 2 drops the last term */
+static void grad_populations(const lattice *L, int order, const tensors *a, double *f)
+{
+    const int D = L->D;
+    for (int i = 0; i < L->Q; ++i) {
+        const double *c = L->c[i];
+        double s = a->t0;
+        for (int al = 0; al < D; ++al) s += a->t1[al] * c[al] / TL;
+        for (int al = 0; al < D; ++al)
+            for (int be = 0; be < D; ++be)
+                s += a->t2[al][be] * (c[al] * c[be] - TL * kd(al, be)) / (2.0 * TL * TL);
+        if (order >= 3)
+            for (int al = 0; al < D; ++al)
+                for (int be = 0; be < D; ++be)
+                    for (int ga = 0; ga < D; ++ga) {
+                        double h3 = c[al] * c[be] * c[ga] -
+                                    TL * (c[al] * kd(be, ga) + c[be] * kd(al, ga) + c[ga] * kd(al, be));
+                        s += a->t3[al][be][ga] * h3 / (6.0 * TL * TL * TL);
+                    }
+        f[i] = L->W[i] * s;
+    }
+}
+
+static void grad_project(const lattice *L, int order, const tensors *M, const double *up,
+                         double Tp, double *f)
+{
+    tensors a;
+    grad_coefficients(L->D, order, M, up, Tp, &a);
+    grad_populations(L, order, &a, f);
+}
+
+/* packing helpers for the exported unit functions */
+static void pack(int D, int order, const tensors *M, double *out)
+{
+    int k = 0;
+    out[k++] = M->t0;
+    if (order >= 1)
+        for (int a = 0; a < D; ++a) out[k++] = M->t1[a];
+    if (order >= 2)
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) out[k++] = M->t2[a][b];
+    if (order >= 3)
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                for (int c = 0; c < D; ++c) out[k++] = M->t3[a][b][c];
+}
+
+static void unpack(int D, int order, const double *in, tensors *M)
+{
+    int k = 0;
+    memset(M, 0, sizeof(*M));
+    M->t0 = in[k++];
+    if (order >= 1)
+        for (int a = 0; a < D; ++a) M->t1[a] = in[k++];
+    if (order >= 2)
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b) M->t2[a][b] = in[k++];
+    if (order >= 3)
+        for (int a = 0; a < D; ++a)
+            for (int b = 0; b < D; ++b)
+                for (int c = 0; c < D; ++c) M->t3[a][b][c] = in[k++];
+}
+
+void orc_moments(int dim, int order, const double *f, const double *u, double T, double *M)
+{
+    lattice L;
+    tensors t;
+    make_lattice(dim, &L);
+    moments(&L, f, u, T, &t);
+    pack(dim, order, &t, M);
+}
+
+void orc_grad_project(int dim, int order, const double *M, const double *u, double T, double *f)
+{
+    lattice L;
+    tensors t;
+    make_lattice(dim, &L);
+    unpack(dim, order, M, &t);
+    grad_project(&L, order, &t, u, T, f);
+}
+
+void orc_grad_coefficients(int dim, int order, const double *M, const double *u, double T, double *a)
+{
+    tensors t, c;
+    unpack(dim, order, M, &t);
+    grad_coefficients(dim, order, &t, u, T, &c);
+    pack(dim, order, &c, a);
+}
+
+/* ------------------------------------------------------------------------- */
+/* relaxation maps (Sec. III.B.1-3), all in terms of eps = dt/tau            */
+/* ------------------------------------------------------------------------- */
+
+/* phi from the carried variable phi~ = phi - (dt/2tau)(phi_eq - phi) */
+static double phi_from_tilde(double ft, double feq, double eps)
+{
+    return (2.0 * ft + eps * feq) / (2.0 + eps);
+}
+
+/* phi-bar-plus = phi + (h/2)(phi_eq - phi)/tau with h = dt/2, i.e. + (eps/4)(phi_eq - phi) */
+double orc_phibar_plus(double ftilde, double feq, double eps)
+{
+    double phi = phi_from_tilde(ftilde, feq, eps);
+    return phi + 0.25 * eps * (feq - phi);
+}
+
+/* phi at the face from phi-bar = phi - (eps/4)(phi_eq - phi), eps = dt/tau at the face */
+double orc_face_recover(double phibar, double feq, double eps_face)
+{
+    return (phibar + 0.25 * eps_face * feq) / (1.0 + 0.25 * eps_face);
+}
+
+/* collision part of the co-moving update: ((2tau-dt)/(2tau+dt)) phi~ + (2dt/(2tau+dt)) phi_eq */
+double orc_update_relax(double ftilde, double feq, double eps)
+{
+    return ((2.0 - eps) / (2.0 + eps)) * ftilde + (2.0 * eps / (2.0 + eps)) * feq;
+}
+
+/* slope limiters: backward and forward one-sided differences */
+double orc_limiter(int kind, double a, double b)
+{
+    if (a * b <= 0.0) return 0.0;
+    if (kind == ORC_LIM_MINMOD) return (a > 0.0) ? fmin(a, b) : fmax(a, b);
+    return 2.0 * a * b / (a + b); /* Van Leer */
+}
+
+/* ------------------------------------------------------------------------- */
+/* simulation state                                                          */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double f[MAXQ], g[MAXQ]; /* populations (carried f~, g~; or phi-bar-plus for stencils) */
+    double u[MAXD], T;       /* frame the populations are expressed in */
+    double rho;              /* density of the cell (zeroth moment)    */
+} cellrec;
+
+typedef struct {
+    double Mf[1 + MAXD + MAXD * MAXD + MAXD * MAXD * MAXD];
+    double Mg[1 + MAXD + MAXD * MAXD];
+    double u[MAXD], T;   /* final face frame (seed of the next step) */
+    double su[MAXD], sT; /* seed                                     */
+    int seeded;
+    int iters;
+} facerec;
+
+struct orc_sim {
+    orc_config cfg;
+    lattice L;
+    int D, Q, nx, ny, nxg, nyg;
+    double dx[MAXD];
+    double Cv;
+    double t;
+    long long nstep;
+    cellrec *cell;   /* carried state, interior + ghost storage (ghosts unused) */
+    cellrec *plus;   /* phi-bar-plus of every cell, ghosts included             */
+    facerec *face;   /* x-faces then y-faces                                    */
+    long long nfx, nfy;
+};
+
+static inline long long cidx(const orc_sim *s, int i, int j)
+{
+    return (long long)(i + NG) + (long long)s->nxg * (long long)(s->D == 2 ? (j + NG) : 0);
+}
+
+static double xc(const orc_sim *s, int i) { return s->cfg.x0 + (i + 0.5) * s->dx[0]; }
+static double yc(const orc_sim *s, int j) { return s->D == 2 ? s->cfg.y0 + (j + 0.5) * s->dx[1] : 0.0; }
+
+/* equilibrium populations of Sec. II.B in the co-moving frame {u, T}:
+ * f_eq = rho W_i, g_eq = (C_v - D/2) T rho W_i */
+static void set_equilibrium(const orc_sim *s, cellrec *c, double rho, const double *u, double T)
+{
+    for (int i = 0; i < s->Q; ++i) {
+        c->f[i] = rho * s->L.W[i];
+        c->g[i] = (s->Cv - 0.5 * s->D) * T * rho * s->L.W[i];
+    }
+    for (int a = 0; a < s->D; ++a) c->u[a] = u[a];
+    c->T = T;
+    c->rho = rho;
+}
+
+static void set_equilibrium_prim(const orc_sim *s, cellrec *c, const double *st /* rho ux uy p */)
+{
+    double u[MAXD] = {st[1], st[2]};
+    set_equilibrium(s, c, st[0], u, st[3] / st[0]);
+}
+
+/* rho, u, T of populations f, g held in frame (u, T): Sec. II.B definitions
+ * rho = sum f, rho u = sum v f, rho E = sum v^2/2 f + sum g, rho E = C_v rho T + rho u^2/2 */
+static void macro(const orc_sim *s, const double *f, const double *g, const double *u, double T,
+                  double *rho, double *uo, double *To)
+{
+    tensors Mf, Mg;
+    moments(&s->L, f, u, T, &Mf);
+    moments(&s->L, g, u, T, &Mg);
+    double r = Mf.t0;
+    double ke = 0.0, tr = 0.0;
+    for (int a = 0; a < s->D; ++a) {
+        uo[a] = Mf.t1[a] / r;
+        ke += uo[a] * uo[a];
+        tr += Mf.t2[a][a];
+    }
+    double rhoE = 0.5 * tr + Mg.t0;
+    *rho = r;
+    *To = (rhoE / r - 0.5 * ke) / s->Cv;
+}
+
+/* express a cell's populations in its own co-moving frame (Sec. III.B.4, first loop):
+ * third-order Grad projection for f, second order for g (Sec. II.C) */
+static void reframe_cell(const orc_sim *s, const cellrec *in, cellrec *out)
+{
+    tensors Mf, Mg;
+    double rho, u[MAXD] = {0, 0}, T;
+    macro(s, in->f, in->g, in->u, in->T, &rho, u, &T);
+    moments(&s->L, in->f, in->u, in->T, &Mf);
+    moments(&s->L, in->g, in->u, in->T, &Mg);
+    grad_project(&s->L, 3, &Mf, u, T, out->f);
+    grad_project(&s->L, 2, &Mg, u, T, out->g);
+    for (int a = 0; a < s->D; ++a) out->u[a] = u[a];
+    out->T = T;
+    out->rho = rho;
+}
+
+orc_sim *orc_create(const orc_config *cfg, const double *rho, const double *ux, const double *uy,
+                    const double *p)
+{
+    if (!cfg || (cfg->dim != 1 && cfg->dim != 2) || cfg->nx < 2) return NULL;
+    if (cfg->dim == 2 && cfg->ny < 2) return NULL;
+    if (!(cfg->gamma > 1.0)) return NULL;
+    orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
+    s->cfg = *cfg;
+    s->D = cfg->dim;
+    make_lattice(s->D, &s->L);
+    s->Q = s->L.Q;
+    s->nx = cfg->nx;
+    s->ny = (s->D == 2) ? cfg->ny : 1;
+    s->nxg = s->nx + 2 * NG;
+    s->nyg = (s->D == 2) ? s->ny + 2 * NG : 1;
+    s->dx[0] = (cfg->x1 - cfg->x0) / s->nx;
+    s->dx[1] = (s->D == 2) ? (cfg->y1 - cfg->y0) / s->ny : 1.0;
+    s->Cv = 1.0 / (cfg->gamma - 1.0);
+    long long ncg = (long long)s->nxg * s->nyg;
+    s->cell = (cellrec *)calloc((size_t)ncg, sizeof(cellrec));
+    s->plus = (cellrec *)calloc((size_t)ncg, sizeof(cellrec));
+    s->nfx = (long long)(s->nx + 1) * s->ny;
+    s->nfy = (s->D == 2) ? (long long)s->nx * (s->ny + 1) : 0;
+    s->face = (facerec *)calloc((size_t)(s->nfx + s->nfy), sizeof(facerec));
+    /* initial state: local equilibrium in the co-moving frame, so f~ = f = f_eq */
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            long long k = (long long)i + (long long)s->nx * j;
+            double st[4] = {rho[k], ux[k], (s->D == 2 && uy) ? uy[k] : 0.0, p[k]};
+            if (!(st[0] > 0.0) || !(st[3] > 0.0)) {
+                orc_destroy(s);
+                return NULL;
+            }
+            set_equilibrium_prim(s, &s->cell[cidx(s, i, j)], st);
+        }
+    return s;
+}
+
+void orc_destroy(orc_sim *s)
+{
+    if (!s) return;
+    free(s->cell);
+    free(s->plus);
+    free(s->face);
+    free(s);
+}
+
+double orc_time(const orc_sim *s) { return s->t; }
+long long orc_steps(const orc_sim *s) { return s->nstep; }
+long long orc_nfaces(const orc_sim *s) { return s->nfx + s->nfy; }
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
+
+/* ------------------------------------------------------------------------- */
+/* boundary ghosts (applied to the phi-bar-plus records)                     */
+/* ------------------------------------------------------------------------- */
+
+/* mirror a record across an axis: population of node c_i goes to the node with the
+ * opposite component along that axis, and the frame velocity component flips */
+static void mirror(const orc_sim *s, const cellrec *in, cellrec *out, int axis)
+{
+    *out = *in;
+    for (int i = 0; i < s->Q; ++i) {
+        int ix = i % 4, iy = i / 4;
+        int im = (axis == 0) ? (3 - ix) + 4 * iy : ix + 4 * (3 - iy);
+        if (s->D == 1) im = 3 - ix;
+        out->f[im] = in->f[i];
+        out->g[im] = in->g[i];
+    }
+    out->u[axis] = -in->u[axis];
+}
+
+/* ghost rule of one side. side: 0 W, 1 E, 2 S, 3 N. (gi, gj) ghost index;
+ * interior neighbour along the normal is taken from `plus` (already filled). */
+static void fill_ghost(orc_sim *s, int side, int gi, int gj)
+{
+    const int axis = side / 2;
+    const int n = (axis == 0) ? s->nx : s->ny;
+    int g = (axis == 0) ? gi : gj;        /* ghost coordinate along the normal */
+    int layer = (g < 0) ? (-1 - g) : (g - n); /* 0 for the first ghost layer    */
+    int kind = s->cfg.bc[side];
+    double tpos = (axis == 0) ? yc(s, gj) : xc(s, gi); /* tangential centre */
+    cellrec *dst = &s->plus[cidx(s, gi, gj)];
+    if (kind == ORC_BC_SPLIT_FIXED_REFLECT)
+        kind = (tpos < s->cfg.bc_param[side][0]) ? ORC_BC_FIXED : ORC_BC_REFLECT;
+    if (kind == ORC_BC_PERIODIC) {
+        int src = (g < 0) ? g + n : g - n;
+        *dst = (axis == 0) ? s->plus[cidx(s, src, gj)] : s->plus[cidx(s, gi, src)];
+    } else if (kind == ORC_BC_OUTFLOW) {
+        int src = (g < 0) ? 0 : n - 1;
+        *dst = (axis == 0) ? s->plus[cidx(s, src, gj)] : s->plus[cidx(s, gi, src)];
+    } else if (kind == ORC_BC_REFLECT) {
+        int src = (g < 0) ? layer : n - 1 - layer;
+        const cellrec *in = (axis == 0) ? &s->plus[cidx(s, src, gj)] : &s->plus[cidx(s, gi, src)];
+        mirror(s, in, dst, axis);
+    } else if (kind == ORC_BC_FIXED) {
+        set_equilibrium_prim(s, dst, s->cfg.bc_state[side]);
+    } else if (kind == ORC_BC_FIXED_WINDOW) {
+        const double *p = s->cfg.bc_param[side];
+        set_equilibrium_prim(s, dst, (tpos >= p[0] && tpos <= p[1]) ? s->cfg.bc_alt[side]
+                                                                   : s->cfg.bc_state[side]);
+    } else if (kind == ORC_BC_MOVING_SHOCK) {
+        const double *p = s->cfg.bc_param[side];
+        double xs = p[0] + p[1] * (yc(s, gj) + p[2] * s->t);
+        set_equilibrium_prim(s, dst, (xc(s, gi) < xs) ? s->cfg.bc_state[side] : s->cfg.bc_alt[side]);
+    }
+}
+
+static void fill_ghosts(orc_sim *s)
+{
+    for (int j = 0; j < s->ny; ++j)
+        for (int l = 0; l < NG; ++l) {
+            fill_ghost(s, 0, -1 - l, j);
+            fill_ghost(s, 1, s->nx + l, j);
+        }
+    if (s->D == 2)
+        for (int i = -NG; i < s->nx + NG; ++i)
+            for (int l = 0; l < NG; ++l) {
+                fill_ghost(s, 2, i, -1 - l);
+                fill_ghost(s, 3, i, s->ny + l);
+            }
+}
+
+/* ------------------------------------------------------------------------- */
+/* the face predictor-corrector (Sec. III.B.3)                               */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double dt;
+    long long iters_total, nonconv, depout;
+    int iters_max;
+} stepacc;
+
+/* one face along `axis` between cells L=(iL,jL) and R = L + e_axis */
+static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, double dt,
+                           long long *depout, long long *nonphys)
+{
+    const int D = s->D, Q = s->Q;
+    const int t_axis = 1 - axis;
+    const double h = 0.5 * dt;
+    int ei[MAXD] = {0, 0};
+    ei[axis] = 1;
+    /* stencil: 0 = L - e_a, 1 = L, 2 = R, 3 = R + e_a; (2D) 4 = L - e_t, 5 = L + e_t,
+     * 6 = R - e_t, 7 = R + e_t */
+    int ns = (D == 2) ? 8 : 4;
+    int si[8], sj[8];
+    int iR = iL + ei[0], jR = jL + ei[1];
+    si[0] = iL - ei[0]; sj[0] = jL - ei[1];
+    si[1] = iL;         sj[1] = jL;
+    si[2] = iR;         sj[2] = jR;
+    si[3] = iR + ei[0]; sj[3] = jR + ei[1];
+    if (D == 2) {
+        int et[2] = {ei[1], ei[0]};
+        si[4] = iL - et[0]; sj[4] = jL - et[1];
+        si[5] = iL + et[0]; sj[5] = jL + et[1];
+        si[6] = iR - et[0]; sj[6] = jR - et[1];
+        si[7] = iR + et[0]; sj[7] = jR + et[1];
+    }
+    /* lab moments of every stencil cell's phi-bar-plus: they do not depend on the
+     * target frame, so the regularized transformation into any lambda is a Grad
+     * projection of these (Sec. II.C) */
+    tensors Mf[8], Mg[8];
+    for (int k = 0; k < ns; ++k) {
+        const cellrec *c = &s->plus[cidx(s, si[k], sj[k])];
+        moments(&s->L, c->f, c->u, c->T, &Mf[k]);
+        moments(&s->L, c->g, c->u, c->T, &Mg[k]);
+    }
+    const cellrec *cL = &s->plus[cidx(s, iL, jL)];
+    const cellrec *cR = &s->plus[cidx(s, iR, jR)];
+
+    /* frame of the mean conserved variables of L and R: the seed of the first step and
+     * the restart frame of an iteration that has left the physical states */
+    double mu_[MAXD] = {0, 0}, mT;
+    {
+        double r = 0.5 * (cL->rho + cR->rho), m[MAXD] = {0, 0}, e = 0.0, ke = 0.0;
+        const cellrec *cc[2] = {cL, cR};
+        for (int q = 0; q < 2; ++q) {
+            double u2 = 0.0;
+            for (int a = 0; a < D; ++a) {
+                m[a] += 0.5 * cc[q]->rho * cc[q]->u[a];
+                u2 += cc[q]->u[a] * cc[q]->u[a];
+            }
+            e += 0.5 * (s->Cv * cc[q]->rho * cc[q]->T + 0.5 * cc[q]->rho * u2);
+        }
+        for (int a = 0; a < D; ++a) {
+            mu_[a] = m[a] / r;
+            ke += mu_[a] * mu_[a];
+        }
+        mT = (e / r - 0.5 * ke) / s->Cv;
+    }
+    /* predictor frame lambda_0: the face frame of the previous half step */
+    double lu[MAXD] = {0, 0}, lT;
+    if (F->seeded) {
+        for (int a = 0; a < D; ++a) lu[a] = F->su[a];
+        lT = F->sT;
+    } else {
+        for (int a = 0; a < D; ++a) lu[a] = mu_[a];
+        lT = mT;
+    }
+    int restarted = !F->seeded;
+
+    double Pf[8][MAXQ], Pg[8][MAXQ], fb[MAXQ], gb[MAXQ], v[MAXQ][MAXD];
+    tensors Mfb, Mgb;
+    int it, conv = 0, failed = 0;
+    double nu[MAXD] = {0, 0}, nT = lT;
+    for (it = 1; it <= s->cfg.max_iter; ++it) {
+        /* transform every stencil cell into the current frame lambda_k */
+        for (int k = 0; k < ns; ++k) {
+            grad_project(&s->L, 3, &Mf[k], lu, lT, Pf[k]);
+            grad_project(&s->L, 2, &Mg[k], lu, lT, Pg[k]);
+        }
+        velocities(&s->L, lu, lT, v);
+        for (int i = 0; i < Q; ++i) {
+            /* upwind cell and departure point x' = x_b - v_i dt/2 (MUSCL, Sec. III.B.3) */
+            int up = (v[i][axis] >= 0.0);
+            int cU = up ? 1 : 2;
+            int cB = up ? 0 : 1; /* backward neighbour along the axis */
+            int cF = up ? 2 : 3; /* forward neighbour along the axis  */
+            double off_a = (up ? 0.5 * s->dx[axis] : -0.5 * s->dx[axis]) - v[i][axis] * h;
+            if (fabs(v[i][axis]) * h > 0.5 * s->dx[axis]) ++*depout;
+            double sf = orc_limiter(s->cfg.limiter, (Pf[cU][i] - Pf[cB][i]) / s->dx[axis],
+                                    (Pf[cF][i] - Pf[cU][i]) / s->dx[axis]);
+            double sg = orc_limiter(s->cfg.limiter, (Pg[cU][i] - Pg[cB][i]) / s->dx[axis],
+                                    (Pg[cF][i] - Pg[cU][i]) / s->dx[axis]);
+            fb[i] = Pf[cU][i] + off_a * sf;
+            gb[i] = Pg[cU][i] + off_a * sg;
+            if (D == 2) {
+                int tm = up ? 4 : 6, tp = up ? 5 : 7;
+                double off_t = -v[i][t_axis] * h;
+                if (fabs(v[i][t_axis]) * h > 0.5 * s->dx[t_axis]) ++*depout;
+                double tf = orc_limiter(s->cfg.limiter, (Pf[cU][i] - Pf[tm][i]) / s->dx[t_axis],
+                                        (Pf[tp][i] - Pf[cU][i]) / s->dx[t_axis]);
+                double tg = orc_limiter(s->cfg.limiter, (Pg[cU][i] - Pg[tm][i]) / s->dx[t_axis],
+                                        (Pg[tp][i] - Pg[cU][i]) / s->dx[t_axis]);
+                fb[i] += off_t * tf;
+                gb[i] += off_t * tg;
+            }
+        }
+        /* density, momentum and energy at the face -> corrector frame lambda_{k+1} */
+        moments(&s->L, fb, lu, lT, &Mfb);
+        moments(&s->L, gb, lu, lT, &Mgb);
+        double rho = Mfb.t0, ke = 0.0, tr = 0.0;
+        for (int a = 0; a < D; ++a) {
+            nu[a] = Mfb.t1[a] / rho;
+            ke += nu[a] * nu[a];
+            tr += Mfb.t2[a][a];
+        }
+        nT = ((0.5 * tr + Mgb.t0) / rho - 0.5 * ke) / s->Cv;
+        if (!(rho > 0.0) || !(nT > 0.0) || !isfinite(nT) || !isfinite(ke)) {
+            /* the corrector left the physical states: restart once from the frame of
+             * the mean conserved variables of the two neighbours */
+            if (!restarted) {
+                restarted = 1;
+                for (int a = 0; a < D; ++a) lu[a] = mu_[a];
+                lT = mT;
+                continue;
+            }
+            failed = 1;
+            break;
+        }
+        double du = 0.0;
+        for (int a = 0; a < D; ++a) du = fmax(du, fabs(nu[a] - lu[a]));
+        double delta = fmax(du / sqrt(nT), fabs(nT - lT) / nT);
+        for (int a = 0; a < D; ++a) lu[a] = nu[a];
+        lT = nT;
+        if (delta <= s->cfg.tol) {
+            conv = 1;
+            break;
+        }
+    }
+    if (it > s->cfg.max_iter) it = s->cfg.max_iter;
+    F->iters = conv ? it : -it;
+
+    double rho_b = Mfb.t0;
+    int has_frame = 1;
+    if (failed) {
+        /* Reading (the paper is silent on a corrector that leaves the physical states
+         * twice): the face takes the first-order upwind state in which every population
+         * comes from the neighbour it leaves, in that neighbour's own frame (no common
+         * frame, no slope). Its moments give the face frame when they are physical. */
+        ++*nonphys;
+        double vL[MAXQ][MAXD], vR[MAXQ][MAXD], hf[MAXQ], hg[MAXQ];
+        tensors A, B;
+        velocities(&s->L, cL->u, cL->T, vL);
+        velocities(&s->L, cR->u, cR->T, vR);
+        for (int i = 0; i < Q; ++i) {
+            hf[i] = (vL[i][axis] >= 0.0) ? cL->f[i] : 0.0;
+            hg[i] = (vL[i][axis] >= 0.0) ? cL->g[i] : 0.0;
+        }
+        moments(&s->L, hf, cL->u, cL->T, &Mfb);
+        moments(&s->L, hg, cL->u, cL->T, &Mgb);
+        for (int i = 0; i < Q; ++i) {
+            hf[i] = (vR[i][axis] < 0.0) ? cR->f[i] : 0.0;
+            hg[i] = (vR[i][axis] < 0.0) ? cR->g[i] : 0.0;
+        }
+        moments(&s->L, hf, cR->u, cR->T, &A);
+        moments(&s->L, hg, cR->u, cR->T, &B);
+        Mfb.t0 += A.t0;
+        Mgb.t0 += B.t0;
+        for (int a = 0; a < D; ++a) {
+            Mfb.t1[a] += A.t1[a];
+            Mgb.t1[a] += B.t1[a];
+            for (int b = 0; b < D; ++b) {
+                Mfb.t2[a][b] += A.t2[a][b];
+                Mgb.t2[a][b] += B.t2[a][b];
+                for (int c = 0; c < D; ++c) Mfb.t3[a][b][c] += A.t3[a][b][c];
+            }
+        }
+        rho_b = Mfb.t0;
+        double ke = 0.0, tr = 0.0;
+        for (int a = 0; a < D; ++a) {
+            nu[a] = Mfb.t1[a] / rho_b;
+            ke += nu[a] * nu[a];
+            tr += Mfb.t2[a][a];
+        }
+        nT = ((0.5 * tr + Mgb.t0) / rho_b - 0.5 * ke) / s->Cv;
+        if (rho_b > 0.0 && nT > 0.0 && isfinite(nT) && isfinite(ke)) {
+            for (int a = 0; a < D; ++a) lu[a] = nu[a];
+            lT = nT;
+        } else {
+            /* no physical face frame: keep the mean frame as the next seed and leave the
+             * face populations unrelaxed */
+            has_frame = 0;
+            for (int a = 0; a < D; ++a) lu[a] = mu_[a];
+            lT = mT;
+        }
+    }
+
+    /* recover phi at the face from phi-bar with the exact co-moving equilibrium of the
+     * final face frame (Sec. III.B.3), done on the moments (the map is linear) */
+    double eps_b = has_frame ? dt * rho_b * lT / s->cfg.mu : 0.0;
+    cellrec eq;
+    tensors Mfe, Mge;
+    set_equilibrium(s, &eq, rho_b, lu, lT);
+    moments(&s->L, eq.f, lu, lT, &Mfe);
+    moments(&s->L, eq.g, lu, lT, &Mge);
+    tensors Mfo, Mgo;
+    memset(&Mfo, 0, sizeof(Mfo));
+    memset(&Mgo, 0, sizeof(Mgo));
+    Mfo.t0 = orc_face_recover(Mfb.t0, Mfe.t0, eps_b);
+    Mgo.t0 = orc_face_recover(Mgb.t0, Mge.t0, eps_b);
+    for (int a = 0; a < D; ++a) {
+        Mfo.t1[a] = orc_face_recover(Mfb.t1[a], Mfe.t1[a], eps_b);
+        Mgo.t1[a] = orc_face_recover(Mgb.t1[a], Mge.t1[a], eps_b);
+        for (int b = 0; b < D; ++b) {
+            Mfo.t2[a][b] = orc_face_recover(Mfb.t2[a][b], Mfe.t2[a][b], eps_b);
+            Mgo.t2[a][b] = orc_face_recover(Mgb.t2[a][b], Mge.t2[a][b], eps_b);
+            for (int c = 0; c < D; ++c)
+                Mfo.t3[a][b][c] = orc_face_recover(Mfb.t3[a][b][c], Mfe.t3[a][b][c], eps_b);
+        }
+    }
+    pack(D, 3, &Mfo, F->Mf);
+    pack(D, 2, &Mgo, F->Mg);
+    for (int a = 0; a < D; ++a) F->u[a] = lu[a];
+    F->T = lT;
+}
+
+/* ------------------------------------------------------------------------- */
+/* one time step (Sec. III.B.4)                                              */
+/* ------------------------------------------------------------------------- */
+
+int orc_step(orc_sim *s, double t_end, orc_stats *st)
+{
+    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny;
+    const double cmax = s->L.c[Q - 1][0]; /* largest node, sqrt(3 + sqrt 6) */
+    if (s->t >= t_end) return 1;
+
+    /* 1. every cell's populations in its own co-moving frame */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            cellrec tmp;
+            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
+            s->cell[cidx(s, i, j)] = tmp;
+        }
+
+    /* time step from CFL = max |v_ia| dt / dx_a (Sec. IV), clipped at t_end */
+    double rate = 0.0;
+#pragma omp parallel for collapse(2) reduction(max : rate) schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const cellrec *c = &s->cell[cidx(s, i, j)];
+            for (int a = 0; a < D; ++a) {
+                double r = (fabs(c->u[a]) + sqrt(c->T / TL) * cmax) / s->dx[a];
+                rate = fmax(rate, r);
+            }
+        }
+    double dt = s->cfg.cfl / rate;
+    if (s->t + dt > t_end) dt = t_end - s->t;
+
+    /* 2. phi-bar-plus of every cell (Sec. III.B.3), eps = dt/tau = dt p / mu */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            const cellrec *c = &s->cell[cidx(s, i, j)];
+            cellrec *o = &s->plus[cidx(s, i, j)];
+            double eps = dt * c->rho * c->T / s->cfg.mu;
+            double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
+            for (int q = 0; q < Q; ++q) {
+                o->f[q] = orc_phibar_plus(c->f[q], c->rho * s->L.W[q], eps);
+                o->g[q] = orc_phibar_plus(c->g[q], geq_coef * s->L.W[q], eps);
+            }
+            for (int a = 0; a < D; ++a) o->u[a] = c->u[a];
+            o->T = c->T;
+            o->rho = c->rho;
+        }
+    fill_ghosts(s);
+
+    /* 3. faces: predictor-corrector frame iteration and face moments */
+    long long depout = 0, nonphys = 0;
+#pragma omp parallel for collapse(2) reduction(+ : depout, nonphys) schedule(dynamic, 16)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i <= nx; ++i) {
+            facerec *F = &s->face[(long long)i + (long long)(nx + 1) * j];
+            face_iteration(s, F, 0, i - 1, j, dt, &depout, &nonphys);
+        }
+    if (D == 2) {
+#pragma omp parallel for collapse(2) reduction(+ : depout, nonphys) schedule(dynamic, 16)
+        for (int j = 0; j <= ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                facerec *F = &s->face[s->nfx + (long long)i + (long long)nx * j];
+                face_iteration(s, F, 1, i, j - 1, dt, &depout, &nonphys);
+            }
+    }
+
+    /* 4. flux into each cell's frame and the co-moving update (Sec. III.B.2) */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            cellrec *c = &s->cell[cidx(s, i, j)];
+            double v[MAXQ][MAXD];
+            velocities(&s->L, c->u, c->T, v);
+            double Ff[MAXQ], Fg[MAXQ];
+            for (int q = 0; q < Q; ++q) Ff[q] = Fg[q] = 0.0;
+            for (int a = 0; a < D; ++a)
+                for (int side = 0; side < 2; ++side) {
+                    /* side 0: face at x_j - dx/2 with outward normal -e_a; side 1: +e_a */
+                    const facerec *F;
+                    if (a == 0)
+                        F = &s->face[(long long)(i + side) + (long long)(nx + 1) * j];
+                    else
+                        F = &s->face[s->nfx + (long long)i + (long long)nx * (j + side)];
+                    tensors Mf, Mg;
+                    unpack(D, 3, F->Mf, &Mf);
+                    unpack(D, 2, F->Mg, &Mg);
+                    double pf[MAXQ], pg[MAXQ];
+                    grad_project(&s->L, 3, &Mf, c->u, c->T, pf);
+                    grad_project(&s->L, 2, &Mg, c->u, c->T, pg);
+                    double nsign = side ? 1.0 : -1.0;
+                    for (int q = 0; q < Q; ++q) {
+                        /* (dt/V_j) A_c (v_i . n_c) phi_i = (dt/dx_a) (+-v_ia) phi_i */
+                        Ff[q] += dt / s->dx[a] * nsign * v[q][a] * pf[q];
+                        Fg[q] += dt / s->dx[a] * nsign * v[q][a] * pg[q];
+                    }
+                }
+            double eps = dt * c->rho * c->T / s->cfg.mu;
+            double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
+            for (int q = 0; q < Q; ++q) {
+                c->f[q] = orc_update_relax(c->f[q], c->rho * s->L.W[q], eps) - Ff[q];
+                c->g[q] = orc_update_relax(c->g[q], geq_coef * s->L.W[q], eps) - Fg[q];
+            }
+            /* the updated populations stay in the frame lambda_j(t_n) */
+        }
+
+    /* face frames seed the next step's predictor */
+    long long nf = s->nfx + s->nfy, itot = 0, nonc = 0;
+    int imax = 0;
+    for (long long k = 0; k < nf; ++k) {
+        facerec *F = &s->face[k];
+        for (int a = 0; a < D; ++a) F->su[a] = F->u[a];
+        F->sT = F->T;
+        F->seeded = 1;
+        int it = F->iters < 0 ? -F->iters : F->iters;
+        itot += it;
+        if (it > imax) imax = it;
+        if (F->iters < 0) ++nonc;
+    }
+    s->t += dt;
+    s->nstep += 1;
+    if (st) {
+        st->faces = nf;
+        st->iters_total = itot;
+        st->iters_max = imax;
+        st->nonconverged = nonc;
+        st->departure_out = depout;
+        st->nonphysical = nonphys;
+        st->dt = dt;
+    }
+    return nonc ? 2 : 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* read-out                                                                  */
+/* ------------------------------------------------------------------------- */
+
+void orc_fields(const orc_sim *s, double *rho, double *ux, double *uy, double *T)
+{
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            const cellrec *c = &s->cell[cidx(s, i, j)];
+            long long k = (long long)i + (long long)s->nx * j;
+            double r, u[MAXD] = {0, 0}, t;
+            macro(s, c->f, c->g, c->u, c->T, &r, u, &t);
+            rho[k] = r;
+            ux[k] = u[0];
+            if (uy && s->D == 2) uy[k] = u[1];
+            T[k] = t;
+        }
+}
+
+void orc_conserved(const orc_sim *s, double *U)
+{
+    long long n = (long long)s->nx * s->ny;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            const cellrec *c = &s->cell[cidx(s, i, j)];
+            long long k = (long long)i + (long long)s->nx * j;
+            tensors Mf, Mg;
+            moments(&s->L, c->f, c->u, c->T, &Mf);
+            moments(&s->L, c->g, c->u, c->T, &Mg);
+            double tr = 0.0;
+            U[k] = Mf.t0;
+            for (int a = 0; a < s->D; ++a) {
+                U[(1 + a) * n + k] = Mf.t1[a];
+                tr += Mf.t2[a][a];
+            }
+            U[(1 + s->D) * n + k] = 0.5 * tr + Mg.t0;
+        }
+}
+
+static void copy_out(const orc_sim *s, const cellrec *c, long long k, long long n, double *f,
+                     double *g, double *frame)
+{
+    for (int q = 0; q < s->Q; ++q) {
+        if (f) f[q * n + k] = c->f[q];
+        if (g) g[q * n + k] = c->g[q];
+    }
+    if (frame) {
+        for (int a = 0; a < s->D; ++a) frame[a * n + k] = c->u[a];
+        frame[s->D * n + k] = c->T;
+    }
+}
+
+void orc_populations(const orc_sim *s, double *f, double *g, double *frame)
+{
+    long long n = (long long)s->nx * s->ny;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i)
+            copy_out(s, &s->cell[cidx(s, i, j)], (long long)i + (long long)s->nx * j, n, f, g, frame);
+}
+
+void orc_reframed(const orc_sim *s, double *f, double *g, double *frame)
+{
+    long long n = (long long)s->nx * s->ny;
+    for (int j = 0; j < s->ny; ++j)
+        for (int i = 0; i < s->nx; ++i) {
+            cellrec tmp;
+            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
+            copy_out(s, &tmp, (long long)i + (long long)s->nx * j, n, f, g, frame);
+        }
+}
+
+void orc_face_frames(const orc_sim *s, double *out)
+{
+    long long nf = s->nfx + s->nfy;
+    for (long long k = 0; k < nf; ++k) {
+        for (int a = 0; a < s->D; ++a) out[k * (s->D + 1) + a] = s->face[k].su[a];
+        out[k * (s->D + 1) + s->D] = s->face[k].sT;
+    }
+}
+
+void orc_set_face_frames(orc_sim *s, const double *in)
+{
+    long long nf = s->nfx + s->nfy;
+    for (long long k = 0; k < nf; ++k) {
+        for (int a = 0; a < s->D; ++a) s->face[k].su[a] = in[k * (s->D + 1) + a];
+        s->face[k].sT = in[k * (s->D + 1) + s->D];
+        s->face[k].seeded = 1;
+    }
+}
+
+void orc_face_moments(const orc_sim *s, double *Mf, double *Mg)
+{
+    const int D = s->D;
+    const int nf3 = 1 + D + D * D + D * D * D, ng2 = 1 + D + D * D;
+    long long nf = s->nfx + s->nfy;
+    for (long long k = 0; k < nf; ++k) {
+        for (int q = 0; q < nf3; ++q) Mf[k * nf3 + q] = s->face[k].Mf[q];
+        for (int q = 0; q < ng2; ++q) Mg[k * ng2 + q] = s->face[k].Mg[q];
+    }
+}
+
+void orc_face_iters(const orc_sim *s, int *out)
+{
+    long long nf = s->nfx + s->nfy;
+    for (long long k = 0; k < nf; ++k) out[k] = s->face[k].iters;
+}
