@@ -1,0 +1,184 @@
+/*
+ * pond.h -- C ABI of libpond, an MI355X (gfx950) implementation of the
+ * finite-volume Particles-on-Demand (PonD) time step of Kallikounis, Dorschner &
+ * Karlin, "Particles on Demand for flows with strong discontinuities".
+ *
+ * One step (paper Sec. III.B.4) is:
+ *   - every cell's populations expressed in its co-moving frame by the regularized
+ *     (Grad) transformation of Sec. II.C: third order for f, second order for g;
+ *   - phi-bar-plus of every cell (Sec. III.B.3);
+ *   - per face, the predictor-corrector iteration of the face frame with limited
+ *     MUSCL reconstruction at the half-step departure points (Sec. III.B.3);
+ *   - the face populations converted into each cell's frame, the flux and the
+ *     co-moving BGK update (Sec. III.B.2, the update of f~ and g~).
+ *
+ * Conventions for every entry point:
+ *   - units with gas constant 1 (p = rho T) and lattice temperature T_L = 1;
+ *     C_v = 1/(gamma - 1); tau = mu / p (Prandtl number 1);
+ *   - cell fields are plain arrays in x-fastest order (index i + nx*j);
+ *   - host pointers are caller-owned and only read or written during the call;
+ *   - device memory is owned by the context; no entry point retains a caller pointer;
+ *   - on an error the context keeps the state of the last completed step;
+ *   - all calls on one context go to its stream in order; a context is not
+ *     thread-safe, distinct contexts are independent.
+ */
+#ifndef POND_H
+#define POND_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define POND_ABI_VERSION 1
+
+typedef enum {
+    POND_OK = 0,
+    POND_EINVAL = 1,   /* invalid argument, configuration or initial state      */
+    POND_ENOMEM = 2,   /* device allocation failed                              */
+    POND_EDEVICE = 3,  /* HIP runtime error or no usable gfx950 device          */
+    POND_ENOCONV = 4,  /* some face did not converge within max_iter (reported   */
+                       /* by pond_step only when POND_FLAG_STRICT is set)       */
+    POND_ECFL = 5,     /* a departure point left its upwind cell                 */
+    POND_ENONPHYS = 6, /* rho <= 0, T <= 0 or a non-finite value in a cell       */
+    POND_ESTATE = 7    /* call not valid in the context's state                  */
+} pond_status;
+
+/* boundary kinds, one per side: west, east, south, north (Sec. IV) */
+enum {
+    POND_BC_PERIODIC = 0,
+    POND_BC_OUTFLOW = 1,             /* zero gradient: ghost = nearest interior cell      */
+    POND_BC_REFLECT = 2,             /* mirrored cell, normal velocity reversed           */
+    POND_BC_FIXED = 3,               /* equilibrium at bc_state                           */
+    POND_BC_FIXED_WINDOW = 4,        /* bc_alt where param[0] <= tangential centre <=     */
+                                     /* param[1], bc_state elsewhere                      */
+    POND_BC_SPLIT_FIXED_REFLECT = 5, /* fixed bc_state where the tangential centre is    */
+                                     /* below param[0], reflecting beyond                 */
+    POND_BC_MOVING_SHOCK = 6         /* bc_state where x_c < p0 + p1 (y_c + p2 t), bc_alt */
+                                     /* beyond (a plane shock crossing the boundary)      */
+};
+
+enum { POND_LIM_VANLEER = 0, POND_LIM_MINMOD = 1 };
+enum { POND_FP64 = 0, POND_MIXED = 1 };    /* MIXED: FP32 populations, FP64 conserved */
+enum { POND_SEED_PREV = 0, POND_SEED_MLP = 1 };
+enum { POND_FLAG_STRICT = 1 };             /* non-converged faces are an error        */
+
+/* Problem statement (paper Sec. IV: initial fields on a uniform grid, gamma, CFL,
+ * viscosity, boundary conditions). Caller-owned, copied by pond_init. */
+typedef struct {
+    int32_t dim;            /* 1 (D1Q4 lattice) or 2 (D2Q16 lattice), Table I          */
+    int32_t nx, ny;         /* cells; in 1D nx is the total over all instances, ny = 1 */
+    int32_t n_inst;         /* 1D only: number of independent tubes (>= 1)              */
+    const int32_t *len;     /* 1D only: cells per tube (n_inst values, each >= 4), or  */
+                            /* NULL for a single tube of nx cells. Read by pond_init.   */
+    double x0, x1, y0, y1;  /* domain; every tube spans [x0, x1]                        */
+    double gamma;           /* adiabatic exponent (> 1)                                 */
+    double cfl;             /* max |v_ia| dt / dx_a, in (0, 1)                          */
+    double mu;              /* dynamic viscosity (> 0)                                  */
+    int32_t limiter;        /* POND_LIM_*                                               */
+    double tol;             /* face-frame convergence tolerance (> 0)                   */
+    int32_t max_iter;       /* iteration cap per face (>= 1)                            */
+    int32_t precision;      /* POND_FP64 or POND_MIXED                                  */
+    int32_t seed_mode;      /* POND_SEED_PREV or POND_SEED_MLP (needs pond_load_mlp)    */
+    int32_t flags;          /* POND_FLAG_*                                              */
+    int32_t bc[4];          /* west, east, south, north: POND_BC_*                      */
+    double bc_state[4][4];  /* per side: rho, ux, uy, p                                 */
+    double bc_alt[4][4];    /* second state of the window and moving-shock kinds       */
+    double bc_param[4][4];  /* geometry of the window, split and moving-shock kinds     */
+} pond_config;
+
+/* Counters of the steps taken by one pond_step call (all instances together). */
+typedef struct {
+    int64_t steps;                  /* steps taken (the maximum over instances)        */
+    int64_t cell_updates;           /* cells advanced, summed over steps               */
+    int64_t converged_cell_updates; /* of which every face met tol within max_iter     */
+    int64_t faces;                  /* face iterations started, summed over steps      */
+    int64_t iters_total;            /* frame iterations, summed over faces and steps   */
+    int32_t iters_max;              /* largest iteration count of one face             */
+    int64_t nonconverged;           /* faces that hit max_iter                         */
+    int64_t fallback;               /* faces that used the first-order fallback state  */
+    int64_t departure_out;          /* populations whose departure point left the cell */
+    double t_min, t_max;            /* time of the instances after the call            */
+    double dt_min, dt_max;          /* time steps of the last step over instances      */
+} pond_stats;
+
+typedef struct pond_ctx pond_ctx;
+
+/* Create a context: validate cfg, allocate device state and set every cell to the
+ * local equilibrium f = rho W_i, g = (C_v - D/2) rho T W_i of its initial state in its
+ * co-moving frame {u, T = p/rho} (Sec. II.B). rho, ux, p: host arrays of nx*ny values;
+ * uy may be NULL in 1D. rho and p must be positive and finite. On error *out = NULL. */
+pond_status pond_init(const pond_config *cfg, const double *rho, const double *ux,
+                      const double *uy, const double *p, pond_ctx **out);
+
+/* Advance every instance by up to nsteps steps, each with dt = cfl / max rate of its
+ * cells (Sec. IV), the last one clipped so that no instance passes t_end (pass
+ * INFINITY for a fixed step count). st (may be NULL) receives the counters of this
+ * call. Returns POND_OK, or the first error found (POND_ENONPHYS after a step that
+ * produced an invalid cell; POND_ECFL; POND_ENOCONV only with POND_FLAG_STRICT).
+ * The call is asynchronous on the context's stream except for the counter read-back. */
+pond_status pond_step(pond_ctx *ctx, int32_t nsteps, double t_end, pond_stats *st);
+
+/* Cell fields rho, ux, uy, T (host arrays of nx*ny; uy may be NULL) computed from the
+ * conserved variables. Synchronizes the stream. */
+pond_status pond_moments(const pond_ctx *ctx, double *rho, double *ux, double *uy, double *T);
+
+/* Same fields written to a caller-owned device buffer of 4*nx*ny doubles (planes rho,
+ * ux, uy, T) on the context's stream; does not synchronize. */
+pond_status pond_moments_device(const pond_ctx *ctx, double *dev_out);
+
+/* Conserved variables (rho, rho u_x[, rho u_y], rho E): (dim+2) planes of nx*ny. */
+pond_status pond_conserved(const pond_ctx *ctx, double *U);
+
+/* Populations f~, g~ (Q planes of nx*ny each, Q = 4^dim) and their frames ((dim+1)
+ * planes: u..., T) as the next step starts from them: in each cell's co-moving frame. */
+pond_status pond_populations(const pond_ctx *ctx, double *f, double *g, double *frame);
+
+/* Number of faces: 1D: nx + n_inst; 2D: (nx+1)*ny x-faces followed by nx*(ny+1) y-faces
+ * (x-face (i,j) lies between cells (i-1,j) and (i,j); y-face (i,j) between (i,j-1), (i,j)). */
+int64_t pond_nfaces(const pond_ctx *ctx);
+
+/* Face frames of the last step ((dim+1) values per face: u..., T) = the seeds of the
+ * next step's predictor. Host array of pond_nfaces*(dim+1). Before the first step
+ * every T is -1 (no seed yet). */
+pond_status pond_face_frames(const pond_ctx *ctx, double *out);
+/* Replace the seeds (same layout). T <= 0 marks a face as unseeded. */
+pond_status pond_set_face_frames(pond_ctx *ctx, const double *in);
+/* Lab-frame moments of the face populations phi(x_b, t+dt/2) of the last step:
+ * f: 1+d+d^2+d^3 values (M0, M1, M2, M3 row-major), g: 1+d+d^2 values, per face. */
+pond_status pond_face_moments(const pond_ctx *ctx, double *Mf, double *Mg);
+/* Iteration count per face of the last step (negative: not converged). */
+pond_status pond_face_iters(const pond_ctx *ctx, int32_t *out);
+
+/* Time of each instance (host array of n_inst). */
+pond_status pond_time(const pond_ctx *ctx, double *t);
+
+/* Make the context issue its work on a caller's HIP stream (hipStream_t passed as
+ * void*; NULL = the context's own stream). The stream must outlive the context or
+ * be replaced before it is destroyed. */
+pond_status pond_set_stream(pond_ctx *ctx, void *hip_stream);
+
+/* Launch shapes. 1D: face_block threads per block. 2D: face tile bx x by (threads).
+ * Any shape gives bitwise-identical results. pond_autotune times the candidates on
+ * the current state (which it leaves unchanged) and keeps the fastest. */
+pond_status pond_set_tiles(pond_ctx *ctx, int32_t bx, int32_t by, int32_t cell_block);
+pond_status pond_get_tiles(const pond_ctx *ctx, int32_t *bx, int32_t *by, int32_t *cell_block);
+pond_status pond_autotune(pond_ctx *ctx);
+
+/* Average device time in ms per launch of each kernel over the last pond_step call,
+ * measured with HIP events on the context's stream: out[0] dt/time kernel,
+ * out[1] face kernel, out[2] cell update kernel, out[3] seed (MLP) kernel.
+ * Timing is recorded only after pond_enable_timing(ctx, 1). */
+pond_status pond_enable_timing(pond_ctx *ctx, int32_t on);
+pond_status pond_kernel_times(const pond_ctx *ctx, double *out4);
+
+void pond_free(pond_ctx *ctx);
+const char *pond_strerror(pond_status s);
+int32_t pond_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,755 @@
+// pond.hip -- host side of libpond: the C ABI of include/pond.h on top of the kernels in
+// pond_kernels.hpp. The library owns its device memory (hipMalloc) and issues all work on
+// one stream per context; nothing here computes the method, it only validates, allocates,
+// launches and copies.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <vector>
+
+#include "../../include/pond.h"
+#include "pond_kernels.hpp"
+#include "pond_mlp.hpp"
+
+using namespace pond;
+
+struct pond_ctx {
+    pond_config cfg;
+    Params P;
+    int D;
+    int precision;
+    int nh, nfp; // planes of H and F
+    size_t rsize;
+    hipStream_t stream;
+    hipStream_t own_stream;
+    // device buffers
+    double *U = nullptr;
+    void *H = nullptr, *F = nullptr;
+    int *fiter = nullptr;
+    int *cell_inst = nullptr, *face_inst = nullptr;
+    int64_t *cell_off = nullptr, *pad_off = nullptr;
+    double *t = nullptr, *tstart = nullptr, *dt = nullptr, *dxk = nullptr;
+    unsigned long long *vmax = nullptr, *stats = nullptr;
+    int *err = nullptr;
+    double *scratch = nullptr; // read-out staging (4 x ncell doubles)
+    // host mirrors
+    std::vector<int64_t> h_cell_off;
+    int tube_span = 0;
+    int slot = 0;
+    int64_t steps_done = 0;
+    // launch shapes
+    int bx = 256, by = 1, cell_block = 256;
+    // timing
+    int timing = 0;
+    double ktime[4] = {0, 0, 0, 0};
+    hipEvent_t ev[8];
+    // learned seed
+    MlpDevice mlp;
+};
+
+namespace {
+
+const char *kErr[] = {"ok", "invalid argument", "device allocation failed", "HIP runtime error",
+                      "face iteration did not converge", "departure point outside upwind cell",
+                      "non-physical cell state", "invalid call for the context state"};
+
+bool hip_ok(hipError_t e)
+{
+    if (e != hipSuccess) {
+        fprintf(stderr, "libpond: HIP error %s\n", hipGetErrorString(e));
+        return false;
+    }
+    return true;
+}
+
+#define HIPCHK(x)                                                                                  \
+    do {                                                                                           \
+        if (!hip_ok(x)) return POND_EDEVICE;                                                       \
+    } while (0)
+
+template <typename R>
+State<R> state_of(pond_ctx *c)
+{
+    State<R> S;
+    S.U = c->U;
+    S.H = reinterpret_cast<R *>(c->H);
+    S.F = reinterpret_cast<R *>(c->F);
+    S.fiter = c->fiter;
+    S.cell_inst = c->cell_inst;
+    S.face_inst = c->face_inst;
+    S.cell_off = c->cell_off;
+    S.pad_off = c->pad_off;
+    S.t = c->t;
+    S.tstart = c->tstart;
+    S.dt = c->dt;
+    S.dxk = c->dxk;
+    S.vmax = c->vmax;
+    S.stats = c->stats;
+    S.err = c->err;
+    return S;
+}
+
+unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
+{
+    if (c->D == 1) return (size_t)(bx + 3 + 3 * span) * Layout<1>::NL * c->rsize;
+    return (size_t)(bx + 3) * (by + 3) * Layout<2>::NL * c->rsize;
+}
+
+int compute_span(const pond_ctx *c, int B)
+{
+    // largest number of tube boundaries inside one block of B faces
+    if (c->cfg.dim != 1 || c->P.n_inst == 1) return 0;
+    int64_t nf = c->P.nface;
+    int span = 0;
+    const auto &off = c->h_cell_off;
+    int k = 0;
+    for (int64_t f0 = 0; f0 < nf; f0 += B) {
+        int64_t fl = std::min(f0 + B, nf) - 1;
+        while (k + 1 < c->P.n_inst && off[k + 1] + (k + 1) <= f0) ++k;
+        int k1 = k;
+        while (k1 + 1 < c->P.n_inst && off[k1 + 1] + (k1 + 1) <= fl) ++k1;
+        span = std::max(span, k1 - k);
+    }
+    return span;
+}
+
+template <int D, typename R>
+hipError_t launch_face(pond_ctx *c, int bx, int by)
+{
+    State<R> S = state_of<R>(c);
+    if (D == 1) {
+        int span = (bx == c->bx) ? c->tube_span : compute_span(c, bx);
+        size_t lds = face_lds_bytes(c, bx, 1, span);
+        face_kernel_1d<R><<<blocks(c->P.nface, bx), bx, lds, c->stream>>>(c->P, S, span);
+    } else {
+        dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
+        size_t lds = face_lds_bytes(c, bx, by, 0);
+        face_kernel_2d<R><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+    }
+    return hipGetLastError();
+}
+
+template <int D, typename R>
+hipError_t launch_step(pond_ctx *c, double t_end)
+{
+    State<R> S = state_of<R>(c);
+    const bool tm = c->timing != 0;
+    if (tm) hipEventRecord(c->ev[0], c->stream);
+    dt_kernel<D, R><<<blocks(c->P.n_inst, 64), 64, 0, c->stream>>>(c->P, S, t_end, c->slot);
+    if (tm) hipEventRecord(c->ev[1], c->stream);
+    if (c->cfg.seed_mode == POND_SEED_MLP && c->mlp.ready) {
+        hipError_t e = mlp_seed_launch<D, R>(c->mlp, c->P, S, c->stream);
+        if (e != hipSuccess) return e;
+    }
+    if (tm) hipEventRecord(c->ev[2], c->stream);
+    hipError_t e = launch_face<D, R>(c, c->bx, c->by);
+    if (e != hipSuccess) return e;
+    if (tm) hipEventRecord(c->ev[3], c->stream);
+    cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+    if (tm) hipEventRecord(c->ev[4], c->stream);
+    c->slot ^= 1;
+    return hipGetLastError();
+}
+
+hipError_t step_once(pond_ctx *c, double t_end)
+{
+    if (c->D == 1)
+        return c->precision == POND_FP64 ? launch_step<1, double>(c, t_end) : launch_step<1, float>(c, t_end);
+    return c->precision == POND_FP64 ? launch_step<2, double>(c, t_end) : launch_step<2, float>(c, t_end);
+}
+
+hipError_t face_once(pond_ctx *c, int bx, int by)
+{
+    if (c->D == 1)
+        return c->precision == POND_FP64 ? launch_face<1, double>(c, bx, by) : launch_face<1, float>(c, bx, by);
+    return c->precision == POND_FP64 ? launch_face<2, double>(c, bx, by) : launch_face<2, float>(c, bx, by);
+}
+
+pond_status validate(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
+                     const double *p)
+{
+    if (!cfg || !rho || !ux || !p) return POND_EINVAL;
+    if (cfg->dim != 1 && cfg->dim != 2) return POND_EINVAL;
+    if (cfg->dim == 2 && (!uy || cfg->nx < 2 || cfg->ny < 2)) return POND_EINVAL;
+    if (cfg->dim == 1 && (cfg->n_inst < 1 || (cfg->n_inst > 1 && !cfg->len))) return POND_EINVAL;
+    if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0 && cfg->cfl < 1.0) || !(cfg->mu > 0.0)) return POND_EINVAL;
+    if (!(cfg->tol > 0.0) || cfg->max_iter < 1 || cfg->max_iter > 60000) return POND_EINVAL;
+    if (!(cfg->x1 > cfg->x0) || (cfg->dim == 2 && !(cfg->y1 > cfg->y0))) return POND_EINVAL;
+    if (cfg->precision != POND_FP64 && cfg->precision != POND_MIXED) return POND_EINVAL;
+    if (cfg->limiter != POND_LIM_VANLEER && cfg->limiter != POND_LIM_MINMOD) return POND_EINVAL;
+    double Cv = 1.0 / (cfg->gamma - 1.0);
+    if (!(Cv - 0.5 * cfg->dim > 0.0)) return POND_EINVAL;
+    for (int s = 0; s < 4; ++s) {
+        int b = cfg->bc[s];
+        if (b < POND_BC_PERIODIC || b > POND_BC_MOVING_SHOCK) return POND_EINVAL;
+        if (cfg->dim == 1 && s >= 2) continue;
+        if (b == POND_BC_FIXED || b == POND_BC_FIXED_WINDOW || b == POND_BC_SPLIT_FIXED_REFLECT ||
+            b == POND_BC_MOVING_SHOCK) {
+            if (!(cfg->bc_state[s][0] > 0.0) || !(cfg->bc_state[s][3] > 0.0)) return POND_EINVAL;
+        }
+        if ((b == POND_BC_FIXED_WINDOW || b == POND_BC_MOVING_SHOCK) &&
+            (!(cfg->bc_alt[s][0] > 0.0) || !(cfg->bc_alt[s][3] > 0.0)))
+            return POND_EINVAL;
+    }
+    // periodic sides come in pairs
+    if ((cfg->bc[0] == POND_BC_PERIODIC) != (cfg->bc[1] == POND_BC_PERIODIC)) return POND_EINVAL;
+    if (cfg->dim == 2 && (cfg->bc[2] == POND_BC_PERIODIC) != (cfg->bc[3] == POND_BC_PERIODIC))
+        return POND_EINVAL;
+    int64_t n = 0;
+    if (cfg->dim == 1) {
+        if (cfg->n_inst == 1 && !cfg->len) {
+            if (cfg->nx < 4) return POND_EINVAL;
+            n = cfg->nx;
+        } else {
+            for (int k = 0; k < cfg->n_inst; ++k) {
+                if (cfg->len[k] < 4) return POND_EINVAL;
+                n += cfg->len[k];
+            }
+            if (n != cfg->nx) return POND_EINVAL;
+            if (cfg->n_inst > 1 && (cfg->bc[0] == POND_BC_PERIODIC)) return POND_EINVAL;
+        }
+    } else {
+        n = (int64_t)cfg->nx * cfg->ny;
+    }
+    for (int64_t i = 0; i < n; ++i) {
+        if (!(rho[i] > 0.0) || !(p[i] > 0.0) || !std::isfinite(rho[i]) || !std::isfinite(p[i]) ||
+            !std::isfinite(ux[i]) || (cfg->dim == 2 && !std::isfinite(uy[i])))
+            return POND_EINVAL;
+    }
+    return POND_OK;
+}
+
+template <int D, typename R>
+void init_launch(pond_ctx *c, const double *dprim)
+{
+    State<R> S = state_of<R>(c);
+    int64_t nmax = std::max(c->P.ncell, c->P.nface);
+    init_kernel<D, R><<<blocks(nmax, 256), 256, 0, c->stream>>>(c->P, S, dprim, c->nh);
+}
+
+void free_all(pond_ctx *c)
+{
+    void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
+                    c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->scratch};
+    for (void *q : ptrs)
+        if (q) (void)hipFree(q);
+    mlp_free(c->mlp);
+}
+
+} // namespace
+
+extern "C" {
+
+int32_t pond_abi_version(void) { return POND_ABI_VERSION; }
+
+const char *pond_strerror(pond_status s)
+{
+    if ((int)s < 0 || (int)s > 7) return "unknown status";
+    return kErr[(int)s];
+}
+
+pond_status pond_init(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
+                      const double *p, pond_ctx **out)
+{
+    if (!out) return POND_EINVAL;
+    *out = nullptr;
+    pond_status v = validate(cfg, rho, ux, uy, p);
+    if (v != POND_OK) return v;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return POND_EDEVICE;
+    pond_ctx *c = new (std::nothrow) pond_ctx();
+    if (!c) return POND_ENOMEM;
+    c->cfg = *cfg;
+    c->cfg.len = nullptr;
+    c->D = cfg->dim;
+    c->precision = cfg->precision;
+    c->rsize = (cfg->precision == POND_FP64) ? sizeof(double) : sizeof(float);
+    Params &P = c->P;
+    memset(&P, 0, sizeof(P));
+    P.dim = cfg->dim;
+    P.nx = cfg->nx;
+    P.ny = (cfg->dim == 2) ? cfg->ny : 1;
+    P.n_inst = (cfg->dim == 1) ? cfg->n_inst : 1;
+    P.x0 = cfg->x0;
+    P.y0 = cfg->y0;
+    P.Cv = 1.0 / (cfg->gamma - 1.0);
+    P.cfl = cfg->cfl;
+    P.mu = cfg->mu;
+    P.tol = cfg->tol;
+    P.limiter = cfg->limiter;
+    P.max_iter = cfg->max_iter;
+    for (int s = 0; s < 4; ++s) {
+        P.bc[s] = cfg->bc[s];
+        for (int q = 0; q < 4; ++q) {
+            P.bc_state[s][q] = cfg->bc_state[s][q];
+            P.bc_alt[s][q] = cfg->bc_alt[s][q];
+            P.bc_param[s][q] = cfg->bc_param[s][q];
+        }
+    }
+    // per-instance layout (1D tubes concatenated; each tube spans [x0, x1])
+    std::vector<int64_t> coff(P.n_inst + 1, 0), poff(P.n_inst + 1, 0);
+    std::vector<int> len(P.n_inst);
+    for (int k = 0; k < P.n_inst; ++k) len[k] = (cfg->dim == 1 && cfg->len) ? cfg->len[k] : cfg->nx;
+    for (int k = 0; k < P.n_inst; ++k) coff[k + 1] = coff[k] + len[k];
+    for (int k = 0; k <= P.n_inst; ++k) poff[k] = coff[k] + 4 * (int64_t)k;
+    c->h_cell_off = coff;
+    if (cfg->dim == 1) {
+        P.ncell = coff[P.n_inst];
+        P.nface = P.ncell + P.n_inst;
+        P.nfx = P.nface;
+        // every tube spans [x0, x1]: its own cell size is kept per instance
+        P.dx = (cfg->x1 - cfg->x0) / len[0];
+        P.dy = 1.0;
+    } else {
+        P.ncell = (int64_t)P.nx * P.ny;
+        P.nfx = (int64_t)(P.nx + 1) * P.ny;
+        P.nface = P.nfx + (int64_t)P.nx * (P.ny + 1);
+        P.dx = (cfg->x1 - cfg->x0) / P.nx;
+        P.dy = (cfg->y1 - cfg->y0) / P.ny;
+    }
+    c->nh = (c->D == 1) ? Layout<1>::NH : Layout<2>::NH;
+    c->nfp = (c->D == 1) ? Layout<1>::NF : Layout<2>::NF;
+    if (c->D == 2) {
+        c->bx = 16;
+        c->by = 16;
+    }
+    const int64_t n = P.ncell, nf = P.nface;
+    bool ok = true;
+    auto alloc = [&](void **ptr, size_t bytes) {
+        if (ok && hipMalloc(ptr, std::max<size_t>(bytes, 8)) != hipSuccess) ok = false;
+    };
+    alloc((void **)&c->U, sizeof(double) * (c->D + 2) * n);
+    alloc(&c->H, c->rsize * c->nh * n);
+    alloc(&c->F, c->rsize * c->nfp * nf);
+    alloc((void **)&c->fiter, sizeof(int) * nf);
+    alloc((void **)&c->cell_off, sizeof(int64_t) * (P.n_inst + 1));
+    alloc((void **)&c->pad_off, sizeof(int64_t) * (P.n_inst + 1));
+    alloc((void **)&c->t, sizeof(double) * P.n_inst);
+    alloc((void **)&c->tstart, sizeof(double) * P.n_inst);
+    alloc((void **)&c->dt, sizeof(double) * P.n_inst);
+    alloc((void **)&c->vmax, sizeof(unsigned long long) * 2 * P.n_inst);
+    alloc((void **)&c->stats, sizeof(unsigned long long) * ST_N);
+    alloc((void **)&c->err, sizeof(int));
+    alloc((void **)&c->scratch, sizeof(double) * 4 * std::max(n, nf));
+    if (P.n_inst > 1) {
+        alloc((void **)&c->cell_inst, sizeof(int) * n);
+        alloc((void **)&c->face_inst, sizeof(int) * nf);
+        alloc((void **)&c->dxk, sizeof(double) * P.n_inst);
+    }
+    if (!ok) {
+        free_all(c);
+        delete c;
+        return POND_ENOMEM;
+    }
+    if (hipStreamCreate(&c->own_stream) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return POND_EDEVICE;
+    }
+    c->stream = c->own_stream;
+    for (auto &e : c->ev) (void)hipEventCreate(&e);
+    // upload: primitive fields (staged through scratch), instance tables
+    std::vector<double> prim4((size_t)4 * n, 0.0);
+    for (int64_t i = 0; i < n; ++i) {
+        prim4[i] = rho[i];
+        prim4[n + i] = ux[i];
+        prim4[2 * n + i] = (c->D == 2) ? uy[i] : 0.0;
+        prim4[3 * n + i] = p[i];
+    }
+    std::vector<double> zeros(P.n_inst, 0.0);
+    std::vector<unsigned long long> zv(2 * P.n_inst, 0ull), zs(ST_N, 0ull);
+    bool up = hip_ok(hipMemcpy(c->scratch, prim4.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->cell_off, coff.data(), sizeof(int64_t) * coff.size(), hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->pad_off, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->t, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->tstart, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->dt, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->vmax, zv.data(), sizeof(unsigned long long) * zv.size(), hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->stats, zs.data(), sizeof(unsigned long long) * ST_N, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemset(c->err, 0, sizeof(int)));
+    if (up && P.n_inst > 1) {
+        std::vector<int> ci(n), fi(nf);
+        for (int k = 0; k < P.n_inst; ++k) {
+            for (int64_t j = coff[k]; j < coff[k + 1]; ++j) ci[j] = k;
+            for (int64_t f = coff[k] + k; f <= coff[k + 1] + k; ++f) fi[f] = k;
+        }
+        std::vector<double> dxv(P.n_inst);
+        for (int k = 0; k < P.n_inst; ++k) dxv[k] = (cfg->x1 - cfg->x0) / len[k];
+        up = hip_ok(hipMemcpy(c->cell_inst, ci.data(), sizeof(int) * n, hipMemcpyHostToDevice)) &&
+             hip_ok(hipMemcpy(c->face_inst, fi.data(), sizeof(int) * nf, hipMemcpyHostToDevice)) &&
+             hip_ok(hipMemcpy(c->dxk, dxv.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice));
+    }
+    if (!up) {
+        pond_free(c);
+        return POND_EDEVICE;
+    }
+    c->tube_span = compute_span(c, c->bx);
+    if (c->D == 1)
+        c->precision == POND_FP64 ? init_launch<1, double>(c, c->scratch) : init_launch<1, float>(c, c->scratch);
+    else
+        c->precision == POND_FP64 ? init_launch<2, double>(c, c->scratch) : init_launch<2, float>(c, c->scratch);
+    if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(c->stream))) {
+        pond_free(c);
+        return POND_EDEVICE;
+    }
+    *out = c;
+    return POND_OK;
+}
+
+pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
+{
+    if (!c || nsteps < 0) return POND_EINVAL;
+    if (c->cfg.seed_mode == POND_SEED_MLP && !c->mlp.ready) return POND_ESTATE;
+    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
+    double kt[4] = {0, 0, 0, 0};
+    for (int s = 0; s < nsteps; ++s) {
+        HIPCHK(step_once(c, t_end));
+        if (c->timing) {
+            float ms;
+            HIPCHK(hipEventSynchronize(c->ev[4]));
+            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
+            kt[0] += ms;
+            hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
+            kt[1] += ms;
+            hipEventElapsedTime(&ms, c->ev[3], c->ev[4]);
+            kt[2] += ms;
+            hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
+            kt[3] += ms;
+        }
+    }
+    if (c->timing && nsteps > 0)
+        for (int q = 0; q < 4; ++q) c->ktime[q] = kt[q] / nsteps;
+    unsigned long long hs[ST_N];
+    int herr = 0;
+    HIPCHK(hipMemcpyAsync(hs, c->stats, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(&herr, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> ht(c->P.n_inst), hdt(c->P.n_inst);
+    HIPCHK(hipMemcpyAsync(ht.data(), c->t, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hdt.data(), c->dt, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->steps_done += nsteps;
+    if (st) {
+        memset(st, 0, sizeof(*st));
+        st->steps = nsteps;
+        st->cell_updates = (int64_t)hs[ST_CELLS];
+        st->converged_cell_updates = (int64_t)hs[ST_CONV_CELLS];
+        st->faces = (int64_t)hs[ST_FACES];
+        st->iters_total = (int64_t)hs[ST_ITERS];
+        st->iters_max = (int32_t)hs[ST_ITMAX];
+        st->nonconverged = (int64_t)hs[ST_NONCONV];
+        st->fallback = (int64_t)hs[ST_FALLBACK];
+        st->departure_out = (int64_t)hs[ST_DEPOUT];
+        st->t_min = *std::min_element(ht.begin(), ht.end());
+        st->t_max = *std::max_element(ht.begin(), ht.end());
+        st->dt_min = *std::min_element(hdt.begin(), hdt.end());
+        st->dt_max = *std::max_element(hdt.begin(), hdt.end());
+    }
+    if (herr & ERR_NONPHYS) return POND_ENONPHYS;
+    if ((c->cfg.flags & POND_FLAG_STRICT) && hs[ST_NONCONV]) return POND_ENOCONV;
+    if ((c->cfg.flags & POND_FLAG_STRICT) && (herr & ERR_DEPART)) return POND_ECFL;
+    return POND_OK;
+}
+
+pond_status pond_moments_device(const pond_ctx *c, double *dev_out)
+{
+    if (!c || !dev_out) return POND_EINVAL;
+    int64_t n = c->P.ncell;
+    if (c->D == 1)
+        fields_kernel<1><<<blocks(n, 256), 256, 0, c->stream>>>(n, c->U, c->P.Cv, dev_out);
+    else
+        fields_kernel<2><<<blocks(n, 256), 256, 0, c->stream>>>(n, c->U, c->P.Cv, dev_out);
+    HIPCHK(hipGetLastError());
+    return POND_OK;
+}
+
+pond_status pond_moments(const pond_ctx *c, double *rho, double *ux, double *uy, double *T)
+{
+    if (!c || !rho || !ux || !T) return POND_EINVAL;
+    pond_status s = pond_moments_device(c, c->scratch);
+    if (s != POND_OK) return s;
+    int64_t n = c->P.ncell;
+    std::vector<double> h((size_t)4 * n);
+    HIPCHK(hipMemcpyAsync(h.data(), c->scratch, sizeof(double) * 4 * n, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    memcpy(rho, h.data(), sizeof(double) * n);
+    memcpy(ux, h.data() + n, sizeof(double) * n);
+    if (uy) memcpy(uy, h.data() + 2 * n, sizeof(double) * n);
+    memcpy(T, h.data() + 3 * n, sizeof(double) * n);
+    return POND_OK;
+}
+
+pond_status pond_conserved(const pond_ctx *c, double *U)
+{
+    if (!c || !U) return POND_EINVAL;
+    HIPCHK(hipMemcpyAsync(U, c->U, sizeof(double) * (c->D + 2) * c->P.ncell, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
+pond_status pond_populations(const pond_ctx *c, double *f, double *g, double *frame)
+{
+    if (!c || !f || !g || !frame) return POND_EINVAL;
+    const int64_t n = c->P.ncell;
+    const int Q = (c->D == 1) ? 4 : 16;
+    double *df = nullptr, *dg = nullptr, *dfr = nullptr;
+    size_t nb = sizeof(double) * (size_t)n;
+    if (hipMalloc(&df, nb * Q) != hipSuccess || hipMalloc(&dg, nb * Q) != hipSuccess ||
+        hipMalloc(&dfr, nb * (c->D + 1)) != hipSuccess) {
+        if (df) (void)hipFree(df);
+        if (dg) (void)hipFree(dg);
+        return POND_ENOMEM;
+    }
+    pond_ctx *m = const_cast<pond_ctx *>(c);
+    if (c->D == 1) {
+        if (c->precision == POND_FP64)
+            pops_kernel<1, double><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        else
+            pops_kernel<1, float><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
+    } else {
+        if (c->precision == POND_FP64)
+            pops_kernel<2, double><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        else
+            pops_kernel<2, float><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
+    }
+    bool ok = hip_ok(hipGetLastError()) &&
+              hip_ok(hipMemcpyAsync(f, df, nb * Q, hipMemcpyDeviceToHost, c->stream)) &&
+              hip_ok(hipMemcpyAsync(g, dg, nb * Q, hipMemcpyDeviceToHost, c->stream)) &&
+              hip_ok(hipMemcpyAsync(frame, dfr, nb * (c->D + 1), hipMemcpyDeviceToHost, c->stream)) &&
+              hip_ok(hipStreamSynchronize(c->stream));
+    (void)hipFree(df);
+    (void)hipFree(dg);
+    (void)hipFree(dfr);
+    return ok ? POND_OK : POND_EDEVICE;
+}
+
+int64_t pond_nfaces(const pond_ctx *c) { return c ? c->P.nface : 0; }
+
+pond_status pond_face_frames(const pond_ctx *c, double *out)
+{
+    if (!c || !out) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    const int nv = c->D + 1;
+    std::vector<unsigned char> buf(c->rsize * nv * nf);
+    HIPCHK(hipMemcpyAsync(buf.data(), c->F, buf.size(), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int v = 0; v < nv; ++v)
+        for (int64_t f = 0; f < nf; ++f)
+            out[f * nv + v] = (c->precision == POND_FP64)
+                                  ? reinterpret_cast<const double *>(buf.data())[v * nf + f]
+                                  : (double)reinterpret_cast<const float *>(buf.data())[v * nf + f];
+    return POND_OK;
+}
+
+pond_status pond_set_face_frames(pond_ctx *c, const double *in)
+{
+    if (!c || !in) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    const int nv = c->D + 1;
+    std::vector<unsigned char> buf(c->rsize * nv * nf);
+    for (int v = 0; v < nv; ++v)
+        for (int64_t f = 0; f < nf; ++f) {
+            double x = in[f * nv + v];
+            if (v == nv - 1 && !(x > 0.0)) x = -1.0;
+            if (c->precision == POND_FP64)
+                reinterpret_cast<double *>(buf.data())[v * nf + f] = x;
+            else
+                reinterpret_cast<float *>(buf.data())[v * nf + f] = (float)x;
+        }
+    HIPCHK(hipMemcpyAsync(c->F, buf.data(), buf.size(), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
+pond_status pond_face_moments(const pond_ctx *c, double *Mf, double *Mg)
+{
+    if (!c || !Mf || !Mg) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    const int nf3 = (c->D == 1) ? 4 : 15, ng2 = (c->D == 1) ? 3 : 7;
+    double *dm = nullptr, *dg = nullptr;
+    if (hipMalloc(&dm, sizeof(double) * nf3 * nf) != hipSuccess ||
+        hipMalloc(&dg, sizeof(double) * ng2 * nf) != hipSuccess) {
+        if (dm) (void)hipFree(dm);
+        return POND_ENOMEM;
+    }
+    pond_ctx *m = const_cast<pond_ctx *>(c);
+    if (c->D == 1) {
+        if (c->precision == POND_FP64)
+            face_moments_kernel<1, double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), dm, dg);
+        else
+            face_moments_kernel<1, float><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), dm, dg);
+    } else {
+        if (c->precision == POND_FP64)
+            face_moments_kernel<2, double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), dm, dg);
+        else
+            face_moments_kernel<2, float><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), dm, dg);
+    }
+    bool ok = hip_ok(hipGetLastError()) &&
+              hip_ok(hipMemcpyAsync(Mf, dm, sizeof(double) * nf3 * nf, hipMemcpyDeviceToHost, c->stream)) &&
+              hip_ok(hipMemcpyAsync(Mg, dg, sizeof(double) * ng2 * nf, hipMemcpyDeviceToHost, c->stream)) &&
+              hip_ok(hipStreamSynchronize(c->stream));
+    (void)hipFree(dm);
+    (void)hipFree(dg);
+    return ok ? POND_OK : POND_EDEVICE;
+}
+
+pond_status pond_face_iters(const pond_ctx *c, int32_t *out)
+{
+    if (!c || !out) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    std::vector<int> h(nf);
+    HIPCHK(hipMemcpyAsync(h.data(), c->fiter, sizeof(int) * nf, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    for (int64_t f = 0; f < nf; ++f) {
+        int it = h[f] & 0xffff;
+        out[f] = ((h[f] >> 16) & 1) ? -it : it;
+    }
+    return POND_OK;
+}
+
+pond_status pond_time(const pond_ctx *c, double *t)
+{
+    if (!c || !t) return POND_EINVAL;
+    HIPCHK(hipMemcpyAsync(t, c->t, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
+pond_status pond_set_stream(pond_ctx *c, void *s)
+{
+    if (!c) return POND_EINVAL;
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->stream = s ? (hipStream_t)s : c->own_stream;
+    return POND_OK;
+}
+
+pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_block)
+{
+    if (!c) return POND_EINVAL;
+    if (cell_block < 64 || cell_block > 1024 || cell_block % 64) return POND_EINVAL;
+    if (c->D == 1) {
+        if (bx < 64 || bx > 1024 || bx % 64 || by != 1) return POND_EINVAL;
+    } else {
+        if (bx < 1 || by < 1 || bx * by > 1024 || (bx * by) % 64) return POND_EINVAL;
+    }
+    int span = compute_span(c, bx);
+    if (face_lds_bytes(c, bx, by, span) > 160 * 1024) return POND_EINVAL;
+    c->bx = bx;
+    c->by = by;
+    c->cell_block = cell_block;
+    c->tube_span = span;
+    return POND_OK;
+}
+
+pond_status pond_get_tiles(const pond_ctx *c, int32_t *bx, int32_t *by, int32_t *cell_block)
+{
+    if (!c || !bx || !by || !cell_block) return POND_EINVAL;
+    *bx = c->bx;
+    *by = c->by;
+    *cell_block = c->cell_block;
+    return POND_OK;
+}
+
+pond_status pond_autotune(pond_ctx *c)
+{
+    if (!c) return POND_EINVAL;
+    // the face kernel is the dominant cost; time it on the current state. It only writes
+    // face state, which is saved first and restored afterwards (the next step's seeds).
+    const size_t fbytes = c->rsize * c->nfp * c->P.nface;
+    void *save = nullptr;
+    HIPCHK(hipMalloc(&save, fbytes));
+    HIPCHK(hipMemcpyAsync(save, c->F, fbytes, hipMemcpyDeviceToDevice, c->stream));
+    // a dt must exist for the face kernel: run the dt kernel's effect on a copy
+    std::vector<std::pair<int, int>> cand;
+    if (c->D == 1)
+        cand = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
+    else
+        cand = {{16, 16}, {32, 8}, {8, 8}, {64, 4}, {32, 4}, {16, 8}, {64, 2}};
+    double best = 1e30;
+    int bbx = c->bx, bby = c->by;
+    hipEvent_t e0, e1;
+    (void)hipEventCreate(&e0);
+    (void)hipEventCreate(&e1);
+    // make sure dt > 0: use the time step the next step would take
+    double *sdt = nullptr;
+    (void)hipMalloc(&sdt, sizeof(double) * c->P.n_inst * 3);
+    (void)hipMemcpyAsync(sdt, c->dt, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(sdt + c->P.n_inst, c->t, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(sdt + 2 * c->P.n_inst, c->tstart, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    {
+        State<double> S = state_of<double>(c);
+        // the dt kernel only touches t, tstart, dt and the other vmax slot: all restored below
+        std::vector<unsigned long long> vm(2 * c->P.n_inst);
+        (void)hipMemcpyAsync(vm.data(), c->vmax, sizeof(unsigned long long) * vm.size(), hipMemcpyDeviceToHost, c->stream);
+        (void)hipStreamSynchronize(c->stream);
+        dt_kernel<1, double><<<blocks(c->P.n_inst, 64), 64, 0, c->stream>>>(c->P, S, INFINITY, c->slot);
+        for (auto &cd : cand) {
+            if (c->D == 2 && ((cd.first * cd.second) % 64 != 0)) continue;
+            if (face_lds_bytes(c, cd.first, cd.second, compute_span(c, cd.first)) > 160 * 1024) continue;
+            double tsum = 0;
+            for (int rep = 0; rep < 3; ++rep) {
+                (void)hipMemcpyAsync(c->F, save, fbytes, hipMemcpyDeviceToDevice, c->stream);
+                hipEventRecord(e0, c->stream);
+                if (face_once(c, cd.first, cd.second) != hipSuccess) {
+                    tsum = 1e30;
+                    break;
+                }
+                hipEventRecord(e1, c->stream);
+                (void)hipEventSynchronize(e1);
+                float ms = 0;
+                hipEventElapsedTime(&ms, e0, e1);
+                if (rep > 0) tsum += ms;
+            }
+            if (tsum < best) {
+                best = tsum;
+                bbx = cd.first;
+                bby = cd.second;
+            }
+        }
+        (void)hipMemcpyAsync(c->vmax, vm.data(), sizeof(unsigned long long) * vm.size(), hipMemcpyHostToDevice, c->stream);
+    }
+    (void)hipMemcpyAsync(c->dt, sdt, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->t, sdt + c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->tstart, sdt + 2 * c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->F, save, fbytes, hipMemcpyDeviceToDevice, c->stream);
+    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
+    HIPCHK(hipMemsetAsync(c->err, 0, sizeof(int), c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    (void)hipFree(sdt);
+    (void)hipFree(save);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return pond_set_tiles(c, bbx, bby, c->cell_block);
+}
+
+pond_status pond_enable_timing(pond_ctx *c, int32_t on)
+{
+    if (!c) return POND_EINVAL;
+    c->timing = on ? 1 : 0;
+    return POND_OK;
+}
+
+pond_status pond_kernel_times(const pond_ctx *c, double *out4)
+{
+    if (!c || !out4) return POND_EINVAL;
+    for (int q = 0; q < 4; ++q) out4[q] = c->ktime[q];
+    return POND_OK;
+}
+
+void pond_free(pond_ctx *c)
+{
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    for (auto &e : c->ev) (void)hipEventDestroy(e);
+    if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
+    delete c;
+}
+
+} // extern "C"

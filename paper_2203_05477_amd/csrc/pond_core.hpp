@@ -1,0 +1,289 @@
+// pond_core.hpp -- device arithmetic of the PonD step on gfx950.
+//
+// Every cell, face or stencil distribution is held as Hermite coefficients h in its own
+// frame lambda = {u, T} (s = sqrt T): f_i = W_i sum_{p,q} h[p][q] He_p(c_ix) He_q(c_iy),
+// the tensor-product form of the Grad expansion of Sec. II.C (h10 = a_x, h20 = a_xx/2,
+// h11 = a_xy, h30 = a_xxx/6, h21 = a_xxy/2, ...; in 1D h_p = a_p/p!). A change of frame
+// lambda -> lambda' is computed on the dimensionless raw moments mu[k][l] = sum f c_x^k c_y^l:
+// with r = s/s' and d = (u - u')/s', the moments in lambda' are those of (r c + d), a
+// binomial shift. Because Grad's projection is fixed by M_0..M_3 (M_0..M_2 for g), this is
+// the paper's regularized transformation written in frame-relative variables: no quantity
+// of size u^3 is ever formed, so FP32 keeps its relative accuracy at any Mach number.
+//
+// Coefficient order. 2D, degree <= 3: 00 10 01 20 11 02 30 21 12 03 (10 values);
+// degree <= 2: the first 6. 1D: h0 h1 h2 h3.
+// Population order: i = ix + 4 iy, nodes ascending: -cb, -ca, +ca, +cb (Table I, D1Q4).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#define PD __device__ __forceinline__
+
+namespace pond {
+
+// D1Q4 (Table I): nodes +-sqrt(3 -+ sqrt 6), weights (3 +- sqrt 6)/12, and the
+// probabilists' Hermite polynomials He2 = c^2 - 1, He3 = c^3 - 3c at the positive nodes.
+template <typename R>
+struct Lat {
+    static constexpr R ca = R(7.41963784302725803954e-01);
+    static constexpr R cb = R(2.33441421833897733151e+00);
+    static constexpr R wa = R(4.54124145231931508615e-01);
+    static constexpr R wb = R(4.58758547680684913850e-02);
+    static constexpr R he2a = R(-4.49489742783178103380e-01);
+    static constexpr R he2b = R(4.44948974278317788134e+00);
+    static constexpr R he3a = R(-1.81743267916611750401e+00);
+    static constexpr R he3b = R(5.71812368322853536995e+00);
+};
+
+template <typename R>
+PD R node(int k)
+{
+    // k = 0..3 -> -cb, -ca, +ca, +cb
+    R c = (k == 1 || k == 2) ? Lat<R>::ca : Lat<R>::cb;
+    return (k < 2) ? -c : c;
+}
+
+template <typename R>
+PD R weight1(int k)
+{
+    return (k == 1 || k == 2) ? Lat<R>::wa : Lat<R>::wb;
+}
+
+constexpr double CMAX = 2.33441421833897733151e+00; // largest |node|
+
+// ---------------------------------------------------------------------------------
+// Hermite coefficients <-> raw dimensionless moments (Gauss-Hermite is exact here)
+// ---------------------------------------------------------------------------------
+
+template <typename R>
+PD void h2mu_1d(const R h[4], R mu[4])
+{
+    mu[0] = h[0];
+    mu[1] = h[1];
+    mu[2] = h[0] + R(2) * h[2];
+    mu[3] = R(3) * h[1] + R(6) * h[3];
+}
+
+template <typename R>
+PD void mu2h_1d(const R mu[4], R h[4])
+{
+    h[0] = mu[0];
+    h[1] = mu[1];
+    h[2] = R(0.5) * (mu[2] - mu[0]);
+    h[3] = (mu[3] - R(3) * mu[1]) * R(1.0 / 6.0);
+}
+
+// 2D, order 3 (10) -- the first 6 entries are the order-2 set
+template <typename R>
+PD void h2mu_2d(const R h[10], R mu[10], int n)
+{
+    mu[0] = h[0];
+    mu[1] = h[1];
+    mu[2] = h[2];
+    mu[3] = h[0] + R(2) * h[3];
+    mu[4] = h[4];
+    mu[5] = h[0] + R(2) * h[5];
+    if (n > 6) {
+        mu[6] = R(3) * h[1] + R(6) * h[6];
+        mu[7] = h[2] + R(2) * h[7];
+        mu[8] = h[1] + R(2) * h[8];
+        mu[9] = R(3) * h[2] + R(6) * h[9];
+    }
+}
+
+template <typename R>
+PD void mu2h_2d(const R mu[10], R h[10], int n)
+{
+    h[0] = mu[0];
+    h[1] = mu[1];
+    h[2] = mu[2];
+    h[3] = R(0.5) * (mu[3] - mu[0]);
+    h[4] = mu[4];
+    h[5] = R(0.5) * (mu[5] - mu[0]);
+    if (n > 6) {
+        h[6] = (mu[6] - R(3) * mu[1]) * R(1.0 / 6.0);
+        h[7] = R(0.5) * (mu[7] - mu[2]);
+        h[8] = R(0.5) * (mu[8] - mu[1]);
+        h[9] = (mu[9] - R(3) * mu[2]) * R(1.0 / 6.0);
+    }
+}
+
+// moments of (r c + d) from moments of c: 1D, degree 3 (n = 4) or 2 (n = 3)
+template <typename R>
+PD void shift_1d(R mu[4], R r, R d, int n)
+{
+    R r2 = r * r;
+    R m1 = r * mu[1], m2 = r2 * mu[2];
+    R m0 = mu[0];
+    if (n > 3) {
+        R m3 = r2 * r * mu[3];
+        mu[3] = m3 + d * (R(3) * m2 + d * (R(3) * m1 + d * m0));
+    }
+    mu[2] = m2 + d * (R(2) * m1 + d * m0);
+    mu[1] = m1 + d * m0;
+}
+
+// 2D binomial shift: x' = r c + d, moments up to total degree 3 (n = 10) or 2 (n = 6)
+template <typename R>
+PD void shift_2d(R mu[10], R r, R dx, R dy, int n)
+{
+    R r2 = r * r;
+    // scale by r^(k+l)
+    R v00 = mu[0], v10 = r * mu[1], v01 = r * mu[2];
+    R v20 = r2 * mu[3], v11 = r2 * mu[4], v02 = r2 * mu[5];
+    R v30 = R(0), v21 = R(0), v12 = R(0), v03 = R(0);
+    if (n > 6) {
+        R r3 = r2 * r;
+        v30 = r3 * mu[6];
+        v21 = r3 * mu[7];
+        v12 = r3 * mu[8];
+        v03 = r3 * mu[9];
+    }
+    // shift in x
+    R c30 = v30 + dx * (R(3) * v20 + dx * (R(3) * v10 + dx * v00));
+    R c20 = v20 + dx * (R(2) * v10 + dx * v00);
+    R c10 = v10 + dx * v00;
+    R c21 = v21 + dx * (R(2) * v11 + dx * v01);
+    R c11 = v11 + dx * v01;
+    R c12 = v12 + dx * v02;
+    // shift in y
+    mu[1] = c10;
+    mu[2] = v01 + dy * v00;
+    mu[3] = c20;
+    mu[4] = c11 + dy * c10;
+    mu[5] = v02 + dy * (R(2) * v01 + dy * v00);
+    if (n > 6) {
+        mu[6] = c30;
+        mu[7] = c21 + dy * c20;
+        mu[8] = c12 + dy * (R(2) * c11 + dy * c10);
+        mu[9] = v03 + dy * (R(3) * v02 + dy * (R(3) * v01 + dy * v00));
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// reduced populations p_i = f_i / W_i from Hermite coefficients
+// ---------------------------------------------------------------------------------
+
+template <typename R>
+PD void eval_1d(const R h[4], R p[4], int order)
+{
+    R h3 = (order > 2) ? h[3] : R(0);
+    R Ea = h[0] + h[2] * Lat<R>::he2a, Oa = h[1] * Lat<R>::ca + h3 * Lat<R>::he3a;
+    R Eb = h[0] + h[2] * Lat<R>::he2b, Ob = h[1] * Lat<R>::cb + h3 * Lat<R>::he3b;
+    p[0] = Eb - Ob;
+    p[1] = Ea - Oa;
+    p[2] = Ea + Oa;
+    p[3] = Eb + Ob;
+}
+
+// 2D: sum factorization over y then x, with the parity of He_p at +-c
+template <typename R>
+PD void eval_2d(const R h[10], R p[16], int order)
+{
+    const bool o3 = order > 2;
+    R h30 = o3 ? h[6] : R(0), h21 = o3 ? h[7] : R(0), h12 = o3 ? h[8] : R(0), h03 = o3 ? h[9] : R(0);
+    // B[p][iy] = sum_q h[p][q] He_q(c_iy), p = x degree
+    R B0[4], B1[4], B2[4], B3[4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const R c = m ? Lat<R>::cb : Lat<R>::ca;
+        const R e2 = m ? Lat<R>::he2b : Lat<R>::he2a;
+        const R e3 = m ? Lat<R>::he3b : Lat<R>::he3a;
+        const int ip = m ? 3 : 2, im = m ? 0 : 1;
+        R E = h[0] + h[5] * e2, O = h[2] * c + h03 * e3;
+        B0[ip] = E + O;
+        B0[im] = E - O;
+        E = h[1] + h12 * e2;
+        O = h[4] * c;
+        B1[ip] = E + O;
+        B1[im] = E - O;
+        E = h[3];
+        O = h21 * c;
+        B2[ip] = E + O;
+        B2[im] = E - O;
+        B3[ip] = h30;
+        B3[im] = h30;
+    }
+#pragma unroll
+    for (int iy = 0; iy < 4; ++iy) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const R c = m ? Lat<R>::cb : Lat<R>::ca;
+            const R e2 = m ? Lat<R>::he2b : Lat<R>::he2a;
+            const R e3 = m ? Lat<R>::he3b : Lat<R>::he3a;
+            const int ip = m ? 3 : 2, im = m ? 0 : 1;
+            R E = B0[iy] + B2[iy] * e2, O = B1[iy] * c + B3[iy] * e3;
+            p[ip + 4 * iy] = E + O;
+            p[im + 4 * iy] = E - O;
+        }
+    }
+}
+
+// raw moments mu = sum_i W_i p_i c^k (1D), up to degree n-1
+template <typename R>
+PD void moments_1d(const R p[4], R mu[4], int n)
+{
+    R s0a = Lat<R>::wa * (p[2] + p[1]), s0b = Lat<R>::wb * (p[3] + p[0]);
+    R s1a = Lat<R>::wa * (p[2] - p[1]), s1b = Lat<R>::wb * (p[3] - p[0]);
+    const R ca = Lat<R>::ca, cb = Lat<R>::cb;
+    mu[0] = s0a + s0b;
+    mu[1] = ca * s1a + cb * s1b;
+    mu[2] = ca * ca * s0a + cb * cb * s0b;
+    if (n > 3) mu[3] = ca * ca * ca * s1a + cb * cb * cb * s1b;
+}
+
+// 2D raw moments up to total degree 3 (n = 10) or 2 (n = 6)
+template <typename R>
+PD void moments_2d(const R p[16], R mu[10], int n)
+{
+    // reduce over y for every column ix: Rl[ix] = sum_iy w_iy c_iy^l p(ix, iy)
+    R R0[4], R1[4], R2[4], R3[4];
+    const R ca = Lat<R>::ca, cb = Lat<R>::cb;
+#pragma unroll
+    for (int ix = 0; ix < 4; ++ix) {
+        R ea = Lat<R>::wa * (p[ix + 8] + p[ix + 4]), oa = Lat<R>::wa * (p[ix + 8] - p[ix + 4]);
+        R eb = Lat<R>::wb * (p[ix + 12] + p[ix]), ob = Lat<R>::wb * (p[ix + 12] - p[ix]);
+        R0[ix] = ea + eb;
+        R1[ix] = ca * oa + cb * ob;
+        R2[ix] = ca * ca * ea + cb * cb * eb;
+        R3[ix] = ca * ca * ca * oa + cb * cb * cb * ob;
+    }
+    // reduce over x
+    auto red = [&](const R* Rl, R& m0, R& m1, R& m2, R& m3) {
+        R ea = Lat<R>::wa * (Rl[2] + Rl[1]), oa = Lat<R>::wa * (Rl[2] - Rl[1]);
+        R eb = Lat<R>::wb * (Rl[3] + Rl[0]), ob = Lat<R>::wb * (Rl[3] - Rl[0]);
+        m0 = ea + eb;
+        m1 = ca * oa + cb * ob;
+        m2 = ca * ca * ea + cb * cb * eb;
+        m3 = ca * ca * ca * oa + cb * cb * cb * ob;
+    };
+    R a0, a1, a2, a3;
+    red(R0, a0, a1, a2, a3);
+    mu[0] = a0;
+    mu[1] = a1;
+    mu[3] = a2;
+    if (n > 6) mu[6] = a3;
+    red(R1, a0, a1, a2, a3);
+    mu[2] = a0;
+    mu[4] = a1;
+    if (n > 6) mu[7] = a2;
+    red(R2, a0, a1, a2, a3);
+    mu[5] = a0;
+    if (n > 6) mu[8] = a1;
+    if (n > 6) {
+        red(R3, a0, a1, a2, a3);
+        mu[9] = a0;
+    }
+}
+
+// slope limiters of the MUSCL reconstruction (Van Leer, minmod)
+template <typename R>
+PD R limit(R a, R b, int kind)
+{
+    R ab = a * b;
+    if (!(ab > R(0))) return R(0);
+    if (kind == 1) return (a > R(0)) ? fmin(a, b) : fmax(a, b);
+    return R(2) * ab / (a + b);
+}
+
+} // namespace pond

@@ -1,0 +1,1241 @@
+// pond_kernels.hpp -- HIP kernels of the finite-volume PonD step (gfx950, wave64).
+//
+// Per step three launches on one stream:
+//   dt_kernel    one thread per instance: dt = cfl / rate (rate from the previous update's
+//                epilogue), clipped at t_end; advances the instance clock.
+//   face_kernel  one thread per face (2D: per x-face and y-face owner position) with an
+//                LDS-staged halo tile of phi-bar-plus cells; runs the predictor-corrector
+//                iteration of the face frame (Sec. III.B.3) and writes the face state.
+//   cell_kernel  one thread per cell: face populations converted into the cell frame, flux,
+//                co-moving BGK update (Sec. III.B.2), FP64 conserved update, and the reframe
+//                that opens the next step (Sec. III.B.4) with the CFL rate of the new frame.
+//
+// Cell state (SoA planes): FP64 conserved U = (rho, rho u, rho E), plus the non-equilibrium
+// Grad coefficients of f~ (h2, h3) and g~ (h1, h2) in the cell's co-moving frame, in the
+// precision R of the populations. g~'s h0 follows from the energy: the state carries exactly
+// what the next step's reframe keeps.
+// Face state (SoA planes, precision R): frame (u, T) -- also the next step's seed -- and
+// all Hermite coefficients of phi at the face in that frame (f: degree 3, g: degree 2).
+#pragma once
+
+#include <stdint.h>
+
+#include "pond_core.hpp"
+
+namespace pond {
+
+enum { BC_PERIODIC = 0, BC_OUTFLOW, BC_REFLECT, BC_FIXED, BC_FIXED_WINDOW, BC_SPLIT, BC_MOVING };
+
+enum { ST_CELLS = 0, ST_CONV_CELLS, ST_FACES, ST_ITERS, ST_NONCONV, ST_FALLBACK, ST_DEPOUT, ST_ITMAX, ST_N };
+
+enum { ERR_NONPHYS = 1, ERR_DEPART = 2, ERR_NONCONV = 4 };
+
+struct Params {
+    int dim, nx, ny, n_inst;
+    double x0, y0, dx, dy;
+    double Cv, cfl, mu, tol;
+    int limiter, max_iter;
+    int bc[4];
+    double bc_state[4][4], bc_alt[4][4], bc_param[4][4];
+    int64_t ncell, nface, nfx;
+};
+
+template <typename R>
+struct State {
+    double *U;      // (D+2) x ncell
+    R *H;           // non-equilibrium coefficients: 1D 4, 2D 12 planes x ncell
+    R *F;           // face state: 1D 9, 2D 19 planes x nface
+    int *fiter;     // per face: iterations | (nonconverged << 16) | (fallback << 17)
+    const int *cell_inst;   // per cell (1D batch) or null
+    const int *face_inst;   // per face (1D batch) or null
+    const int64_t *cell_off; // per instance + 1
+    const int64_t *pad_off;  // per instance: padded offset (cell_off + 4k)
+    double *t, *tstart, *dt;   // per instance
+    const double *dxk;         // per instance cell size (1D tubes), or null: P.dx
+    unsigned long long *vmax;  // 2 x n_inst (slot by step parity)
+    unsigned long long *stats; // ST_N counters
+    int *err;
+};
+
+template <int D>
+struct Layout;
+template <>
+struct Layout<1> {
+    static constexpr int NH = 4;  // f h2 h3, g h1 h2
+    static constexpr int NF = 9;  // u T | f h0..h3 | g h0..h2
+    static constexpr int NL = 9;  // LDS: u s T rho fh2 fh3 g0 g1 g2
+};
+template <>
+struct Layout<2> {
+    static constexpr int NH = 12; // f h20 h11 h02 h30 h21 h12 h03, g h10 h01 h20 h11 h02
+    static constexpr int NF = 19; // ux uy T | f 10 | g 6
+    static constexpr int NL = 18; // LDS: ux uy s rho f(7) g(6) T
+};
+
+// ---------------------------------------------------------------------------------
+// small helpers
+// ---------------------------------------------------------------------------------
+
+PD unsigned long long wave_sum(unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+PD void stat_add(unsigned long long *stats, int k, unsigned long long v)
+{
+    v = wave_sum(v);
+    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0 && v) atomicAdd(&stats[k], v);
+}
+
+PD void stat_max(unsigned long long *stats, int k, unsigned long long v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0 && v) atomicMax(&stats[k], v);
+}
+
+// rho, u, T from conserved variables (ideal gas, R = 1): rho E = C_v rho T + rho |u|^2 / 2
+template <int D>
+PD void prim(const double *U, int64_t n, int64_t c, double &rho, double u[2], double &T, double Cv)
+{
+    rho = U[c];
+    double ke = 0.0;
+    for (int a = 0; a < D; ++a) {
+        u[a] = U[(1 + a) * n + c] / rho;
+        ke += u[a] * u[a];
+    }
+    if (D == 1) u[1] = 0.0;
+    T = (U[(1 + D) * n + c] / rho - 0.5 * ke) / Cv;
+}
+
+// ---------------------------------------------------------------------------------
+// dt kernel: one thread per instance
+// ---------------------------------------------------------------------------------
+
+template <int D, typename R>
+__global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
+{
+    int k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= P.n_inst) return;
+    double rate = __longlong_as_double((long long)S.vmax[slot * P.n_inst + k]);
+    double t = S.t[k];
+    double dt = P.cfl / rate;
+    if (!(rate > 0.0)) dt = 0.0;
+    if (t + dt > t_end) dt = t_end - t;
+    if (!(dt > 0.0)) dt = 0.0;
+    S.tstart[k] = t;
+    S.dt[k] = dt;
+    S.t[k] = t + dt;
+    S.vmax[(slot ^ 1) * P.n_inst + k] = 0ull;
+}
+
+// ---------------------------------------------------------------------------------
+// boundary mapping and the phi-bar-plus record of one (possibly ghost) cell
+// ---------------------------------------------------------------------------------
+
+struct CellRef {
+    int64_t src;   // source cell index, or -1 for a fixed state
+    int mx, my;    // mirror flags
+    const double *st; // fixed state (rho ux uy p)
+};
+
+PD double xcen(const Params &P, int i) { return P.x0 + (i + 0.5) * P.dx; }
+PD double ycen(const Params &P, int j) { return P.y0 + (j + 0.5) * P.dy; }
+
+// rule of one side along one axis; g = ghost coordinate, n = cells along the axis.
+// returns the source coordinate, or -1 with *st set for a fixed state.
+PD int side_rule(const Params &P, int side, int g, int n, double tpos, double xc_, double yc_,
+                 double t, int &mirror, const double *&st)
+{
+    int kind = P.bc[side];
+    if (kind == BC_SPLIT) kind = (tpos < P.bc_param[side][0]) ? BC_FIXED : BC_REFLECT;
+    switch (kind) {
+    case BC_PERIODIC: return (g < 0) ? g + n : g - n;
+    case BC_OUTFLOW: return (g < 0) ? 0 : n - 1;
+    case BC_REFLECT: mirror ^= 1; return (g < 0) ? (-1 - g) : (2 * n - 1 - g);
+    case BC_FIXED: st = P.bc_state[side]; return -1;
+    case BC_FIXED_WINDOW:
+        st = (tpos >= P.bc_param[side][0] && tpos <= P.bc_param[side][1]) ? P.bc_alt[side]
+                                                                           : P.bc_state[side];
+        return -1;
+    default: { // moving shock
+        double xs = P.bc_param[side][0] + P.bc_param[side][1] * (yc_ + P.bc_param[side][2] * t);
+        st = (xc_ < xs) ? P.bc_state[side] : P.bc_alt[side];
+        return -1;
+    }
+    }
+}
+
+// 2D: y rule first (every column), then x rule at the mapped row
+PD CellRef map2d(const Params &P, int i, int j, double t)
+{
+    CellRef r{0, 0, 0, nullptr};
+    int si = i, sj = j;
+    if (j < 0 || j >= P.ny) {
+        int side = (j < 0) ? 2 : 3;
+        sj = side_rule(P, side, j, P.ny, xcen(P, i), xcen(P, i), ycen(P, j), t, r.my, r.st);
+        if (sj < 0) {
+            r.src = -1;
+            return r;
+        }
+    }
+    if (i < 0 || i >= P.nx) {
+        int side = (i < 0) ? 0 : 1;
+        si = side_rule(P, side, i, P.nx, ycen(P, sj), xcen(P, i), ycen(P, sj), t, r.mx, r.st);
+        if (si < 0) {
+            r.src = -1;
+            return r;
+        }
+    }
+    r.src = (int64_t)si + (int64_t)P.nx * sj;
+    return r;
+}
+
+// phi-bar-plus of one cell into an LDS record (Sec. III.B.3): phi+ = A f~ + B f_eq with
+// A = (2 - eps/2)/(2 + eps), B = (3 eps/2)/(2 + eps), eps = dt p / mu; f_eq = rho W_i
+// and g_eq = (C_v - D/2) rho T W_i in the co-moving frame (Sec. II.B).
+template <int D, typename R>
+PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double dt, R *out,
+                    int NT, int slot)
+{
+    double rho, u[2], T;
+    R fh[7] = {0, 0, 0, 0, 0, 0, 0}, gh[5] = {0, 0, 0, 0, 0};
+    const int nfh = (D == 1) ? 2 : 7, ngh = (D == 1) ? 2 : 5;
+    if (c.src < 0) {
+        rho = c.st[0];
+        u[0] = c.st[1];
+        u[1] = (D == 2) ? c.st[2] : 0.0;
+        T = c.st[3] / c.st[0];
+    } else {
+        prim<D>(S.U, P.ncell, c.src, rho, u, T, P.Cv);
+        for (int k = 0; k < nfh; ++k) fh[k] = S.H[k * P.ncell + c.src];
+        for (int k = 0; k < ngh; ++k) gh[k] = S.H[(nfh + k) * P.ncell + c.src];
+        if (D == 1) {
+            if (c.mx) {
+                u[0] = -u[0];
+                fh[1] = -fh[1];
+                gh[0] = -gh[0];
+            }
+        } else {
+            if (c.mx) { // odd x degree flips: f h11 h30 h12, g h10 h11
+                u[0] = -u[0];
+                fh[1] = -fh[1];
+                fh[3] = -fh[3];
+                fh[5] = -fh[5];
+                gh[0] = -gh[0];
+                gh[3] = -gh[3];
+            }
+            if (c.my) { // odd y degree flips: f h11 h21 h03, g h01 h11
+                u[1] = -u[1];
+                fh[1] = -fh[1];
+                fh[4] = -fh[4];
+                fh[6] = -fh[6];
+                gh[1] = -gh[1];
+                gh[3] = -gh[3];
+            }
+        }
+    }
+    const double eps = dt * rho * T / P.mu;
+    const double Ap = (2.0 - 0.5 * eps) / (2.0 + eps), Bp = 1.5 * eps / (2.0 + eps);
+    const double geq = (P.Cv - 0.5 * D) * rho * T;
+    // g~'s zeroth coefficient from the energy: rho E = rho|u|^2/2 + T(tr h2 + D rho/2) + b0
+    double trh2 = (D == 1) ? (double)fh[0] : (double)fh[0] + (double)fh[2];
+    double b0 = geq - T * trh2;
+    if (D == 1) {
+        out[0 * NT] = (R)u[0];
+        out[1 * NT] = (R)sqrt(T);
+        out[2 * NT] = (R)T;
+        out[3 * NT] = (R)rho;
+        out[4 * NT] = (R)(Ap * fh[0]);
+        out[5 * NT] = (R)(Ap * fh[1]);
+        out[6 * NT] = (R)(Ap * b0 + Bp * geq);
+        out[7 * NT] = (R)(Ap * gh[0]);
+        out[8 * NT] = (R)(Ap * gh[1]);
+    } else {
+        out[0 * NT] = (R)u[0];
+        out[1 * NT] = (R)u[1];
+        out[2 * NT] = (R)sqrt(T);
+        out[3 * NT] = (R)rho;
+        for (int k = 0; k < 7; ++k) out[(4 + k) * NT] = (R)(Ap * fh[k]);
+        out[11 * NT] = (R)(Ap * b0 + Bp * geq);
+        for (int k = 0; k < 5; ++k) out[(12 + k) * NT] = (R)(Ap * gh[k]);
+        out[17 * NT] = (R)T;
+    }
+    (void)slot;
+}
+
+// ---------------------------------------------------------------------------------
+// stencil populations in the current face frame
+// ---------------------------------------------------------------------------------
+
+// reduced populations of stencil cell c (LDS record) in frame (u, s); f (NC = full
+// degree 3) or g (degree 2)
+template <typename R, bool G>
+PD void cell_pops_1d(const R *L, int NT, int c, R u, R inv_s, R p[4])
+{
+    R r = L[1 * NT + c] * inv_s, d = (L[c] - u) * inv_s;
+    R h[4], mu[4];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = L[4 * NT + c];
+        h[3] = L[5 * NT + c];
+    } else {
+        h[0] = L[6 * NT + c];
+        h[1] = L[7 * NT + c];
+        h[2] = L[8 * NT + c];
+        h[3] = R(0);
+    }
+    h2mu_1d(h, mu);
+    shift_1d(mu, r, d, G ? 3 : 4);
+    mu2h_1d(mu, h);
+    eval_1d(h, p, G ? 2 : 3);
+}
+
+template <typename R, bool G>
+PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
+{
+    R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
+    R h[10], mu[10];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = R(0);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
+        h2mu_2d(h, mu, 10);
+        shift_2d(mu, r, dx, dy, 10);
+        mu2h_2d(mu, h, 10);
+        eval_2d(h, p, 3);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
+        h2mu_2d(h, mu, 6);
+        shift_2d(mu, r, dx, dy, 6);
+        mu2h_2d(mu, h, 6);
+        eval_2d(h, p, 2);
+    }
+}
+
+// MUSCL reconstruction at the departure points, 1D. idx: L, R, L-1, R+1.
+// Returns the reduced populations phi-bar_i / W_i at the face.
+template <typename R, bool G>
+PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx, int lim,
+                 R out[4])
+{
+    R PL[4], PR[4], T[4], A[4];
+    cell_pops_1d<R, G>(L, NT, idx[0], u, inv_s, PL);
+    cell_pops_1d<R, G>(L, NT, idx[1], u, inv_s, PR);
+    cell_pops_1d<R, G>(L, NT, idx[2], u, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        R v = s * node<R>(i) + u;
+        A[i] = (v >= R(0)) ? PL[i] - T[i] : PR[i] - PL[i];
+    }
+    cell_pops_1d<R, G>(L, NT, idx[3], u, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        R v = s * node<R>(i) + u;
+        bool up = v >= R(0);
+        R B = up ? PR[i] - PL[i] : T[i] - PR[i];
+        R sl = limit(A[i], B, lim);
+        R off = (up ? R(0.5) : R(-0.5)) - v * hdx;
+        out[i] = (up ? PL[i] : PR[i]) + off * sl;
+    }
+}
+
+// 2D, face normal along AXIS. idx: L, R, L-n, R+n, L-t, L+t, R-t, R+t.
+template <typename R, bool G, int AXIS>
+PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
+                 int lim, R out[16])
+{
+    R PL[16], PR[16], T[16], A[16];
+    const R un = AXIS ? uy : ux, ut = AXIS ? ux : uy;
+    bool upn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) upn[k] = (s * node<R>(k) + un) >= R(0);
+    auto nk = [](int i) { return AXIS ? (i >> 2) : (i & 3); };
+    auto tk = [](int i) { return AXIS ? (i & 3) : (i >> 2); };
+    cell_pops_2d<R, G>(L, NT, idx[0], ux, uy, inv_s, PL);
+    cell_pops_2d<R, G>(L, NT, idx[1], ux, uy, inv_s, PR);
+    cell_pops_2d<R, G>(L, NT, idx[2], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) A[i] = upn[nk(i)] ? PL[i] - T[i] : PR[i] - PL[i];
+    cell_pops_2d<R, G>(L, NT, idx[3], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const bool up = upn[nk(i)];
+        R vn = s * node<R>(nk(i)) + un;
+        R B = up ? PR[i] - PL[i] : T[i] - PR[i];
+        R sl = limit(A[i], B, lim);
+        R off = (up ? R(0.5) : R(-0.5)) - vn * hdn;
+        R pu = up ? PL[i] : PR[i];
+        out[i] = pu + off * sl;
+        PL[i] = pu; // upwind value, kept for the tangential slope
+    }
+    // tangential slope of the upwind cell
+    cell_pops_2d<R, G>(L, NT, idx[4], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) A[i] = PL[i] - T[i];
+    cell_pops_2d<R, G>(L, NT, idx[6], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i)
+        if (!upn[nk(i)]) A[i] = PL[i] - T[i];
+    cell_pops_2d<R, G>(L, NT, idx[5], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) PR[i] = T[i] - PL[i];
+    cell_pops_2d<R, G>(L, NT, idx[7], ux, uy, inv_s, T);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
+        R sl = limit(A[i], B, lim);
+        R vt = s * node<R>(tk(i)) + ut;
+        out[i] += (-vt * hdt) * sl;
+    }
+}
+
+// ---------------------------------------------------------------------------------
+// face finalization: moments of phi-bar in frame `last` -> phi in the final frame
+// ---------------------------------------------------------------------------------
+
+// writes the face state: frame, f coefficients (degree 3) and g coefficients (degree 2)
+// of phi = (phi-bar + (eps/4) phi_eq) / (1 + eps/4), phi_eq the co-moving equilibrium of the
+// final frame (Sec. III.B.3), eps = dt p_b / mu.
+template <int D, typename R>
+PD void face_write(const Params &P, const State<R> &S, int64_t f, R *mf, R *mg, const R *ul,
+                   R sl, const R *uf, R Tf, bool has_frame, double dt)
+{
+    const int64_t nf = P.nface;
+    R sf = sqrt(Tf);
+    if (D == 1) {
+        R h[4], hg[4];
+        if (has_frame) {
+            R inv = R(1) / sf;
+            shift_1d(mf, sl * inv, (ul[0] - uf[0]) * inv, 4);
+            shift_1d(mg, sl * inv, (ul[0] - uf[0]) * inv, 3);
+        }
+        mu2h_1d(mf, h);
+        mg[3] = R(0);
+        mu2h_1d(mg, hg);
+        R rho = h[0];
+        double eps = has_frame ? dt * (double)rho * (double)Tf / P.mu : 0.0;
+        R c = (R)(1.0 / (1.0 + 0.25 * eps));
+        R e4 = (R)(0.25 * eps);
+        S.F[0 * nf + f] = uf[0];
+        S.F[1 * nf + f] = Tf;
+        S.F[2 * nf + f] = rho;
+        S.F[3 * nf + f] = h[1] * c;
+        S.F[4 * nf + f] = h[2] * c;
+        S.F[5 * nf + f] = h[3] * c;
+        S.F[6 * nf + f] = (hg[0] + e4 * (R)(P.Cv - 0.5) * rho * Tf) * c;
+        S.F[7 * nf + f] = hg[1] * c;
+        S.F[8 * nf + f] = hg[2] * c;
+    } else {
+        R h[10], hg[10];
+        if (has_frame) {
+            R inv = R(1) / sf;
+            R r = sl * inv, dx = (ul[0] - uf[0]) * inv, dy = (ul[1] - uf[1]) * inv;
+            shift_2d(mf, r, dx, dy, 10);
+            shift_2d(mg, r, dx, dy, 6);
+        }
+        mu2h_2d(mf, h, 10);
+        mu2h_2d(mg, hg, 6);
+        R rho = h[0];
+        double eps = has_frame ? dt * (double)rho * (double)Tf / P.mu : 0.0;
+        R c = (R)(1.0 / (1.0 + 0.25 * eps));
+        R e4 = (R)(0.25 * eps);
+        S.F[0 * nf + f] = uf[0];
+        S.F[1 * nf + f] = uf[1];
+        S.F[2 * nf + f] = Tf;
+        S.F[3 * nf + f] = rho;
+#pragma unroll
+        for (int k = 1; k < 10; ++k) S.F[(3 + k) * nf + f] = h[k] * c;
+        S.F[13 * nf + f] = (hg[0] + e4 * (R)(P.Cv - 1.0) * rho * Tf) * c;
+#pragma unroll
+        for (int k = 1; k < 6; ++k) S.F[(13 + k) * nf + f] = hg[k] * c;
+    }
+}
+
+// mean frame of two cells' conserved variables (seed of the first step, restart frame)
+template <int D, typename R>
+PD void mean_frame(const R *L, int NT, int a, int b, const Params &P, R u[2], R &T)
+{
+    const int su = 0, ss = (D == 1) ? 1 : 2, sT = (D == 1) ? 2 : 17, sr = 3;
+    (void)ss;
+    double ra = L[sr * NT + a], rb = L[sr * NT + b];
+    double ua[2] = {(double)L[su * NT + a], D == 2 ? (double)L[NT + a] : 0.0};
+    double ub[2] = {(double)L[su * NT + b], D == 2 ? (double)L[NT + b] : 0.0};
+    double Ta = L[sT * NT + a], Tb = L[sT * NT + b];
+    double r = 0.5 * (ra + rb), e = 0.0, ke = 0.0, m[2];
+    double ka = 0.0, kb = 0.0;
+    for (int q = 0; q < D; ++q) {
+        m[q] = 0.5 * (ra * ua[q] + rb * ub[q]);
+        ka += ua[q] * ua[q];
+        kb += ub[q] * ub[q];
+    }
+    e = 0.5 * (P.Cv * ra * Ta + 0.5 * ra * ka) + 0.5 * (P.Cv * rb * Tb + 0.5 * rb * kb);
+    for (int q = 0; q < D; ++q) {
+        u[q] = (R)(m[q] / r);
+        ke += (m[q] / r) * (m[q] / r);
+    }
+    if (D == 1) u[1] = R(0);
+    T = (R)((e / r - 0.5 * ke) / P.Cv);
+}
+
+// first-order upwind state from each neighbour's own frame (fallback), as raw moments
+// in frame (um, sm)
+template <typename R, bool G>
+PD void own_half_1d(const R *L, int NT, int c, bool right, R um, R inv_sm, R mu[4])
+{
+    R u = L[c], s = L[NT + c];
+    R h[4], p[4];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = L[4 * NT + c];
+        h[3] = L[5 * NT + c];
+    } else {
+        h[0] = L[6 * NT + c];
+        h[1] = L[7 * NT + c];
+        h[2] = L[8 * NT + c];
+        h[3] = R(0);
+    }
+    eval_1d(h, p, G ? 2 : 3);
+    for (int i = 0; i < 4; ++i) {
+        R v = s * node<R>(i) + u;
+        bool take = right ? (v < R(0)) : (v >= R(0));
+        if (!take) p[i] = R(0);
+    }
+    moments_1d(p, mu, 4);
+    shift_1d(mu, s * inv_sm, (u - um) * inv_sm, 4);
+}
+
+template <typename R, bool G, int AXIS>
+PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_sm, R mu[10])
+{
+    R ux = L[c], uy = L[NT + c], s = L[2 * NT + c];
+    R h[10], p[16];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = R(0);
+        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
+        eval_2d(h, p, 3);
+    } else {
+        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
+        eval_2d(h, p, 2);
+    }
+    const R un = AXIS ? uy : ux;
+    for (int i = 0; i < 16; ++i) {
+        R v = s * node<R>(AXIS ? (i >> 2) : (i & 3)) + un;
+        bool take = right ? (v < R(0)) : (v >= R(0));
+        if (!take) p[i] = R(0);
+    }
+    moments_2d(p, mu, 10);
+    shift_2d(mu, s * inv_sm, (ux - umx) * inv_sm, (uy - umy) * inv_sm, 10);
+}
+
+// ---------------------------------------------------------------------------------
+// the face iteration (Sec. III.B.3)
+// ---------------------------------------------------------------------------------
+
+struct FaceCount {
+    unsigned long long iters, nonconv, fallback, depout, itmax;
+};
+
+// 1D face f with LDS stencil indices idx = {L, R, L-1, R+1}
+template <typename R>
+PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[4], int64_t f,
+                double dt, double dx, FaceCount &cnt)
+{
+    const R hdx = (R)(0.5 * dt / dx);
+    const int64_t nf = P.nface;
+    R u[2] = {S.F[0 * nf + f], R(0)}, T = S.F[1 * nf + f];
+    R mu_m[2];
+    R T_m;
+    mean_frame<1, R>(L, NT, idx[0], idx[1], P, mu_m, T_m);
+    bool restarted = false;
+    if (!(T > R(0))) {
+        u[0] = mu_m[0];
+        T = T_m;
+        restarted = true;
+    }
+    R mf[4], mg[4], ul[2] = {u[0], R(0)}, sl = sqrt(T);
+    int it = 0;
+    bool conv = false, failed = false;
+    while (it < P.max_iter) {
+        ++it;
+        R s = sqrt(T), inv_s = R(1) / s;
+        R qf[4], qg[4];
+        recon_1d<R, false>(L, NT, idx, u[0], s, inv_s, hdx, P.limiter, qf);
+        recon_1d<R, true>(L, NT, idx, u[0], s, inv_s, hdx, P.limiter, qg);
+        moments_1d(qf, mf, 4);
+        moments_1d(qg, mg, 3);
+        R rho = mf[0];
+        R du = s * mf[1] / rho;
+        R rhoe = R(0.5) * s * s * (mf[2] - mf[1] * mf[1] / rho) + mg[0];
+        R Tn = rhoe / ((R)P.Cv * rho);
+        if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(du)) {
+            if (!restarted) {
+                restarted = true;
+                u[0] = mu_m[0];
+                T = T_m;
+                continue;
+            }
+            failed = true;
+            break;
+        }
+        R delta = fmax(fabs(du) / sqrt(Tn), fabs(Tn - T) / Tn);
+        ul[0] = u[0];
+        sl = s;
+        u[0] += du;
+        T = Tn;
+        if (delta <= (R)P.tol) {
+            conv = true;
+            break;
+        }
+    }
+    bool has_frame = true;
+    if (failed) {
+        // first-order upwind state from the neighbours' own frames
+        R inv_sm = R(1) / sqrt(T_m);
+        R a[4], b[4];
+        own_half_1d<R, false>(L, NT, idx[0], false, mu_m[0], inv_sm, a);
+        own_half_1d<R, false>(L, NT, idx[1], true, mu_m[0], inv_sm, b);
+        for (int k = 0; k < 4; ++k) mf[k] = a[k] + b[k];
+        own_half_1d<R, true>(L, NT, idx[0], false, mu_m[0], inv_sm, a);
+        own_half_1d<R, true>(L, NT, idx[1], true, mu_m[0], inv_sm, b);
+        for (int k = 0; k < 4; ++k) mg[k] = a[k] + b[k];
+        R sm = sqrt(T_m);
+        R rho = mf[0];
+        R du = sm * mf[1] / rho;
+        R Tn = (R(0.5) * sm * sm * (mf[2] - mf[1] * mf[1] / rho) + mg[0]) / ((R)P.Cv * rho);
+        ul[0] = mu_m[0];
+        sl = sm;
+        if (rho > R(0) && Tn > R(0) && isfinite(Tn) && isfinite(du)) {
+            u[0] = mu_m[0] + du;
+            T = Tn;
+        } else {
+            has_frame = false;
+            u[0] = mu_m[0];
+            T = T_m;
+        }
+        cnt.fallback += 1;
+    }
+    {
+        R s = sqrt(T);
+        R v0 = s * node<R>(3) + fabs(u[0]);
+        if (v0 * (R)(0.5 * dt) > (R)(0.5 * dx)) cnt.depout += 1;
+    }
+    if (!conv) cnt.nonconv += 1;
+    cnt.iters += it;
+    if ((unsigned long long)it > cnt.itmax) cnt.itmax = it;
+    face_write<1, R>(P, S, f, mf, mg, ul, sl, u, T, has_frame, dt);
+    S.fiter[f] = it | ((conv ? 0 : 1) << 16) | ((failed ? 1 : 0) << 17);
+}
+
+template <typename R, int AXIS>
+PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[8], int64_t f,
+                double dt, FaceCount &cnt)
+{
+    const double dn = AXIS ? P.dy : P.dx, dtn = AXIS ? P.dx : P.dy;
+    const R hdn = (R)(0.5 * dt / dn), hdt = (R)(0.5 * dt / dtn);
+    const int64_t nf = P.nface;
+    R u[2] = {S.F[0 * nf + f], S.F[1 * nf + f]}, T = S.F[2 * nf + f];
+    R um[2], T_m;
+    mean_frame<2, R>(L, NT, idx[0], idx[1], P, um, T_m);
+    bool restarted = false;
+    if (!(T > R(0))) {
+        u[0] = um[0];
+        u[1] = um[1];
+        T = T_m;
+        restarted = true;
+    }
+    R mf[10], mg[10], ul[2] = {u[0], u[1]}, sl = sqrt(T);
+    int it = 0;
+    bool conv = false, failed = false;
+    while (it < P.max_iter) {
+        ++it;
+        R s = sqrt(T), inv_s = R(1) / s;
+        {
+            R q[16];
+            recon_2d<R, false, AXIS>(L, NT, idx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, q);
+            moments_2d(q, mf, 10);
+            recon_2d<R, true, AXIS>(L, NT, idx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, q);
+            moments_2d(q, mg, 6);
+        }
+        R rho = mf[0];
+        R irho = R(1) / rho;
+        R dux = s * mf[1] * irho, duy = s * mf[2] * irho;
+        R rhoe = R(0.5) * s * s * (mf[3] + mf[5] - (mf[1] * mf[1] + mf[2] * mf[2]) * irho) + mg[0];
+        R Tn = rhoe / ((R)P.Cv * rho);
+        if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(dux) || !isfinite(duy)) {
+            if (!restarted) {
+                restarted = true;
+                u[0] = um[0];
+                u[1] = um[1];
+                T = T_m;
+                continue;
+            }
+            failed = true;
+            break;
+        }
+        R delta = fmax(fmax(fabs(dux), fabs(duy)) / sqrt(Tn), fabs(Tn - T) / Tn);
+        ul[0] = u[0];
+        ul[1] = u[1];
+        sl = s;
+        u[0] += dux;
+        u[1] += duy;
+        T = Tn;
+        if (delta <= (R)P.tol) {
+            conv = true;
+            break;
+        }
+    }
+    bool has_frame = true;
+    if (failed) {
+        R sm = sqrt(T_m), inv_sm = R(1) / sm;
+        R a[10], b[10];
+        own_half_2d<R, false, AXIS>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
+        own_half_2d<R, false, AXIS>(L, NT, idx[1], true, um[0], um[1], inv_sm, b);
+        for (int k = 0; k < 10; ++k) mf[k] = a[k] + b[k];
+        own_half_2d<R, true, AXIS>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
+        own_half_2d<R, true, AXIS>(L, NT, idx[1], true, um[0], um[1], inv_sm, b);
+        for (int k = 0; k < 10; ++k) mg[k] = a[k] + b[k];
+        R rho = mf[0];
+        R dux = sm * mf[1] / rho, duy = sm * mf[2] / rho;
+        R Tn = (R(0.5) * sm * sm * (mf[3] + mf[5] - (mf[1] * mf[1] + mf[2] * mf[2]) / rho) + mg[0]) /
+               ((R)P.Cv * rho);
+        ul[0] = um[0];
+        ul[1] = um[1];
+        sl = sm;
+        if (rho > R(0) && Tn > R(0) && isfinite(Tn) && isfinite(dux) && isfinite(duy)) {
+            u[0] = um[0] + dux;
+            u[1] = um[1] + duy;
+            T = Tn;
+        } else {
+            has_frame = false;
+            u[0] = um[0];
+            u[1] = um[1];
+            T = T_m;
+        }
+        cnt.fallback += 1;
+    }
+    {
+        R s = sqrt(T);
+        R vx = s * node<R>(3) + fabs(u[0]), vy = s * node<R>(3) + fabs(u[1]);
+        if (vx * (R)(0.5 * dt) > (R)(0.5 * P.dx) || vy * (R)(0.5 * dt) > (R)(0.5 * P.dy)) cnt.depout += 1;
+    }
+    if (!conv) cnt.nonconv += 1;
+    cnt.iters += it;
+    if ((unsigned long long)it > cnt.itmax) cnt.itmax = it;
+    face_write<2, R>(P, S, f, mf, mg, ul, sl, u, T, has_frame, dt);
+    S.fiter[f] = it | ((conv ? 0 : 1) << 16) | ((failed ? 1 : 0) << 17);
+}
+
+// ---------------------------------------------------------------------------------
+// face kernels
+// ---------------------------------------------------------------------------------
+
+// 1D: one thread per face. Tubes are laid out in a padded index space with two ghost
+// slots on each side: face f of tube k has its stencil at padded slots f + 3k .. f + 3k + 3.
+template <typename R>
+__global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int tube_span)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *L = reinterpret_cast<R *>(smem_raw);
+    const int B = blockDim.x;
+    const int NT = B + 3 + 3 * tube_span;
+    const int64_t f0 = (int64_t)blockIdx.x * B;
+    const int64_t f = f0 + threadIdx.x;
+    const int64_t flast = min(f0 + B, P.nface) - 1;
+    const int k0 = S.face_inst ? S.face_inst[f0] : 0;
+    const int k1 = S.face_inst ? S.face_inst[flast] : 0;
+    const int64_t vlo = f0 + 3 * (int64_t)k0;
+    const int64_t vhi = flast + 3 * (int64_t)k1 + 3;
+    // all instances in one block share nothing but the LDS tile; each cell uses its
+    // own instance's dt and clock
+    for (int64_t v = vlo + threadIdx.x; v <= vhi; v += B) {
+        int k = k0;
+        while (k < k1 && v >= S.pad_off[k + 1]) ++k;
+        const int64_t c0 = S.cell_off[k];
+        const int n = (int)(S.cell_off[k + 1] - c0);
+        int q = (int)(v - S.pad_off[k]) - 2;
+        CellRef c{0, 0, 0, nullptr};
+        if (q >= 0 && q < n) {
+            c.src = c0 + q;
+        } else {
+            int side = (q < 0) ? 0 : 1;
+            int sq = side_rule(P, side, q, n, 0.0, xcen(P, q), 0.0, S.tstart[k], c.mx, c.st);
+            c.src = (sq < 0) ? -1 : c0 + sq;
+        }
+        plus_record<1, R>(P, S, c, S.dt[k], L + (v - vlo), NT, 0);
+    }
+    __syncthreads();
+    FaceCount cnt{0, 0, 0, 0, 0};
+    unsigned long long nfc = 0;
+    if (f < P.nface) {
+        const int k = S.face_inst ? S.face_inst[f] : 0;
+        const double dt = S.dt[k];
+        if (dt > 0.0) {
+            const int base = (int)(f + 3 * (int64_t)k - vlo);
+            const int idx[4] = {base + 1, base + 2, base, base + 3};
+            face_1d<R>(P, S, L, NT, idx, f, dt, S.dxk ? S.dxk[k] : P.dx, cnt);
+            nfc = 1;
+        }
+    }
+    stat_add(S.stats, ST_FACES, nfc);
+    stat_add(S.stats, ST_ITERS, cnt.iters);
+    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
+    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
+    stat_add(S.stats, ST_DEPOUT, cnt.depout);
+    stat_max(S.stats, ST_ITMAX, cnt.itmax);
+    if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// 2D: thread (i, j) owns x-face (i, j) (if j < ny) and y-face (i, j) (if i < nx).
+// LDS tile: cells i0-2 .. i0+BX, j0-2 .. j0+BY.
+template <typename R>
+__global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *L = reinterpret_cast<R *>(smem_raw);
+    const int BX = blockDim.x, BY = blockDim.y;
+    const int TX = BX + 3, TY = BY + 3;
+    const int NT = TX * TY;
+    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    const double dt = S.dt[0];
+    if (!(dt > 0.0)) return;
+    const double t = S.tstart[0];
+    const int tid = threadIdx.x + BX * threadIdx.y;
+    for (int e = tid; e < NT; e += BX * BY) {
+        int ci = i0 - 2 + e % TX, cj = j0 - 2 + e / TX;
+        // faces reference cells in [-2, nx+1] x [-2, ny+1] only
+        if (ci > P.nx + 1 || cj > P.ny + 1) continue;
+        CellRef c = map2d(P, ci, cj, t);
+        plus_record<2, R>(P, S, c, dt, L + e, NT, 0);
+    }
+    __syncthreads();
+    const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
+    auto li = [&](int ci, int cj) { return (ci - i0 + 2) + TX * (cj - j0 + 2); };
+    FaceCount cnt{0, 0, 0, 0, 0};
+    unsigned long long nfaces = 0;
+    if (i <= P.nx && j < P.ny) {
+        const int idx[8] = {li(i - 1, j), li(i, j), li(i - 2, j), li(i + 1, j),
+                            li(i - 1, j - 1), li(i - 1, j + 1), li(i, j - 1), li(i, j + 1)};
+        face_2d<R, 0>(P, S, L, NT, idx, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
+        ++nfaces;
+    }
+    if (i < P.nx && j <= P.ny) {
+        const int idx[8] = {li(i, j - 1), li(i, j), li(i, j - 2), li(i, j + 1),
+                            li(i - 1, j - 1), li(i + 1, j - 1), li(i - 1, j), li(i + 1, j)};
+        face_2d<R, 1>(P, S, L, NT, idx, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
+        ++nfaces;
+    }
+    stat_add(S.stats, ST_FACES, nfaces);
+    stat_add(S.stats, ST_ITERS, cnt.iters);
+    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
+    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
+    stat_add(S.stats, ST_DEPOUT, cnt.depout);
+    stat_max(S.stats, ST_ITMAX, cnt.itmax);
+    if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// ---------------------------------------------------------------------------------
+// cell update (Sec. III.B.2) + reframe of the next step (Sec. III.B.4)
+// ---------------------------------------------------------------------------------
+
+// conserved flux through a face along `axis` (lab frame, FP64) from the face state:
+// mass sum f v_a, momentum sum f v_b v_a, energy sum (|v|^2/2) f v_a + sum g v_a
+template <int D, typename R>
+PD void face_flux(const Params &P, const State<R> &S, int64_t f, int axis, double out[4])
+{
+    const int64_t nf = P.nface;
+    double u[2], T, h[10], hg[6];
+    if (D == 1) {
+        u[0] = S.F[f];
+        u[1] = 0.0;
+        T = S.F[nf + f];
+        for (int k = 0; k < 4; ++k) h[k] = S.F[(2 + k) * nf + f];
+        for (int k = 0; k < 3; ++k) hg[k] = S.F[(6 + k) * nf + f];
+        double s = sqrt(T), rho = h[0];
+        double m1 = h[1], m2 = h[0] + 2.0 * h[2], m3 = 3.0 * h[1] + 6.0 * h[3];
+        double uu = u[0];
+        out[0] = rho * uu + s * m1;
+        out[1] = rho * uu * uu + 2.0 * s * uu * m1 + s * s * m2;
+        out[2] = 0.5 * (rho * uu * uu * uu + 3.0 * s * uu * uu * m1 + 3.0 * s * s * uu * m2 +
+                        s * s * s * m3) +
+                 hg[0] * uu + s * hg[1];
+    } else {
+        u[0] = S.F[f];
+        u[1] = S.F[nf + f];
+        T = S.F[2 * nf + f];
+        for (int k = 0; k < 10; ++k) h[k] = S.F[(3 + k) * nf + f];
+        for (int k = 0; k < 6; ++k) hg[k] = S.F[(13 + k) * nf + f];
+        double s = sqrt(T), rho = h[0];
+        double m1[2] = {h[1], h[2]};
+        double m2[2][2] = {{h[0] + 2.0 * h[3], h[4]}, {h[4], h[0] + 2.0 * h[5]}};
+        double m3x = 3.0 * h[1] + 6.0 * h[6], m3xxy = h[2] + 2.0 * h[7];
+        double m3xyy = h[1] + 2.0 * h[8], m3y = 3.0 * h[2] + 6.0 * h[9];
+        const int a = axis;
+        double ua = u[a];
+        double uu = u[0] * u[0] + u[1] * u[1];
+        double um1 = u[0] * m1[0] + u[1] * m1[1];
+        double trm2 = m2[0][0] + m2[1][1];
+        double ugm2 = u[0] * m2[0][a] + u[1] * m2[1][a];
+        double m3c = (a == 0) ? (m3x + m3xyy) : (m3xxy + m3y);
+        out[0] = rho * ua + s * m1[a];
+        for (int b = 0; b < 2; ++b)
+            out[1 + b] = rho * u[b] * ua + s * (u[b] * m1[a] + ua * m1[b]) + s * s * m2[b][a];
+        out[3] = 0.5 * (rho * uu * ua + s * uu * m1[a] + 2.0 * s * ua * um1 + 2.0 * s * s * ugm2 +
+                        s * s * ua * trm2 + s * s * s * m3c) +
+                 hg[0] * ua + s * hg[1 + a];
+    }
+}
+
+template <int D, typename R>
+PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
+                    unsigned long long &bits, bool &all_conv);
+
+template <int D, typename R>
+__global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool active = c < P.ncell;
+    const int k = (active && S.cell_inst) ? S.cell_inst[c] : 0;
+    const double dt = S.dt[k];
+    const bool work = active && dt > 0.0;
+    unsigned long long bits = 0ull;
+    bool all_conv = false;
+    if (work) cell_update<D, R>(P, S, c, k, dt, slot, bits, all_conv);
+    unsigned long long *vm = S.vmax + (size_t)(slot ^ 1) * P.n_inst + k;
+    // one atomic per wave when the whole wave belongs to one instance
+    int k_first = __shfl(k, 0, 64);
+    bool same = __all(k == k_first);
+    if (same) {
+        unsigned long long m = bits;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            unsigned long long w = __shfl_xor(m, o, 64);
+            m = w > m ? w : m;
+        }
+        if ((threadIdx.x & 63) == 0 && m) atomicMax(vm, m);
+    } else if (work) {
+        atomicMax(vm, bits);
+    }
+    stat_add(S.stats, ST_CELLS, work ? 1 : 0);
+    stat_add(S.stats, ST_CONV_CELLS, (work && all_conv) ? 1 : 0);
+}
+
+template <int D, typename R>
+PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
+                    unsigned long long &bits_out, bool &all_conv_out)
+{
+    const int64_t n = P.ncell;
+    const int64_t nf = P.nface;
+    double rho, ud[2], T;
+    prim<D>(S.U, n, c, rho, ud, T, P.Cv);
+    const R su = (R)sqrt(T), inv_su = (R)(1.0 / sqrt(T));
+    const R ux = (R)ud[0], uy = (R)ud[1];
+    const double eps = dt * rho * T / P.mu;
+    const R A = (R)((2.0 - eps) / (2.0 + eps)), Bc = (R)(2.0 * eps / (2.0 + eps));
+    const double geq = (P.Cv - 0.5 * D) * rho * T;
+    double dU[4] = {0.0, 0.0, 0.0, 0.0};
+    bool all_conv = true;
+    R mfo[10], mgo[10];
+    const double dxc = (D == 1 && S.dxk) ? S.dxk[k] : P.dx;
+    if (D == 1) {
+        R h[4] = {(R)rho, R(0), S.H[c], S.H[n + c]};
+        R hg[4] = {(R)(geq - T * (double)h[2]), S.H[2 * n + c], S.H[3 * n + c], R(0)};
+        R pf[4], pg[4];
+        eval_1d(h, pf, 3);
+        eval_1d(hg, pg, 2);
+        for (int i = 0; i < 4; ++i) {
+            pf[i] = A * pf[i] + Bc * (R)rho;
+            pg[i] = A * pg[i] + Bc * (R)geq;
+        }
+        const int64_t fl = c + k; // left face of this cell (tube k)
+        for (int side = 0; side < 2; ++side) {
+            const int64_t f = fl + side;
+            const R sgn = side ? R(1) : R(-1);
+            R fu = S.F[f], fT = S.F[nf + f];
+            R r = sqrt(fT) * inv_su, d = (fu - ux) * inv_su;
+            R hf[4] = {S.F[2 * nf + f], S.F[3 * nf + f], S.F[4 * nf + f], S.F[5 * nf + f]};
+            R hgf[4] = {S.F[6 * nf + f], S.F[7 * nf + f], S.F[8 * nf + f], R(0)};
+            R mu[4], q[4];
+            h2mu_1d(hf, mu);
+            shift_1d(mu, r, d, 4);
+            mu2h_1d(mu, hf);
+            eval_1d(hf, q, 3);
+            h2mu_1d(hgf, mu);
+            shift_1d(mu, r, d, 3);
+            mu2h_1d(mu, hgf);
+            R qg[4];
+            eval_1d(hgf, qg, 2);
+            const R kf = (R)(dt / dxc) * sgn;
+            for (int i = 0; i < 4; ++i) {
+                R v = su * node<R>(i) + ux;
+                pf[i] -= kf * v * q[i];
+                pg[i] -= kf * v * qg[i];
+            }
+            double fl3[4];
+            face_flux<1, R>(P, S, f, 0, fl3);
+            for (int q3 = 0; q3 < 3; ++q3) dU[q3] -= (dt / dxc) * (double)sgn * fl3[q3];
+            all_conv = all_conv && !(S.fiter[f] >> 16);
+        }
+        moments_1d(pf, mfo, 4);
+        moments_1d(pg, mgo, 3);
+    } else {
+        const int i = (int)(c % P.nx), j = (int)(c / P.nx);
+        R h[10] = {(R)rho, R(0), R(0)};
+        for (int q = 0; q < 7; ++q) h[3 + q] = S.H[q * n + c];
+        R hg[10];
+        hg[0] = (R)(geq - T * ((double)h[3] + (double)h[5]));
+        for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
+        R pf[16], pg[16];
+        eval_2d(h, pf, 3);
+        eval_2d(hg, pg, 2);
+#pragma unroll
+        for (int q = 0; q < 16; ++q) {
+            pf[q] = A * pf[q] + Bc * (R)rho;
+            pg[q] = A * pg[q] + Bc * (R)geq;
+        }
+        for (int side = 0; side < 4; ++side) {
+            const int axis = side >> 1;
+            const int hi = side & 1;
+            const int64_t f = axis == 0 ? (int64_t)(i + hi) + (int64_t)(P.nx + 1) * j
+                                        : P.nfx + (int64_t)i + (int64_t)P.nx * (j + hi);
+            const R sgn = hi ? R(1) : R(-1);
+            R fux = S.F[f], fuy = S.F[nf + f], fT = S.F[2 * nf + f];
+            R r = sqrt(fT) * inv_su, dx = (fux - ux) * inv_su, dy = (fuy - uy) * inv_su;
+            R hf[10], mu[10], q[16];
+#pragma unroll
+            for (int m = 0; m < 10; ++m) hf[m] = S.F[(3 + m) * nf + f];
+            h2mu_2d(hf, mu, 10);
+            shift_2d(mu, r, dx, dy, 10);
+            mu2h_2d(mu, hf, 10);
+            eval_2d(hf, q, 3);
+            const R kf = (R)(dt / (axis ? P.dy : P.dx)) * sgn;
+            const R ua = axis ? uy : ux;
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                R v = su * node<R>(axis ? (m >> 2) : (m & 3)) + ua;
+                pf[m] -= kf * v * q[m];
+            }
+#pragma unroll
+            for (int m = 0; m < 6; ++m) hf[m] = S.F[(13 + m) * nf + f];
+            h2mu_2d(hf, mu, 6);
+            shift_2d(mu, r, dx, dy, 6);
+            mu2h_2d(mu, hf, 6);
+            eval_2d(hf, q, 2);
+#pragma unroll
+            for (int m = 0; m < 16; ++m) {
+                R v = su * node<R>(axis ? (m >> 2) : (m & 3)) + ua;
+                pg[m] -= kf * v * q[m];
+            }
+            double fl4[4];
+            face_flux<2, R>(P, S, f, axis, fl4);
+            const double kd = (dt / (axis ? P.dy : P.dx)) * (double)sgn;
+            for (int q4 = 0; q4 < 4; ++q4) dU[q4] -= kd * fl4[q4];
+            all_conv = all_conv && !(S.fiter[f] >> 16);
+        }
+        moments_2d(pf, mfo, 10);
+        moments_2d(pg, mgo, 6);
+    }
+    // FP64 conserved update (flux form: exact telescoping between neighbours)
+    double Un[4];
+    for (int q = 0; q < D + 2; ++q) Un[q] = S.U[q * n + c] + dU[q];
+    double rn = Un[0], un[2] = {Un[1] / rn, D == 2 ? Un[2] / rn : 0.0};
+    double ke = un[0] * un[0] + un[1] * un[1];
+    double Tn = (Un[D + 1] / rn - 0.5 * ke) / P.Cv;
+    bool ok = (rn > 0.0) && (Tn > 0.0) && isfinite(Tn) && isfinite(ke);
+    if (!ok) atomicOr(S.err, ERR_NONPHYS);
+    double sn = sqrt(fabs(Tn));
+    // reframe: non-equilibrium coefficients of the updated populations in the new
+    // co-moving frame (Sec. II.C with u' = u, T' = T)
+    R r = (R)(sqrt(T) / sn), dxs = (R)((ud[0] - un[0]) / sn), dys = (R)((ud[1] - un[1]) / sn);
+    if (D == 1) {
+        R hh[4];
+        shift_1d(mfo, r, dxs, 4);
+        mfo[0] = (R)rn;
+        mu2h_1d(mfo, hh);
+        S.H[c] = hh[2];
+        S.H[n + c] = hh[3];
+        shift_1d(mgo, r, dxs, 3);
+        mgo[3] = R(0);
+        mu2h_1d(mgo, hh);
+        S.H[2 * n + c] = hh[1];
+        S.H[3 * n + c] = hh[2];
+    } else {
+        R hh[10];
+        shift_2d(mfo, r, dxs, dys, 10);
+        mfo[0] = (R)rn;
+        mu2h_2d(mfo, hh, 10);
+        for (int q = 0; q < 7; ++q) S.H[q * n + c] = hh[3 + q];
+        shift_2d(mgo, r, dxs, dys, 6);
+        mu2h_2d(mgo, hh, 6);
+        for (int q = 0; q < 5; ++q) S.H[(7 + q) * n + c] = hh[1 + q];
+    }
+    for (int q = 0; q < D + 2; ++q) S.U[q * n + c] = Un[q];
+    // CFL rate of the new frame: max_a (|u_a| + sqrt(T) c_max) / dx_a
+    double rate = (fabs(un[0]) + sn * CMAX) / dxc;
+    if (D == 2) rate = fmax(rate, (fabs(un[1]) + sn * CMAX) / P.dy);
+    if (!ok) rate = 0.0;
+    bits_out = (unsigned long long)__double_as_longlong(rate);
+    all_conv_out = all_conv;
+    (void)slot;
+    (void)k;
+}
+
+// ---------------------------------------------------------------------------------
+// initialization and read-out
+// ---------------------------------------------------------------------------------
+
+// conserved variables of the initial equilibrium; non-equilibrium coefficients zero;
+// rate of the first step; faces unseeded (T = -1)
+template <int D, typename R>
+__global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.ncell;
+    if (c < n) {
+        double rho = prim4[c], ux = prim4[n + c], uy = prim4[2 * n + c], p = prim4[3 * n + c];
+        double T = p / rho;
+        S.U[c] = rho;
+        S.U[n + c] = rho * ux;
+        if (D == 2) S.U[2 * n + c] = rho * uy;
+        double ke = ux * ux + (D == 2 ? uy * uy : 0.0);
+        S.U[(1 + D) * n + c] = P.Cv * rho * T + 0.5 * rho * ke;
+        for (int q = 0; q < nh; ++q) S.H[q * n + c] = R(0);
+        const int k = S.cell_inst ? S.cell_inst[c] : 0;
+        double rate = (fabs(ux) + sqrt(T) * CMAX) / ((D == 1 && S.dxk) ? S.dxk[k] : P.dx);
+        if (D == 2) rate = fmax(rate, (fabs(uy) + sqrt(T) * CMAX) / P.dy);
+        atomicMax(S.vmax + k, (unsigned long long)__double_as_longlong(rate));
+    }
+    if (c < P.nface) S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
+}
+
+// rho, ux, uy, T planes from U
+template <int D>
+__global__ void fields_kernel(int64_t n, const double *U, double Cv, double *out)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= n) return;
+    double rho, u[2], T;
+    prim<D>(U, n, c, rho, u, T, Cv);
+    out[c] = rho;
+    out[n + c] = u[0];
+    out[2 * n + c] = u[1];
+    out[3 * n + c] = T;
+}
+
+// populations f~ = W_i (...) and g~ of every cell in its co-moving frame
+template <int D, typename R>
+__global__ void pops_kernel(Params P, State<R> S, double *f, double *g, double *frame)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.ncell;
+    if (c >= n) return;
+    double rho, u[2], T;
+    prim<D>(S.U, n, c, rho, u, T, P.Cv);
+    const double geq = (P.Cv - 0.5 * D) * rho * T;
+    if (D == 1) {
+        double h[4] = {rho, 0.0, (double)S.H[c], (double)S.H[n + c]};
+        double hg[4] = {geq - T * h[2], (double)S.H[2 * n + c], (double)S.H[3 * n + c], 0.0};
+        double p[4], q[4];
+        eval_1d(h, p, 3);
+        eval_1d(hg, q, 2);
+        for (int i = 0; i < 4; ++i) {
+            f[i * n + c] = weight1<double>(i) * p[i];
+            g[i * n + c] = weight1<double>(i) * q[i];
+        }
+        frame[c] = u[0];
+        frame[n + c] = T;
+    } else {
+        double h[10] = {rho, 0.0, 0.0}, hg[10];
+        for (int q = 0; q < 7; ++q) h[3 + q] = S.H[q * n + c];
+        hg[0] = geq - T * (h[3] + h[5]);
+        for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
+        for (int q = 6; q < 10; ++q) hg[q] = 0.0;
+        double p[16], q2[16];
+        eval_2d(h, p, 3);
+        eval_2d(hg, q2, 2);
+        for (int i = 0; i < 16; ++i) {
+            double W = weight1<double>(i & 3) * weight1<double>(i >> 2);
+            f[i * n + c] = W * p[i];
+            g[i * n + c] = W * q2[i];
+        }
+        frame[c] = u[0];
+        frame[n + c] = u[1];
+        frame[2 * n + c] = T;
+    }
+}
+
+// lab-frame moments of the face populations (for comparison with a lab-frame reference)
+template <int D, typename R>
+__global__ void face_moments_kernel(Params P, State<R> S, double *Mf, double *Mg)
+{
+    const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t nf = P.nface;
+    if (f >= nf) return;
+    const int nf3 = (D == 1) ? 4 : 15, ng2 = (D == 1) ? 3 : 7;
+    double u[2] = {0, 0}, T, h[10], hg[10];
+    if (D == 1) {
+        u[0] = S.F[f];
+        T = S.F[nf + f];
+        for (int k = 0; k < 4; ++k) h[k] = S.F[(2 + k) * nf + f];
+        for (int k = 0; k < 3; ++k) hg[k] = S.F[(6 + k) * nf + f];
+        hg[3] = 0.0;
+        double mu[4], mg[4];
+        h2mu_1d(h, mu);
+        h2mu_1d(hg, mg);
+        // lab moments: shift to frame {0, 1}: x = s c + u
+        double s = sqrt(T);
+        shift_1d(mu, s, u[0], 4);
+        shift_1d(mg, s, u[0], 3);
+        for (int k = 0; k < 4; ++k) Mf[f * nf3 + k] = mu[k];
+        for (int k = 0; k < 3; ++k) Mg[f * ng2 + k] = mg[k];
+    } else {
+        u[0] = S.F[f];
+        u[1] = S.F[nf + f];
+        T = S.F[2 * nf + f];
+        for (int k = 0; k < 10; ++k) h[k] = S.F[(3 + k) * nf + f];
+        for (int k = 0; k < 6; ++k) hg[k] = S.F[(13 + k) * nf + f];
+        double mu[10], mg[10];
+        h2mu_2d(h, mu, 10);
+        h2mu_2d(hg, mg, 6);
+        double s = sqrt(T);
+        shift_2d(mu, s, u[0], u[1], 10);
+        shift_2d(mg, s, u[0], u[1], 6);
+        // packed tensors M0, M1[a], M2[a][b], M3[a][b][c] from mu[k][l] (k x-, l y-degree)
+        auto m = [&](const double *v, int kx, int ky) {
+            int deg = kx + ky;
+            int base = deg == 0 ? 0 : deg == 1 ? 1 : deg == 2 ? 3 : 6;
+            return v[base + ky];
+        };
+        double *o = Mf + f * nf3;
+        o[0] = m(mu, 0, 0);
+        o[1] = m(mu, 1, 0);
+        o[2] = m(mu, 0, 1);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) o[3 + 2 * a + b] = m(mu, (a == 0) + (b == 0), (a == 1) + (b == 1));
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b)
+                for (int cc = 0; cc < 2; ++cc)
+                    o[7 + 4 * a + 2 * b + cc] =
+                        m(mu, (a == 0) + (b == 0) + (cc == 0), (a == 1) + (b == 1) + (cc == 1));
+        double *og = Mg + f * ng2;
+        og[0] = m(mg, 0, 0);
+        og[1] = m(mg, 1, 0);
+        og[2] = m(mg, 0, 1);
+        for (int a = 0; a < 2; ++a)
+            for (int b = 0; b < 2; ++b) og[3 + 2 * a + b] = m(mg, (a == 0) + (b == 0), (a == 1) + (b == 1));
+    }
+}
+
+} // namespace pond

@@ -1,0 +1,118 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle, element by element.
+
+Tolerance (FP64): relative max-norm error <= 1e-12 per conserved field, the bar stated for
+the FP64 form; both sides iterate the face frames to tol = 1e-13 from the same seeds.
+"""
+import numpy as np
+import pytest
+
+from paper_2203_05477_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _pair(orc, cfg, f, precision="fp64"):
+    from paper_2203_05477_amd import pond
+
+    g = pond.Context(cfg, f, precision=precision)
+    o = orc.Sim(cfg, f["rho"], f["ux"], f.get("uy"), f["p"])
+    return g, o
+
+
+def _relerr(a, b):
+    out = []
+    for k in range(b.shape[0]):
+        scale = np.abs(b[k]).max()
+        out.append(np.abs(a[k] - b[k]).max() / (scale if scale > 0 else 1.0))
+    return np.array(out)
+
+
+def _print(tag, **kw):
+    print(tag, " ".join(f"{k}={v}" for k, v in kw.items()), flush=True)
+
+
+def test_shock_tube_full_run_fp64(orc):
+    """The 400-cell shock tube to t = 0.2 at CFL 0.5 (about 540 steps): conserved fields,
+    face frames and the populations the next step starts from."""
+    cfg, f = W.shock_tube(400)
+    _print("case", name="shock_tube", n=400)
+    g, o = _pair(orc, cfg, f)
+    n = 0
+    while o.t < 0.2 * (1 - 1e-14):
+        o.step(0.2)
+        g.step(1, 0.2)
+        n += 1
+    assert g.time()[0] == pytest.approx(o.t, rel=1e-13)
+    e = _relerr(g.conserved(), o.conserved())
+    _print("shock_tube", steps=n, err=e.max())
+    assert e.max() <= TOL64
+    fg, gg, frg = g.populations()
+    fo, go, fro = o.reframed()
+    assert np.abs(fg - fo).max() <= TOL64 * np.abs(fo).max()
+    assert np.abs(gg - go).max() <= TOL64 * np.abs(go).max()
+    assert np.abs(frg - fro).max() <= TOL64 * np.abs(fro).max()
+    ff = g.face_frames()
+    fo2 = o.face_frames()
+    assert np.abs(ff - fo2).max() <= 1e-11 * np.abs(fo2).max()
+
+
+@pytest.mark.parametrize("nx,ny,steps", [(40, 24, 8), (67, 35, 4)])
+def test_periodic_random_2d_fp64(orc, nx, ny, steps):
+    """Smooth random periodic fields on ragged grid sizes (several LDS tiles and a tail)."""
+    cfg, f = W.random_smooth(2, nx, ny, seed=7, cfl=0.3, tol=1e-13)
+    _print("case", name="random2d", nx=nx, ny=ny)
+    g, o = _pair(orc, cfg, f)
+    for _ in range(steps):
+        o.step()
+        g.step(1)
+    e = _relerr(g.conserved(), o.conserved())
+    _print("random2d", err=e.max())
+    assert e.max() <= TOL64
+    Mf_g, Mg_g = g.face_moments()
+    Mf_o, Mg_o = o.face_moments()
+    assert np.abs(Mf_g - Mf_o).max() <= 1e-11 * np.abs(Mf_o).max()
+    assert np.abs(Mg_g - Mg_o).max() <= 1e-11 * np.abs(Mg_o).max()
+    it_g, it_o = g.face_iters(), o.face_iters()
+    assert np.mean(np.abs(it_g) == np.abs(it_o)) > 0.99
+
+
+def test_double_mach_small_fp64(orc):
+    """Double Mach reflection on 96 x 24 cells, 30 steps: fixed, split fixed/reflecting,
+    moving-shock and outflow boundaries, strong shocks, restarts and fallbacks."""
+    cfg, f = W.double_mach(96, 24)
+    _print("case", name="dmr", nx=96, ny=24)
+    g, o = _pair(orc, cfg, f)
+    for k in range(30):
+        o.step()
+        g.step(1)
+        e = _relerr(g.conserved(), o.conserved())
+        assert e.max() <= TOL64, (k, e)
+    _print("dmr", err=e.max(), fallback=o.last["nonphysical"])
+
+
+def test_uniform_state_is_kept_gpu(orc):
+    from paper_2203_05477_amd import pond
+
+    cfg, f = W.uniform(2, 33, 17, tol=1e-13)
+    for prec, tol in (("fp64", 1e-13), ("mixed", 2e-6)):
+        g = pond.Context(cfg, f, precision=prec)
+        g.step(3)
+        r, ux, uy, T = g.moments()
+        assert np.abs(r - 1).max() < tol and np.abs(ux - 0.3).max() < tol
+        assert np.abs(uy + 0.2).max() < tol and np.abs(T - 0.7).max() < tol
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_periodic_conservation_gpu(orc, precision):
+    """FP64 conserved update: totals exact to FP64 round-off in both precisions."""
+    from paper_2203_05477_amd import pond
+
+    cfg, f = W.random_smooth(2, 48, 32, seed=2, cfl=0.3, tol=1e-12 if precision == "fp64" else 1e-5)
+    g = pond.Context(cfg, f, precision=precision)
+    U0 = g.conserved().sum(axis=1)
+    g.step(20)
+    U1 = g.conserved().sum(axis=1)
+    scale = np.abs(g.conserved()).sum(axis=1)
+    assert np.all(np.abs(U1 - U0) <= 1e-13 * scale)
