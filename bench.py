@@ -1,0 +1,174 @@
+"""Throughput of the finite-volume PonD step on one MI355X.
+
+Workload: the Mach-10 double Mach reflection on 1920 x 480 cells (D2Q16), the 2D
+configuration the metric is quoted on. A step is one pass of the whole hot path over the
+grid (dt reduction, face predictor-corrector, cell update + reframe). W untimed steps from
+t = 0 are followed by K timed steps (defaults 100 + 1900 = the configuration's 2000 steps).
+
+Reported: converged Mcell-updates/s (cells advanced in steps where all of their faces met
+the iteration tolerance) of the headline form, mixed precision (FP32 populations, FP64
+conserved variables); the plain FP64 form timed beside it; the relative L1 distance of the
+mixed form from the FP64 form (the FP64 form matches the FP64 oracle to 1e-12); the face
+kernel's roofline position; and the FP64 CPU oracle timed on this host on a bounded sample.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+import numpy as np  # noqa: E402
+
+METRIC = "converged Mcell-updates/s at fixed L1 err vs FP64 oracle; learned+FP32 vs plain"
+
+# Algorithmic floating-point operations of the face kernel, per face iteration and per
+# face (finalization), as counted in the kernel's arithmetic (FMA = 2): transform of the 8
+# (2D) or 4 (1D) stencil cells into the face frame, population evaluation, limited MUSCL
+# reconstruction, moments and frame update. Derivation in the design doc.
+FLOPS_FACE_ITER = {1: 330, 2: 3200}
+FLOPS_FACE_FINAL = {1: 60, 2: 330}
+# FP64 / FP32 vector peaks of MI355X (no packed FP32 instructions are used: FP32 issues at
+# the FP64 rate, so both peaks are the 78.6 TFLOP/s non-packed figure)
+PEAK_VALU_TFLOPS = 78.6
+
+
+def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True):
+    from paper_2203_05477_amd import pond
+
+    ctx = pond.Context(cfg, fields, precision=precision, seed=seed)
+    if warmup:
+        ctx.step(warmup)
+    if autotune:
+        ctx.autotune()
+    ctx.enable_timing(True)
+    import torch
+
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.step(steps)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    kt = ctx.kernel_times()
+    return ctx, st, t1 - t0, kt
+
+
+def cpu_baseline(cfg, fields, budget_s=15.0, max_steps=20):
+    """The FP64 oracle on this host's cores, first steps of the same workload."""
+    import oracle
+
+    sim = oracle.Sim(cfg, fields["rho"], fields["ux"], fields.get("uy"), fields["p"])
+    n = cfg["nx"] * cfg["ny"]
+    t0 = time.perf_counter()
+    steps, conv = 0, 0
+    while steps < max_steps:
+        sim.step()
+        steps += 1
+        if sim.last["nonconverged"] == 0:
+            conv += n
+        if time.perf_counter() - t0 > budget_s:
+            break
+    el = time.perf_counter() - t0
+    return {"value": n * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+            "kind": "oracle",
+            "sample": f"first {steps} steps of the {cfg['nx']}x{cfg['ny']} double Mach reflection "
+                      f"from t=0 (FP64, plain seed, tol {cfg['tol']:g}); {el:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=1900)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--nx", type=int, default=1920)
+    ap.add_argument("--ny", type=int, default=480)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp64", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: the PonD step is built and timed on a single MI355X; "
+              "multi-GPU runs are not part of this build (see DESIGN.md for the sharding plan)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    if not torch.cuda.is_available():
+        raise RuntimeError("bench.py needs a GPU")
+    torch.cuda.set_device(0)
+    from paper_2203_05477_amd import pond
+    from paper_2203_05477_amd import workloads as W
+
+    pond.load()
+    tol32, tol64 = W.TOL_FP32, W.TOL_FP64
+    cfg32, fields = W.double_mach(args.nx, args.ny, tol=tol32)
+    cfg64, _ = W.double_mach(args.nx, args.ny, tol=tol64)
+    ncell = args.nx * args.ny
+
+    ctx32, st32, el32, kt32 = run_form(cfg32, fields, "mixed", args.warmup, args.steps,
+                                       autotune=not args.no_autotune)
+    rec = {}
+    if not args.no_fp64:
+        ctx64, st64, el64, kt64 = run_form(cfg64, fields, "fp64", args.warmup, args.steps,
+                                           autotune=not args.no_autotune)
+        U32, U64 = ctx32.conserved(), ctx64.conserved()
+        l1 = [float(np.abs(U32[k] - U64[k]).sum() / np.abs(U64[k]).sum()) for k in range(4)]
+        rec["fp64_plain"] = {
+            "value": st64["converged_cell_updates"] / el64 / 1e6,
+            "ms_per_step": 1e3 * el64 / args.steps,
+            "mean_iters": st64["iters_total"] / max(st64["faces"], 1),
+            "face_kernel_ms": kt64["face"], "cell_kernel_ms": kt64["cell"],
+            "tiles": list(ctx64.tiles()),
+        }
+        rec["mixed_rel_l1_vs_fp64"] = {"rho": l1[0], "rho_u": l1[1], "rho_v": l1[2], "rho_E": l1[3]}
+        ctx64.close()
+
+    value = st32["converged_cell_updates"] / el32 / 1e6
+    iters_per_face = st32["iters_total"] / max(st32["faces"], 1)
+    faces_per_step = st32["faces"] / args.steps
+    face_flops = faces_per_step * (iters_per_face * FLOPS_FACE_ITER[2] + FLOPS_FACE_FINAL[2])
+    achieved = face_flops / (kt32["face"] * 1e-3) / 1e12
+    line = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "Mcell-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el32 / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"double_mach_reflection_{args.nx}x{args.ny}", "lattice": "D2Q16",
+                   "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain",
+                   "tol": tol32, "cfl": cfg32["cfl"], "mu": cfg32["mu"],
+                   "steps_from_t0": args.warmup + args.steps},
+        "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "kernel": "face_kernel_2d<float>", "kernel_ms": kt32["face"]},
+        "cell_updates": st32["cell_updates"],
+        "converged_fraction": st32["converged_cell_updates"] / max(st32["cell_updates"], 1),
+        "mean_iters_per_face": iters_per_face,
+        "fallback_faces": st32["fallback"],
+        "nonconverged_faces": st32["nonconverged"],
+        "kernel_ms": {"dt": kt32["dt"], "face": kt32["face"], "cell": kt32["cell"]},
+        "tiles": list(ctx32.tiles()),
+        "t_end": st32["t_max"],
+    }
+    line.update(rec)
+    ctx32.close()
+    if not args.no_cpu_baseline:
+        cfgc, fc = W.double_mach(args.nx, args.ny, tol=tol64)
+        line["cpu_baseline"] = cpu_baseline(cfgc, fc)
+    print(json.dumps(line), flush=True)
+
+
+if __name__ == "__main__":
+    main()

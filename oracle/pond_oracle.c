@@ -26,7 +26,10 @@
  *  - upwind cell is the left/lower one when the normal component v_i.n >= 0;
  *  - frame convergence: max(|u^(k+1)-u^(k)|_inf / sqrt(T^(k+1)),
  *    |T^(k+1)-T^(k)| / T^(k+1)) <= tol; the face keeps the moments of the last
- *    reconstruction and the frame computed from them;
+ *    reconstruction and the frame computed from them; an iteration that returns to
+ *    within 1e-2 of its last step of the frame two iterations back (a 2-cycle, which
+ *    the discontinuous upwind choice can produce) stops there as non-converged, as
+ *    does one that reaches max_iter;
  *  - seed of the first step: frame of the mean conserved variables of the two
  *    cells next to the face; later steps: the face frame of the previous step;
  *  - the face equilibrium used to recover phi from phi-bar is the co-moving
@@ -35,8 +38,9 @@
  *    y-ghosts of every column (so corner ghosts take the y rule of an x-ghost);
  *  - a corrector frame with rho <= 0 or T <= 0 restarts the iteration once from
  *    the frame of the mean conserved variables of the two neighbours; a second
- *    such frame switches the face to the first-order upwind state assembled from
- *    each neighbour's populations in that neighbour's own frame.
+ *    such frame, or an iteration that stops without converging, switches the face to
+ *    the first-order upwind state assembled from each neighbour's populations in that
+ *    neighbour's own frame.
  */
 #include "pond_oracle.h"
 
@@ -606,7 +610,8 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
 
     double Pf[8][MAXQ], Pg[8][MAXQ], fb[MAXQ], gb[MAXQ], v[MAXQ][MAXD];
     tensors Mfb, Mgb;
-    int it, conv = 0, failed = 0;
+    int it, conv = 0, failed = 0, have_pp = 0;
+    double pu[MAXD] = {0, 0}, pT = 1.0; /* frame two iterations back */
     double nu[MAXD] = {0, 0}, nT = lT;
     for (it = 1; it <= s->cfg.max_iter; ++it) {
         /* transform every stencil cell into the current frame lambda_k */
@@ -658,31 +663,45 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
                 restarted = 1;
                 for (int a = 0; a < D; ++a) lu[a] = mu_[a];
                 lT = mT;
+                have_pp = 0;
                 continue;
             }
             failed = 1;
             break;
         }
-        double du = 0.0;
-        for (int a = 0; a < D; ++a) du = fmax(du, fabs(nu[a] - lu[a]));
+        double du = 0.0, du2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            du = fmax(du, fabs(nu[a] - lu[a]));
+            du2 = fmax(du2, fabs(nu[a] - pu[a]));
+        }
         double delta = fmax(du / sqrt(nT), fabs(nT - lT) / nT);
-        for (int a = 0; a < D; ++a) lu[a] = nu[a];
+        /* distance to the frame two iterations back: a 2-cycle returns to it */
+        double delta2 = fmax(du2 / sqrt(nT), fabs(nT - pT) / nT);
+        for (int a = 0; a < D; ++a) {
+            pu[a] = lu[a];
+            lu[a] = nu[a];
+        }
+        pT = lT;
         lT = nT;
         if (delta <= s->cfg.tol) {
             conv = 1;
             break;
         }
+        if (have_pp && delta2 <= 1e-2 * delta) break; /* oscillation: stop, not converged */
+        have_pp = 1;
     }
     if (it > s->cfg.max_iter) it = s->cfg.max_iter;
     F->iters = conv ? it : -it;
 
     double rho_b = Mfb.t0;
     int has_frame = 1;
-    if (failed) {
-        /* Reading (the paper is silent on a corrector that leaves the physical states
-         * twice): the face takes the first-order upwind state in which every population
-         * comes from the neighbour it leaves, in that neighbour's own frame (no common
-         * frame, no slope). Its moments give the face frame when they are physical. */
+    if (failed || !conv) {
+        /* Reading (the paper is silent on an iteration that does not converge or leaves
+         * the physical states twice): the face takes the first-order upwind state in
+         * which every population comes from the neighbour it leaves, in that neighbour's
+         * own frame (no common frame, no slope). Its moments give the face frame when
+         * they are physical. The last iterate of a non-converged iteration is not used:
+         * it depends on the path (a cycle or a wandering sequence), this state does not. */
         ++*nonphys;
         double vL[MAXQ][MAXD], vR[MAXQ][MAXD], hf[MAXQ], hg[MAXQ];
         tensors A, B;

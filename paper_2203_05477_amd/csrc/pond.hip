@@ -44,10 +44,11 @@ struct pond_ctx {
     int64_t steps_done = 0;
     // launch shapes
     int bx = 256, by = 1, cell_block = 256;
-    // timing
+    // timing: one set of 5 events per step of a pond_step call, read once at its end
     int timing = 0;
     double ktime[4] = {0, 0, 0, 0};
-    hipEvent_t ev[8];
+    std::vector<hipEvent_t> evs;
+    hipEvent_t *ev = nullptr;
     // learned seed
     MlpDevice mlp;
 };
@@ -140,20 +141,20 @@ template <int D, typename R>
 hipError_t launch_step(pond_ctx *c, double t_end)
 {
     State<R> S = state_of<R>(c);
-    const bool tm = c->timing != 0;
-    if (tm) hipEventRecord(c->ev[0], c->stream);
+    const bool tm = c->ev != nullptr;
+    if (tm) (void)hipEventRecord(c->ev[0], c->stream);
     dt_kernel<D, R><<<blocks(c->P.n_inst, 64), 64, 0, c->stream>>>(c->P, S, t_end, c->slot);
-    if (tm) hipEventRecord(c->ev[1], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[1], c->stream);
     if (c->cfg.seed_mode == POND_SEED_MLP && c->mlp.ready) {
         hipError_t e = mlp_seed_launch<D, R>(c->mlp, c->P, S, c->stream);
         if (e != hipSuccess) return e;
     }
-    if (tm) hipEventRecord(c->ev[2], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[2], c->stream);
     hipError_t e = launch_face<D, R>(c, c->bx, c->by);
     if (e != hipSuccess) return e;
-    if (tm) hipEventRecord(c->ev[3], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[3], c->stream);
     cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
-    if (tm) hipEventRecord(c->ev[4], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[4], c->stream);
     c->slot ^= 1;
     return hipGetLastError();
 }
@@ -316,9 +317,9 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     }
     c->nh = (c->D == 1) ? Layout<1>::NH : Layout<2>::NH;
     c->nfp = (c->D == 1) ? Layout<1>::NF : Layout<2>::NF;
-    if (c->D == 2) {
-        c->bx = 16;
-        c->by = 16;
+    if (c->D == 2) { // fastest measured on the double Mach reflection; pond_autotune re-picks
+        c->bx = 8;
+        c->by = 8;
     }
     const int64_t n = P.ncell, nf = P.nface;
     bool ok = true;
@@ -354,7 +355,6 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         return POND_EDEVICE;
     }
     c->stream = c->own_stream;
-    for (auto &e : c->ev) (void)hipEventCreate(&e);
     // upload: primitive fields (staged through scratch), instance tables
     std::vector<double> prim4((size_t)4 * n, 0.0);
     for (int64_t i = 0; i < n; ++i) {
@@ -409,23 +409,35 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
     if (c->cfg.seed_mode == POND_SEED_MLP && !c->mlp.ready) return POND_ESTATE;
     HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
     double kt[4] = {0, 0, 0, 0};
-    for (int s = 0; s < nsteps; ++s) {
-        HIPCHK(step_once(c, t_end));
-        if (c->timing) {
-            float ms;
-            HIPCHK(hipEventSynchronize(c->ev[4]));
-            hipEventElapsedTime(&ms, c->ev[0], c->ev[1]);
-            kt[0] += ms;
-            hipEventElapsedTime(&ms, c->ev[2], c->ev[3]);
-            kt[1] += ms;
-            hipEventElapsedTime(&ms, c->ev[3], c->ev[4]);
-            kt[2] += ms;
-            hipEventElapsedTime(&ms, c->ev[1], c->ev[2]);
-            kt[3] += ms;
+    if (c->timing) {
+        size_t need = (size_t)5 * std::max(nsteps, 1);
+        while (c->evs.size() < need) {
+            hipEvent_t e;
+            HIPCHK(hipEventCreate(&e));
+            c->evs.push_back(e);
         }
     }
-    if (c->timing && nsteps > 0)
+    for (int s = 0; s < nsteps; ++s) {
+        c->ev = c->timing ? &c->evs[(size_t)5 * s] : nullptr;
+        HIPCHK(step_once(c, t_end));
+    }
+    if (c->timing && nsteps > 0) {
+        HIPCHK(hipStreamSynchronize(c->stream));
+        for (int s = 0; s < nsteps; ++s) {
+            hipEvent_t *e = &c->evs[(size_t)5 * s];
+            float ms = 0.0f;
+            (void)hipEventElapsedTime(&ms, e[0], e[1]);
+            kt[0] += ms;
+            (void)hipEventElapsedTime(&ms, e[2], e[3]);
+            kt[1] += ms;
+            (void)hipEventElapsedTime(&ms, e[3], e[4]);
+            kt[2] += ms;
+            (void)hipEventElapsedTime(&ms, e[1], e[2]);
+            kt[3] += ms;
+        }
         for (int q = 0; q < 4; ++q) c->ktime[q] = kt[q] / nsteps;
+    }
+    c->ev = nullptr;
     unsigned long long hs[ST_N];
     int herr = 0;
     HIPCHK(hipMemcpyAsync(hs, c->stats, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
@@ -670,7 +682,7 @@ pond_status pond_autotune(pond_ctx *c)
     if (c->D == 1)
         cand = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
     else
-        cand = {{16, 16}, {32, 8}, {8, 8}, {64, 4}, {32, 4}, {16, 8}, {64, 2}};
+        cand = {{8, 8}, {16, 4}, {16, 8}, {16, 16}, {32, 8}, {64, 4}, {32, 2}};
     double best = 1e30;
     int bbx = c->bx, bby = c->by;
     hipEvent_t e0, e1;
@@ -747,7 +759,7 @@ void pond_free(pond_ctx *c)
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
     free_all(c);
-    for (auto &e : c->ev) (void)hipEventDestroy(e);
+    for (auto &e : c->evs) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
 }

@@ -141,16 +141,19 @@ __global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
 struct CellRef {
     int64_t src;   // source cell index, or -1 for a fixed state
     int mx, my;    // mirror flags
-    const double *st; // fixed state (rho ux uy p)
+    int fside;     // side whose fixed state applies (src < 0)
+    int falt;      // 0: bc_state of that side, 1: bc_alt
 };
 
 PD double xcen(const Params &P, int i) { return P.x0 + (i + 0.5) * P.dx; }
 PD double ycen(const Params &P, int j) { return P.y0 + (j + 0.5) * P.dy; }
 
 // rule of one side along one axis; g = ghost coordinate, n = cells along the axis.
-// returns the source coordinate, or -1 with *st set for a fixed state.
+// returns the source coordinate, or -1 with (fside, falt) naming the fixed state.
+// (No pointer into the by-value kernel argument is formed: that would force a private
+// copy of the whole parameter block.)
 PD int side_rule(const Params &P, int side, int g, int n, double tpos, double xc_, double yc_,
-                 double t, int &mirror, const double *&st)
+                 double t, int &mirror, int &fside, int &falt)
 {
     int kind = P.bc[side];
     if (kind == BC_SPLIT) kind = (tpos < P.bc_param[side][0]) ? BC_FIXED : BC_REFLECT;
@@ -158,14 +161,15 @@ PD int side_rule(const Params &P, int side, int g, int n, double tpos, double xc
     case BC_PERIODIC: return (g < 0) ? g + n : g - n;
     case BC_OUTFLOW: return (g < 0) ? 0 : n - 1;
     case BC_REFLECT: mirror ^= 1; return (g < 0) ? (-1 - g) : (2 * n - 1 - g);
-    case BC_FIXED: st = P.bc_state[side]; return -1;
+    case BC_FIXED: fside = side; falt = 0; return -1;
     case BC_FIXED_WINDOW:
-        st = (tpos >= P.bc_param[side][0] && tpos <= P.bc_param[side][1]) ? P.bc_alt[side]
-                                                                           : P.bc_state[side];
+        fside = side;
+        falt = (tpos >= P.bc_param[side][0] && tpos <= P.bc_param[side][1]) ? 1 : 0;
         return -1;
     default: { // moving shock
         double xs = P.bc_param[side][0] + P.bc_param[side][1] * (yc_ + P.bc_param[side][2] * t);
-        st = (xc_ < xs) ? P.bc_state[side] : P.bc_alt[side];
+        fside = side;
+        falt = (xc_ < xs) ? 0 : 1;
         return -1;
     }
     }
@@ -174,11 +178,11 @@ PD int side_rule(const Params &P, int side, int g, int n, double tpos, double xc
 // 2D: y rule first (every column), then x rule at the mapped row
 PD CellRef map2d(const Params &P, int i, int j, double t)
 {
-    CellRef r{0, 0, 0, nullptr};
+    CellRef r{0, 0, 0, -1, 0};
     int si = i, sj = j;
     if (j < 0 || j >= P.ny) {
         int side = (j < 0) ? 2 : 3;
-        sj = side_rule(P, side, j, P.ny, xcen(P, i), xcen(P, i), ycen(P, j), t, r.my, r.st);
+        sj = side_rule(P, side, j, P.ny, xcen(P, i), xcen(P, i), ycen(P, j), t, r.my, r.fside, r.falt);
         if (sj < 0) {
             r.src = -1;
             return r;
@@ -186,7 +190,7 @@ PD CellRef map2d(const Params &P, int i, int j, double t)
     }
     if (i < 0 || i >= P.nx) {
         int side = (i < 0) ? 0 : 1;
-        si = side_rule(P, side, i, P.nx, ycen(P, sj), xcen(P, i), ycen(P, sj), t, r.mx, r.st);
+        si = side_rule(P, side, i, P.nx, ycen(P, sj), xcen(P, i), ycen(P, sj), t, r.mx, r.fside, r.falt);
         if (si < 0) {
             r.src = -1;
             return r;
@@ -207,13 +211,18 @@ PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double
     R fh[7] = {0, 0, 0, 0, 0, 0, 0}, gh[5] = {0, 0, 0, 0, 0};
     const int nfh = (D == 1) ? 2 : 7, ngh = (D == 1) ? 2 : 5;
     if (c.src < 0) {
-        rho = c.st[0];
-        u[0] = c.st[1];
-        u[1] = (D == 2) ? c.st[2] : 0.0;
-        T = c.st[3] / c.st[0];
+        double st[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) st[q] = c.falt ? P.bc_alt[c.fside][q] : P.bc_state[c.fside][q];
+        rho = st[0];
+        u[0] = st[1];
+        u[1] = (D == 2) ? st[2] : 0.0;
+        T = st[3] / st[0];
     } else {
         prim<D>(S.U, P.ncell, c.src, rho, u, T, P.Cv);
+#pragma unroll
         for (int k = 0; k < nfh; ++k) fh[k] = S.H[k * P.ncell + c.src];
+#pragma unroll
         for (int k = 0; k < ngh; ++k) gh[k] = S.H[(nfh + k) * P.ncell + c.src];
         if (D == 1) {
             if (c.mx) {
@@ -352,9 +361,9 @@ PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx,
 // 2D, face normal along AXIS. idx: L, R, L-n, R+n, L-t, L+t, R-t, R+t.
 template <typename R, bool G, int AXIS>
 PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
-                 int lim, R out[16])
+                 int lim, R M[10])
 {
-    R PL[16], PR[16], T[16], A[16];
+    R PL[16], PR[16], T[16], A[16], out[16];
     const R un = AXIS ? uy : ux, ut = AXIS ? ux : uy;
     bool upn[4];
 #pragma unroll
@@ -362,10 +371,13 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
     auto nk = [](int i) { return AXIS ? (i >> 2) : (i & 3); };
     auto tk = [](int i) { return AXIS ? (i & 3) : (i >> 2); };
     cell_pops_2d<R, G>(L, NT, idx[0], ux, uy, inv_s, PL);
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[1], ux, uy, inv_s, PR);
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[2], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = upn[nk(i)] ? PL[i] - T[i] : PR[i] - PL[i];
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[3], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -379,23 +391,154 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
         PL[i] = pu; // upwind value, kept for the tangential slope
     }
     // tangential slope of the upwind cell
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[4], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = PL[i] - T[i];
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[6], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         if (!upn[nk(i)]) A[i] = PL[i] - T[i];
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[5], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) PR[i] = T[i] - PL[i];
+    __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[7], ux, uy, inv_s, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
         R sl = limit(A[i], B, lim);
         R vt = s * node<R>(tk(i)) + ut;
-        out[i] += (-vt * hdt) * sl;
+        A[i] = out[i] + (-vt * hdt) * sl;
+    }
+    moments_2d(A, M, G ? 6 : 10);
+}
+
+// half of the populations of stencil cell c in frame (u, s), normal magnitude c_m
+template <typename R, bool G, int AXIS>
+PD void cell_half_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int m, R p[8])
+{
+    R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
+    R h[10], mu[10];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = R(0);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
+        h2mu_2d(h, mu, 10);
+        shift_2d(mu, r, dx, dy, 10);
+        mu2h_2d(mu, h, 10);
+        eval_half_2d<R, AXIS>(h, m, p, 3);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
+        h2mu_2d(h, mu, 6);
+        shift_2d(mu, r, dx, dy, 6);
+        mu2h_2d(mu, h, 6);
+        eval_half_2d<R, AXIS>(h, m, p, 2);
+    }
+}
+
+// MUSCL reconstruction of one half of the populations (normal magnitude c_m) at the
+// departure points, 2D, face normal along AXIS. The stencil cells are visited one at a
+// time (L, R, L-n, R+n, L-t, L+t, R-t, R+t: LDS index base + a*sn + b*st), which keeps
+// only four half-population arrays live. The reconstructed phi-bar_i / W_i are
+// accumulated into raw moments M (normal, tangential degree order of mu).
+template <typename R, bool G, int AXIS>
+PD void recon_half_2d(const R *L, int NT, int base, int sn, int st, R un, R ut, R ux, R uy,
+                      R s, R inv_s, R hdn, R hdt, int lim, int m, R M[10])
+{
+    R PL[8], PR[8], A[8], Bt[8];
+    const R cm = m ? Lat<R>::cb : Lat<R>::ca;
+    const R wm = m ? Lat<R>::wb : Lat<R>::wa;
+    R vn[2];
+    vn[0] = un - s * cm;
+    vn[1] = un + s * cm;
+    const bool up0 = vn[0] >= R(0), up1 = vn[1] >= R(0);
+#pragma unroll 1
+    for (int k = 0; k < 8; ++k) {
+        const int a = (k == 1 || k >= 6) ? 1 : (k == 2 ? -1 : (k == 3 ? 2 : 0));
+        const int b = (k == 4 || k == 6) ? -1 : ((k == 5 || k == 7) ? 1 : 0);
+        R X[8];
+        cell_half_2d<R, G, AXIS>(L, NT, base + a * sn + b * st, ux, uy, inv_s, m, X);
+        if (k == 0) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) PL[j] = X[j];
+        } else if (k == 1) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) PR[j] = X[j];
+        } else if (k == 2) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A[j] = ((j & 1) ? up1 : up0) ? PL[j] - X[j] : PR[j] - PL[j];
+        } else if (k == 3) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) {
+                const bool u = (j & 1) ? up1 : up0;
+                R B = u ? PR[j] - PL[j] : X[j] - PR[j];
+                R sl = limit(A[j], B, lim);
+                R pu = u ? PL[j] : PR[j];
+                R off = (u ? R(0.5) : R(-0.5)) - vn[j & 1] * hdn;
+                PL[j] = pu;            // upwind value
+                PR[j] = pu + off * sl; // reconstruction so far
+            }
+        } else if (k == 4) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) A[j] = PL[j] - X[j];
+        } else if (k == 5) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) Bt[j] = X[j] - PL[j];
+        } else if (k == 6) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j)
+                if (!((j & 1) ? up1 : up0)) A[j] = PL[j] - X[j];
+        } else {
+#pragma unroll
+            for (int t = 0; t < 4; ++t) {
+                const R ct = node<R>(t);
+                const R off = -(s * ct + ut) * hdt;
+                R q[2];
+#pragma unroll
+                for (int sg = 0; sg < 2; ++sg) {
+                    const int j = 2 * t + sg;
+                    R B = (sg ? up1 : up0) ? Bt[j] : X[j] - PL[j];
+                    q[sg] = PR[j] + off * limit(A[j], B, lim);
+                }
+                // moments of the pair (+-c_m, c_t): even normal degree takes the sum,
+                // odd normal degree the difference
+                const R w = wm * weight1<R>(t);
+                const R Sw = w * (q[1] + q[0]), Dw = w * cm * (q[1] - q[0]);
+                const R ct2 = ct * ct;
+                M[0] += Sw;
+                M[2] += Sw * ct;
+                M[5] += Sw * ct2;
+                M[1] += Dw;
+                M[4] += Dw * ct;
+                M[3] += Sw * cm * cm;
+                if (!G) {
+                    M[9] += Sw * ct2 * ct;
+                    M[8] += Dw * ct2;
+                    M[7] += Sw * cm * cm * ct;
+                    M[6] += Dw * cm * cm;
+                }
+            }
+        }
+    }
+}
+
+// (normal, tangential) moment order -> (x, y) order for a y-normal face
+template <typename R, int AXIS>
+PD void to_xy(R M[10], int n)
+{
+    if (AXIS == 0) return;
+    R t;
+    t = M[1]; M[1] = M[2]; M[2] = t;
+    t = M[3]; M[3] = M[5]; M[5] = t;
+    if (n > 6) {
+        t = M[6]; M[6] = M[9]; M[9] = t;
+        t = M[7]; M[7] = M[8]; M[8] = t;
     }
 }
 
@@ -566,6 +709,8 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
         restarted = true;
     }
     R mf[4], mg[4], ul[2] = {u[0], R(0)}, sl = sqrt(T);
+    R upp = u[0], Tpp = T; // frame two iterations back
+    bool have_pp = false;
     int it = 0;
     bool conv = false, failed = false;
     while (it < P.max_iter) {
@@ -585,23 +730,31 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
                 restarted = true;
                 u[0] = mu_m[0];
                 T = T_m;
+                have_pp = false;
                 continue;
             }
             failed = true;
             break;
         }
+        R un = u[0] + du;
         R delta = fmax(fabs(du) / sqrt(Tn), fabs(Tn - T) / Tn);
+        R delta2 = fmax(fabs(un - upp) / sqrt(Tn), fabs(Tn - Tpp) / Tn);
+        upp = u[0];
+        Tpp = T;
         ul[0] = u[0];
         sl = s;
-        u[0] += du;
+        u[0] = un;
         T = Tn;
         if (delta <= (R)P.tol) {
             conv = true;
             break;
         }
+        // an iteration that returns to the frame two iterations back oscillates: stop
+        if (have_pp && delta2 <= R(1e-2) * delta) break;
+        have_pp = true;
     }
     bool has_frame = true;
-    if (failed) {
+    if (failed || !conv) {
         // first-order upwind state from the neighbours' own frames
         R inv_sm = R(1) / sqrt(T_m);
         R a[4], b[4];
@@ -640,8 +793,8 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
 }
 
 template <typename R, int AXIS>
-PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[8], int64_t f,
-                double dt, FaceCount &cnt)
+PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[2], int sn,
+                int stn, int64_t f, double dt, FaceCount &cnt)
 {
     const double dn = AXIS ? P.dy : P.dx, dtn = AXIS ? P.dx : P.dy;
     const R hdn = (R)(0.5 * dt / dn), hdt = (R)(0.5 * dt / dtn);
@@ -657,17 +810,18 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
         restarted = true;
     }
     R mf[10], mg[10], ul[2] = {u[0], u[1]}, sl = sqrt(T);
+    R upp[2] = {u[0], u[1]}, Tpp = T; // frame two iterations back
+    bool have_pp = false;
     int it = 0;
     bool conv = false, failed = false;
     while (it < P.max_iter) {
         ++it;
         R s = sqrt(T), inv_s = R(1) / s;
         {
-            R q[16];
-            recon_2d<R, false, AXIS>(L, NT, idx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, q);
-            moments_2d(q, mf, 10);
-            recon_2d<R, true, AXIS>(L, NT, idx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, q);
-            moments_2d(q, mg, 6);
+            const int b0 = idx[0];
+            const int sidx[8] = {b0, b0 + sn, b0 - sn, b0 + 2 * sn, b0 - stn, b0 + stn, b0 + sn - stn, b0 + sn + stn};
+            recon_2d<R, false, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, mf);
+            recon_2d<R, true, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, mg);
         }
         R rho = mf[0];
         R irho = R(1) / rho;
@@ -680,25 +834,35 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
                 u[0] = um[0];
                 u[1] = um[1];
                 T = T_m;
+                have_pp = false;
                 continue;
             }
             failed = true;
             break;
         }
-        R delta = fmax(fmax(fabs(dux), fabs(duy)) / sqrt(Tn), fabs(Tn - T) / Tn);
+        const R unx = u[0] + dux, uny = u[1] + duy;
+        const R isq = R(1) / sqrt(Tn);
+        R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, fabs(Tn - T) / Tn);
+        R delta2 = fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, fabs(Tn - Tpp) / Tn);
+        upp[0] = u[0];
+        upp[1] = u[1];
+        Tpp = T;
         ul[0] = u[0];
         ul[1] = u[1];
         sl = s;
-        u[0] += dux;
-        u[1] += duy;
+        u[0] = unx;
+        u[1] = uny;
         T = Tn;
         if (delta <= (R)P.tol) {
             conv = true;
             break;
         }
+        // an iteration that returns to the frame two iterations back oscillates: stop
+        if (have_pp && delta2 <= R(1e-2) * delta) break;
+        have_pp = true;
     }
     bool has_frame = true;
-    if (failed) {
+    if (failed || !conv) {
         R sm = sqrt(T_m), inv_sm = R(1) / sm;
         R a[10], b[10];
         own_half_2d<R, false, AXIS>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
@@ -766,12 +930,12 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
         const int64_t c0 = S.cell_off[k];
         const int n = (int)(S.cell_off[k + 1] - c0);
         int q = (int)(v - S.pad_off[k]) - 2;
-        CellRef c{0, 0, 0, nullptr};
+        CellRef c{0, 0, 0, -1, 0};
         if (q >= 0 && q < n) {
             c.src = c0 + q;
         } else {
             int side = (q < 0) ? 0 : 1;
-            int sq = side_rule(P, side, q, n, 0.0, xcen(P, q), 0.0, S.tstart[k], c.mx, c.st);
+            int sq = side_rule(P, side, q, n, 0.0, xcen(P, q), 0.0, S.tstart[k], c.mx, c.fside, c.falt);
             c.src = (sq < 0) ? -1 : c0 + sq;
         }
         plus_record<1, R>(P, S, c, S.dt[k], L + (v - vlo), NT, 0);
@@ -826,15 +990,13 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
     FaceCount cnt{0, 0, 0, 0, 0};
     unsigned long long nfaces = 0;
     if (i <= P.nx && j < P.ny) {
-        const int idx[8] = {li(i - 1, j), li(i, j), li(i - 2, j), li(i + 1, j),
-                            li(i - 1, j - 1), li(i - 1, j + 1), li(i, j - 1), li(i, j + 1)};
-        face_2d<R, 0>(P, S, L, NT, idx, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
+        const int idx[2] = {li(i - 1, j), li(i, j)};
+        face_2d<R, 0>(P, S, L, NT, idx, 1, TX, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
         ++nfaces;
     }
     if (i < P.nx && j <= P.ny) {
-        const int idx[8] = {li(i, j - 1), li(i, j), li(i, j - 2), li(i, j + 1),
-                            li(i - 1, j - 1), li(i + 1, j - 1), li(i - 1, j), li(i + 1, j)};
-        face_2d<R, 1>(P, S, L, NT, idx, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
+        const int idx[2] = {li(i, j - 1), li(i, j)};
+        face_2d<R, 1>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
         ++nfaces;
     }
     stat_add(S.stats, ST_FACES, nfaces);
@@ -1005,6 +1167,7 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             pf[q] = A * pf[q] + Bc * (R)rho;
             pg[q] = A * pg[q] + Bc * (R)geq;
         }
+#pragma unroll 1
         for (int side = 0; side < 4; ++side) {
             const int axis = side >> 1;
             const int hi = side & 1;

@@ -70,6 +70,12 @@ def load(path: str | None = None):
     global _lib
     if _lib is not None:
         return _lib
+    # PyTorch ships its own HIP runtime under the same soname as ROCm's: load it first so
+    # that torch (device memory, streams) and libpond share one runtime in the process.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     path = path or LIB_PATH
     if not os.path.exists(path):
         raise ImportError(f"libpond.so not built ({path}); run __graft_entry__.build()")

@@ -24,7 +24,7 @@ TOL_FP32 = 1e-5
 
 
 def base_config(dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=0.2,
-                mu=1e-3, tol=TOL_PARITY, max_iter=100, limiter="vanleer",
+                mu=1e-3, tol=TOL_PARITY, max_iter=32, limiter="vanleer",
                 bc=("outflow", "outflow", "outflow", "outflow")):
     z = [[0.0] * 4 for _ in range(4)]
     return {
@@ -49,7 +49,7 @@ def cell_centres(cfg):
 
 
 def riemann_1d(left, right, nx=400, x0=0.0, x1=1.0, xi=0.5, gamma=1.4, cfl=0.5, mu=1e-3,
-               tol=TOL_PARITY, max_iter=100, bc=("outflow", "outflow")):
+               tol=TOL_PARITY, max_iter=32, bc=("outflow", "outflow")):
     """A 1D Riemann problem: state `left` = (rho, u, p) for x_c < xi, `right` beyond."""
     cfg = base_config(1, nx, x0=x0, x1=x1, gamma=gamma, cfl=cfl, mu=mu, tol=tol,
                       max_iter=max_iter, bc=(bc[0], bc[1], "outflow", "outflow"))
@@ -106,7 +106,7 @@ def rankine_hugoniot(rho1, p1, mach, gamma):
 
 
 def double_mach(nx=1920, ny=480, mach=10.0, gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL_PARITY,
-                max_iter=100):
+                max_iter=32):
     """Mach-10 shock meeting a 30 degree wall (Sec. IV.C.4): [0,4]x[0,1]; shock through
     (1/6, 0) inclined 60 degrees to the x axis; pre-shock (1.4, 0, 0, 1); post-shock
     from the normal-shock relations; bottom fixed post-shock for x < 1/6 and reflecting
@@ -146,7 +146,7 @@ def double_mach(nx=1920, ny=480, mach=10.0, gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL
 
 
 def shocked_interface(nx=2048, ny=512, mach=2.0, density_ratio=3.0, amplitude=0.05,
-                      gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_iter=100):
+                      gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_iter=32):
     """Shock of Mach `mach` in light gas (1, 0, 0, 1) hitting a heavy/light interface
     (density ratio 3) at x_I(y) = 1 + a cos(2 pi y) on [0,4]x[0,1], periodic in y;
     left fixed post-shock inflow, right outflow (stand-in for Sec. IV.C.3)."""
@@ -166,7 +166,7 @@ def shocked_interface(nx=2048, ny=512, mach=2.0, density_ratio=3.0, amplitude=0.
     return cfg, {"rho": rho, "ux": ux, "uy": np.zeros_like(rho), "p": p}
 
 
-def jet(nx=2048, ny=2048, gamma=5.0 / 3.0, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_iter=100,
+def jet(nx=2048, ny=2048, gamma=5.0 / 3.0, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_iter=32,
         width=0.1):
     """Mach-80 jet (Sec. IV.C.5): [0,1]x[-0.5,0.5]; ambient (0.5, 0, 0, 0.4127); left
     boundary fixed jet (5, 30, 0, 0.4127) for |y| <= width/2, fixed ambient elsewhere;
@@ -224,7 +224,7 @@ TUBES_SEED = 220305477
 
 
 def tube_batch(n_tubes=4096, seed=TUBES_SEED, len_lo=200, len_hi=4000, gamma=1.4, cfl=0.2,
-               mu=1e-3, tol=TOL_FP32, max_iter=100):
+               mu=1e-3, tol=TOL_FP32, max_iter=32):
     """Independent 1D shock tubes on [0,1] with the interface at 0.5 and outflow ends.
     Drawn in this order from PCG64(seed): cell count N ~ integers[len_lo, len_hi];
     density ratio 10^U[0,5); pressure ratio 10^U[0,6); Mach numbers M_L, M_R ~ U[-5,5];
