@@ -102,6 +102,7 @@ typedef struct {
     int64_t departure_out;          /* populations whose departure point left the cell */
     double t_min, t_max;            /* time of the instances after the call            */
     double dt_min, dt_max;          /* time steps of the last step over instances      */
+    int32_t failed_instances;       /* instances frozen after producing an invalid cell */
 } pond_stats;
 
 typedef struct pond_ctx pond_ctx;
@@ -152,6 +153,11 @@ pond_status pond_face_moments(const pond_ctx *ctx, double *Mf, double *Mg);
 /* Iteration count per face of the last step (negative: not converged). */
 pond_status pond_face_iters(const pond_ctx *ctx, int32_t *out);
 
+/* Per instance: nonzero once one of its steps produced a cell with rho <= 0, T <= 0 or a
+ * non-finite value. Such an instance is frozen (its later steps have dt = 0) while the
+ * other instances go on; pond_step reports POND_ENONPHYS for the call in which it failed. */
+pond_status pond_failed_instances(const pond_ctx *ctx, int32_t *flags);
+
 /* Time of each instance (host array of n_inst). */
 pond_status pond_time(const pond_ctx *ctx, double *t);
 
@@ -173,6 +179,60 @@ pond_status pond_autotune(pond_ctx *ctx);
  * Timing is recorded only after pond_enable_timing(ctx, 1). */
 pond_status pond_enable_timing(pond_ctx *ctx, int32_t on);
 pond_status pond_kernel_times(const pond_ctx *ctx, double *out4);
+
+
+/* ---------------------------------------------------------------------------------------
+ * Learned seed of the face-frame iteration (not part of the paper's method: it only
+ * replaces the predictor frame lambda_0 of Sec. III.B.3 for faces that needed
+ * `hard_iters` or more iterations in the previous step; the iteration still runs to the
+ * same tolerance). A 2 x 64 hidden-layer ReLU MLP, BF16 MFMA with FP32 accumulation,
+ * FP32 master weights trained with Adam. Feature and target layouts are described in
+ * pond_mlp_features. All device pointers are caller-owned (e.g. torch tensors) and must
+ * stay valid during the call; calls are issued on the stream of the context or on `stream`.
+ * --------------------------------------------------------------------------------------- */
+typedef struct pond_mlp pond_mlp;
+
+typedef struct {
+    int32_t epochs;     /* passes over the data                         */
+    int32_t batch;      /* samples per Adam step (multiple of 32)       */
+    float lr;           /* Adam step size                               */
+    float beta1, beta2; /* Adam moment decay rates                      */
+    float eps;          /* Adam denominator offset                      */
+} pond_train_cfg;
+
+/* number of FP32 parameters: W1 (64x64, out x in), b1 (64), W2 (64x64), b2 (64),
+ * W3 (3x64), b3 (3) */
+int32_t pond_mlp_nparams(void);
+/* Create a network with the given host parameters (pond_mlp_nparams values), or, if
+ * params is NULL, with He-normal weights from a generator seeded by `seed` and zero biases. */
+pond_status pond_mlp_create(const float *params, uint64_t seed, pond_mlp **out);
+pond_status pond_mlp_get(const pond_mlp *m, float *params);
+pond_status pond_mlp_set(pond_mlp *m, const float *params);
+/* Inference: dev_Y[n][4] (outputs in columns 0..2) from dev_X[n][64] (FP32, row-major). */
+pond_status pond_mlp_forward(pond_mlp *m, const float *dev_X, int64_t n, float *dev_Y, void *stream);
+/* Loss (1/n) sum (y - t)^2 over samples and the 3 outputs, and its gradient w.r.t. the
+ * parameters (host array, pond_mlp_nparams values); dev_T[n][4] targets (columns 0..2). */
+pond_status pond_mlp_grad(pond_mlp *m, const float *dev_X, const float *dev_T, int64_t n,
+                          float *grad, float *loss);
+/* Adam training over consecutive batches of (dev_X, dev_T); loss_out (may be NULL) gets
+ * the mean batch loss of every epoch (cfg->epochs values). */
+pond_status pond_mlp_train(pond_mlp *m, const float *dev_X, const float *dev_T, int64_t n,
+                           const pond_train_cfg *cfg, float *loss_out);
+void pond_mlp_free(pond_mlp *m);
+
+/* Features of every face at the context's current state (call before pond_step):
+ * dev_X[nfaces][64], dev_ref[nfaces][4] = (u_n, u_t, sqrt T, T) of the centre cell.
+ * Features: 3x3 cells centred on the face's lower neighbour, each as log(rho/rho_c),
+ * (u_n - u_cn)/s_c, (u_t - u_ct)/s_c, log(T/T_c); then the previous face frame in the same
+ * form and a flag (1 if the face has one); zeros up to 64. */
+pond_status pond_mlp_features(pond_ctx *ctx, float *dev_X, float *dev_ref);
+/* Targets of every face after a step: the face frames normalized by dev_ref,
+ * ((u_n - u_cn)/s_c, (u_t - u_ct)/s_c, log(T/T_c)), minus the normalized previous frame
+ * (features 36..38 of dev_X) where the face had one (feature 39 = 1); column 3 is 0.
+ * dev_X and dev_ref are the arrays pond_mlp_features filled before the step. */
+pond_status pond_mlp_targets(pond_ctx *ctx, const float *dev_X, const float *dev_ref, float *dev_T);
+/* Attach a copy of the network to a context whose seed_mode is POND_SEED_MLP. */
+pond_status pond_load_mlp(pond_ctx *ctx, const pond_mlp *m, int32_t hard_iters);
 
 void pond_free(pond_ctx *ctx);
 const char *pond_strerror(pond_status s);

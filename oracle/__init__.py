@@ -235,9 +235,9 @@ class Sim:
 
     def __del__(self):
         h = getattr(self, "_h", None)
-        if h:
-            _load().orc_destroy(h)
-            self._h = None
+        if h and _lib is not None:
+            _lib.orc_destroy(h)
+        self._h = None
 
     def step(self, t_end: float = float("inf")) -> int:
         st = _Stats()

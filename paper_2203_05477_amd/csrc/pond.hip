@@ -36,6 +36,7 @@ struct pond_ctx {
     double *t = nullptr, *tstart = nullptr, *dt = nullptr, *dxk = nullptr;
     unsigned long long *vmax = nullptr, *stats = nullptr;
     int *err = nullptr;
+    int *inst_err = nullptr;
     double *scratch = nullptr; // read-out staging (4 x ncell doubles)
     // host mirrors
     std::vector<int64_t> h_cell_off;
@@ -92,6 +93,7 @@ State<R> state_of(pond_ctx *c)
     S.vmax = c->vmax;
     S.stats = c->stats;
     S.err = c->err;
+    S.inst_err = c->inst_err;
     return S;
 }
 
@@ -238,7 +240,7 @@ void init_launch(pond_ctx *c, const double *dprim)
 void free_all(pond_ctx *c)
 {
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
-                    c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->scratch};
+                    c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -338,6 +340,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     alloc((void **)&c->vmax, sizeof(unsigned long long) * 2 * P.n_inst);
     alloc((void **)&c->stats, sizeof(unsigned long long) * ST_N);
     alloc((void **)&c->err, sizeof(int));
+    alloc((void **)&c->inst_err, sizeof(int) * P.n_inst);
     alloc((void **)&c->scratch, sizeof(double) * 4 * std::max(n, nf));
     if (P.n_inst > 1) {
         alloc((void **)&c->cell_inst, sizeof(int) * n);
@@ -373,7 +376,8 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
               hip_ok(hipMemcpy(c->dt, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->vmax, zv.data(), sizeof(unsigned long long) * zv.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->stats, zs.data(), sizeof(unsigned long long) * ST_N, hipMemcpyHostToDevice)) &&
-              hip_ok(hipMemset(c->err, 0, sizeof(int)));
+              hip_ok(hipMemset(c->err, 0, sizeof(int))) &&
+              hip_ok(hipMemset(c->inst_err, 0, sizeof(int) * P.n_inst));
     if (up && P.n_inst > 1) {
         std::vector<int> ci(n), fi(nf);
         for (int k = 0; k < P.n_inst; ++k) {
@@ -462,6 +466,9 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         st->t_max = *std::max_element(ht.begin(), ht.end());
         st->dt_min = *std::min_element(hdt.begin(), hdt.end());
         st->dt_max = *std::max_element(hdt.begin(), hdt.end());
+        std::vector<int> fe(c->P.n_inst);
+        HIPCHK(hipMemcpy(fe.data(), c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost));
+        st->failed_instances = (int32_t)std::count_if(fe.begin(), fe.end(), [](int v) { return v != 0; });
     }
     if (herr & ERR_NONPHYS) return POND_ENONPHYS;
     if ((c->cfg.flags & POND_FLAG_STRICT) && hs[ST_NONCONV]) return POND_ENOCONV;
@@ -625,6 +632,14 @@ pond_status pond_face_iters(const pond_ctx *c, int32_t *out)
     return POND_OK;
 }
 
+pond_status pond_failed_instances(const pond_ctx *c, int32_t *flags)
+{
+    if (!c || !flags) return POND_EINVAL;
+    HIPCHK(hipMemcpyAsync(flags, c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
 pond_status pond_time(const pond_ctx *c, double *t)
 {
     if (!c || !t) return POND_EINVAL;
@@ -762,6 +777,266 @@ void pond_free(pond_ctx *c)
     for (auto &e : c->evs) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
     delete c;
+}
+
+} // extern "C"
+
+// ---------------------------------------------------------------------------------------
+// learned seed
+// ---------------------------------------------------------------------------------------
+
+struct pond_mlp {
+    MlpDevice dev;
+    hipStream_t stream = nullptr;
+};
+
+namespace {
+
+uint64_t splitmix64(uint64_t &x)
+{
+    uint64_t z = (x += 0x9e3779b97f4a7c15ull);
+    z = (z ^ (z >> 30)) * 0xbf58476d1ce4e5b9ull;
+    z = (z ^ (z >> 27)) * 0x94d049bb133111ebull;
+    return z ^ (z >> 31);
+}
+
+double unit_open(uint64_t &x) { return ((splitmix64(x) >> 11) + 0.5) * (1.0 / 9007199254740992.0); }
+
+void he_init(std::vector<float> &p, uint64_t seed)
+{
+    std::fill(p.begin(), p.end(), 0.0f);
+    uint64_t st = seed;
+    auto fill = [&](int off, int rows, int cols) {
+        double sd = std::sqrt(2.0 / cols);
+        for (int i = 0; i < rows * cols; ++i) {
+            double u1 = unit_open(st), u2 = unit_open(st);
+            p[off + i] = (float)(sd * std::sqrt(-2.0 * std::log(u1)) * std::cos(6.283185307179586 * u2));
+        }
+    };
+    fill(OFF_W1, MLP_H, MLP_NF);  // only the used inputs get weights; padding columns stay 0
+    for (int o = MLP_H - 1; o >= 0; --o)
+        for (int k = MLP_IN - 1; k >= 0; --k) p[OFF_W1 + o * MLP_IN + k] = (k < MLP_NF) ? p[OFF_W1 + o * MLP_NF + k] : 0.0f;
+    fill(OFF_W2, MLP_H, MLP_H);
+    fill(OFF_W3, MLP_OUT, MLP_H);
+}
+
+pond_status mlp_alloc(MlpDevice &M, int npartial)
+{
+    bool ok = hipMalloc(&M.master, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&M.adam_m, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&M.adam_v, sizeof(float) * MLP_NPARAM) == hipSuccess &&
+              hipMalloc(&M.wbf, sizeof(__bf16) * (2 * MLP_H * MLP_IN + 16 * MLP_H)) == hipSuccess &&
+              hipMalloc(&M.partial, sizeof(float) * (size_t)npartial * (MLP_NPARAM + 1)) == hipSuccess &&
+              hipMalloc(&M.grad, sizeof(float) * (MLP_NPARAM + 1)) == hipSuccess;
+    M.npartial = npartial;
+    if (!ok) {
+        mlp_free(M);
+        return POND_ENOMEM;
+    }
+    return POND_OK;
+}
+
+pond_status mlp_upload(MlpDevice &M, const float *params, hipStream_t st)
+{
+    HIPCHK(hipMemcpyAsync(M.master, params, sizeof(float) * MLP_NPARAM, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemsetAsync(M.adam_m, 0, sizeof(float) * MLP_NPARAM, st));
+    HIPCHK(hipMemsetAsync(M.adam_v, 0, sizeof(float) * MLP_NPARAM, st));
+    mlp_pack_kernel<<<blocks(MLP_H * MLP_IN, 256), 256, 0, st>>>(M.master, M.wbf);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(st));
+    M.adam_t = 0;
+    M.ready = true;
+    return POND_OK;
+}
+
+int train_grid(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 31) / 32, cap)); }
+
+} // namespace
+
+extern "C" {
+
+int32_t pond_mlp_nparams(void) { return MLP_NPARAM; }
+
+pond_status pond_mlp_create(const float *params, uint64_t seed, pond_mlp **out)
+{
+    if (!out) return POND_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return POND_EDEVICE;
+    pond_mlp *m = new (std::nothrow) pond_mlp();
+    if (!m) return POND_ENOMEM;
+    if (hipStreamCreate(&m->stream) != hipSuccess) {
+        delete m;
+        return POND_EDEVICE;
+    }
+    pond_status s = mlp_alloc(m->dev, 1024);
+    if (s != POND_OK) {
+        pond_mlp_free(m);
+        return s;
+    }
+    std::vector<float> p(MLP_NPARAM);
+    if (params)
+        std::copy(params, params + MLP_NPARAM, p.begin());
+    else
+        he_init(p, seed);
+    s = mlp_upload(m->dev, p.data(), m->stream);
+    if (s != POND_OK) {
+        pond_mlp_free(m);
+        return s;
+    }
+    *out = m;
+    return POND_OK;
+}
+
+pond_status pond_mlp_get(const pond_mlp *m, float *params)
+{
+    if (!m || !params) return POND_EINVAL;
+    HIPCHK(hipMemcpyAsync(params, m->dev.master, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    return POND_OK;
+}
+
+pond_status pond_mlp_set(pond_mlp *m, const float *params)
+{
+    if (!m || !params) return POND_EINVAL;
+    return mlp_upload(m->dev, params, m->stream);
+}
+
+pond_status pond_mlp_forward(pond_mlp *m, const float *X, int64_t n, float *Y, void *stream)
+{
+    if (!m || !X || !Y || n < 0) return POND_EINVAL;
+    hipStream_t st = stream ? (hipStream_t)stream : m->stream;
+    if (n == 0) return POND_OK;
+    unsigned grid = (unsigned)std::min<int64_t>((n + 15) / 16, 4096);
+    mlp_forward_kernel<<<grid, 64, 0, st>>>(m->dev.wbf, m->dev.master, X, n, Y);
+    HIPCHK(hipGetLastError());
+    if (!stream) HIPCHK(hipStreamSynchronize(st));
+    return POND_OK;
+}
+
+pond_status pond_mlp_grad(pond_mlp *m, const float *X, const float *T, int64_t n, float *grad, float *loss)
+{
+    if (!m || !X || !T || !grad || n < 1) return POND_EINVAL;
+    int nw = train_grid(n, m->dev.npartial);
+    mlp_train_kernel<<<nw, 64, 0, m->stream>>>(m->dev.wbf, m->dev.master, X, T, n, m->dev.partial);
+    mlp_reduce_kernel<<<blocks(MLP_NPARAM + 1, 256), 256, 0, m->stream>>>(m->dev.partial, nw, m->dev.grad);
+    HIPCHK(hipGetLastError());
+    std::vector<float> h(MLP_NPARAM + 1);
+    HIPCHK(hipMemcpyAsync(h.data(), m->dev.grad, sizeof(float) * (MLP_NPARAM + 1), hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
+    std::copy(h.begin(), h.begin() + MLP_NPARAM, grad);
+    if (loss) *loss = h[MLP_NPARAM];
+    return POND_OK;
+}
+
+pond_status pond_mlp_train(pond_mlp *m, const float *X, const float *T, int64_t n, const pond_train_cfg *cfg,
+                           float *loss_out)
+{
+    if (!m || !X || !T || !cfg || n < 1 || cfg->epochs < 0 || cfg->batch < 32 || cfg->batch % 32) return POND_EINVAL;
+    MlpDevice &M = m->dev;
+    const int64_t B = cfg->batch;
+    std::vector<float> losses;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        int nb = 0;
+        // each batch's loss lands in grad[NPARAM]; collected on the device side per batch
+        std::vector<float> hl;
+        float *dloss = nullptr;
+        int64_t nbatches = (n + B - 1) / B;
+        HIPCHK(hipMalloc(&dloss, sizeof(float) * nbatches));
+        for (int64_t b0 = 0; b0 < n; b0 += B) {
+            int64_t nbn = std::min<int64_t>(B, n - b0);
+            int nw = train_grid(nbn, M.npartial);
+            mlp_train_kernel<<<nw, 64, 0, m->stream>>>(M.wbf, M.master, X + b0 * MLP_IN, T + b0 * 4, nbn, M.partial);
+            mlp_reduce_kernel<<<blocks(MLP_NPARAM + 1, 256), 256, 0, m->stream>>>(M.partial, nw, M.grad);
+            M.adam_t += 1;
+            mlp_adam_kernel<<<blocks(MLP_NPARAM, 256), 256, 0, m->stream>>>(M.master, M.adam_m, M.adam_v, M.grad, M.wbf,
+                                                                            cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, M.adam_t);
+            HIPCHK(hipMemcpyAsync(dloss + nb, M.grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToDevice, m->stream));
+            ++nb;
+        }
+        HIPCHK(hipGetLastError());
+        hl.resize(nb);
+        HIPCHK(hipMemcpyAsync(hl.data(), dloss, sizeof(float) * nb, hipMemcpyDeviceToHost, m->stream));
+        HIPCHK(hipStreamSynchronize(m->stream));
+        (void)hipFree(dloss);
+        double sum = 0.0;
+        for (float v : hl) sum += v;
+        losses.push_back((float)(sum / std::max(nb, 1)));
+    }
+    if (loss_out) std::copy(losses.begin(), losses.end(), loss_out);
+    return POND_OK;
+}
+
+void pond_mlp_free(pond_mlp *m)
+{
+    if (!m) return;
+    if (m->stream) (void)hipStreamSynchronize(m->stream);
+    mlp_free(m->dev);
+    if (m->stream) (void)hipStreamDestroy(m->stream);
+    delete m;
+}
+
+pond_status pond_mlp_features(pond_ctx *c, float *X, float *ref)
+{
+    if (!c || !X || !ref) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    if (c->D == 1) {
+        if (c->precision == POND_FP64)
+            mlp_features_kernel<1, double><<<blocks(nf, 128), 128, 0, c->stream>>>(c->P, state_of<double>(c), X, ref);
+        else
+            mlp_features_kernel<1, float><<<blocks(nf, 128), 128, 0, c->stream>>>(c->P, state_of<float>(c), X, ref);
+    } else {
+        if (c->precision == POND_FP64)
+            mlp_features_kernel<2, double><<<blocks(nf, 128), 128, 0, c->stream>>>(c->P, state_of<double>(c), X, ref);
+        else
+            mlp_features_kernel<2, float><<<blocks(nf, 128), 128, 0, c->stream>>>(c->P, state_of<float>(c), X, ref);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
+pond_status pond_mlp_targets(pond_ctx *c, const float *X, const float *ref, float *T)
+{
+    if (!c || !X || !ref || !T) return POND_EINVAL;
+    const int64_t nf = c->P.nface;
+    if (c->D == 1) {
+        if (c->precision == POND_FP64)
+            mlp_targets_kernel<1, double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(c), X, ref, T);
+        else
+            mlp_targets_kernel<1, float><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<float>(c), X, ref, T);
+    } else {
+        if (c->precision == POND_FP64)
+            mlp_targets_kernel<2, double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(c), X, ref, T);
+        else
+            mlp_targets_kernel<2, float><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<float>(c), X, ref, T);
+    }
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    return POND_OK;
+}
+
+pond_status pond_load_mlp(pond_ctx *c, const pond_mlp *m, int32_t hard_iters)
+{
+    if (!c || !m || !m->dev.ready || hard_iters < 1) return POND_EINVAL;
+    MlpDevice &M = c->mlp;
+    if (!M.master) {
+        pond_status s = mlp_alloc(M, 1);
+        if (s != POND_OK) return s;
+        if (hipMalloc(&M.list, sizeof(int) * c->P.nface) != hipSuccess ||
+            hipMalloc(&M.count, sizeof(int)) != hipSuccess) {
+            mlp_free(M);
+            return POND_ENOMEM;
+        }
+    }
+    HIPCHK(hipStreamSynchronize(m->stream));
+    HIPCHK(hipMemcpyAsync(M.master, m->dev.master, sizeof(float) * MLP_NPARAM, hipMemcpyDeviceToDevice, c->stream));
+    mlp_pack_kernel<<<blocks(MLP_H * MLP_IN, 256), 256, 0, c->stream>>>(M.master, M.wbf);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipStreamSynchronize(c->stream));
+    M.hard_iters = hard_iters;
+    M.ready = true;
+    return POND_OK;
 }
 
 } // extern "C"

@@ -55,6 +55,7 @@ struct State {
     unsigned long long *vmax;  // 2 x n_inst (slot by step parity)
     unsigned long long *stats; // ST_N counters
     int *err;
+    int *inst_err;             // per instance: nonzero once a step produced an invalid cell
 };
 
 template <int D>
@@ -125,7 +126,7 @@ __global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
     double rate = __longlong_as_double((long long)S.vmax[slot * P.n_inst + k]);
     double t = S.t[k];
     double dt = P.cfl / rate;
-    if (!(rate > 0.0)) dt = 0.0;
+    if (!(rate > 0.0) || S.inst_err[k]) dt = 0.0; // a failed instance stays frozen
     if (t + dt > t_end) dt = t_end - t;
     if (!(dt > 0.0)) dt = 0.0;
     S.tstart[k] = t;
@@ -1217,7 +1218,10 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
     double ke = un[0] * un[0] + un[1] * un[1];
     double Tn = (Un[D + 1] / rn - 0.5 * ke) / P.Cv;
     bool ok = (rn > 0.0) && (Tn > 0.0) && isfinite(Tn) && isfinite(ke);
-    if (!ok) atomicOr(S.err, ERR_NONPHYS);
+    if (!ok) {
+        atomicOr(S.err, ERR_NONPHYS);
+        atomicOr(S.inst_err + k, 1);
+    }
     double sn = sqrt(fabs(Tn));
     // reframe: non-equilibrium coefficients of the updated populations in the new
     // co-moving frame (Sec. II.C with u' = u, T' = T)

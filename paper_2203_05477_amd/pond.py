@@ -54,10 +54,16 @@ class Stats(ctypes.Structure):
         ("departure_out", ctypes.c_int64),
         ("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
+        ("failed_instances", ctypes.c_int32),
     ]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class TrainCfg(ctypes.Structure):
+    _fields_ = [("epochs", ctypes.c_int32), ("batch", ctypes.c_int32), ("lr", ctypes.c_float),
+                ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float)]
 
 
 _lib = None
@@ -94,6 +100,7 @@ def load(path: str | None = None):
         "pond_face_moments": (S, [_P, _D, _D]),
         "pond_face_iters": (S, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "pond_time": (S, [_P, _D]),
+        "pond_failed_instances": (S, [_P, ctypes.POINTER(ctypes.c_int32)]),
         "pond_set_stream": (S, [_P, _P]),
         "pond_set_tiles": (S, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32]),
         "pond_get_tiles": (S, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
@@ -102,6 +109,19 @@ def load(path: str | None = None):
         "pond_enable_timing": (S, [_P, ctypes.c_int32]),
         "pond_kernel_times": (S, [_P, _D]),
         "pond_free": (None, [_P]),
+        "pond_mlp_nparams": (ctypes.c_int32, []),
+        "pond_mlp_create": (S, [ctypes.POINTER(ctypes.c_float), ctypes.c_uint64, ctypes.POINTER(_P)]),
+        "pond_mlp_get": (S, [_P, ctypes.POINTER(ctypes.c_float)]),
+        "pond_mlp_set": (S, [_P, ctypes.POINTER(ctypes.c_float)]),
+        "pond_mlp_forward": (S, [_P, _P, ctypes.c_int64, _P, _P]),
+        "pond_mlp_grad": (S, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(ctypes.c_float),
+                              ctypes.POINTER(ctypes.c_float)]),
+        "pond_mlp_train": (S, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
+                               ctypes.POINTER(ctypes.c_float)]),
+        "pond_mlp_free": (None, [_P]),
+        "pond_mlp_features": (S, [_P, _P, _P]),
+        "pond_mlp_targets": (S, [_P, _P, _P, _P]),
+        "pond_load_mlp": (S, [_P, _P, ctypes.c_int32]),
         "pond_strerror": (ctypes.c_char_p, [ctypes.c_int]),
         "pond_abi_version": (ctypes.c_int32, []),
     }
@@ -117,9 +137,13 @@ def exported_symbols():
     """Names the header declares (checked against the library by the CPU tests)."""
     return ["pond_init", "pond_step", "pond_moments", "pond_moments_device", "pond_conserved",
             "pond_populations", "pond_nfaces", "pond_face_frames", "pond_set_face_frames",
-            "pond_face_moments", "pond_face_iters", "pond_time", "pond_set_stream",
+            "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
+            "pond_set_stream",
             "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_enable_timing",
-            "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version"]
+            "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
+            "pond_mlp_nparams", "pond_mlp_create", "pond_mlp_get", "pond_mlp_set",
+            "pond_mlp_forward", "pond_mlp_grad", "pond_mlp_train", "pond_mlp_free",
+            "pond_mlp_features", "pond_mlp_targets", "pond_load_mlp"]
 
 
 def _strerror(s):
@@ -200,9 +224,9 @@ class Context:
 
     def close(self):
         h = getattr(self, "_h", None)
-        if h:
-            load().pond_free(h)
-            self._h = None
+        if h and _lib is not None:
+            _lib.pond_free(h)
+        self._h = None
 
     __del__ = close
 
@@ -271,6 +295,13 @@ class Context:
             raise PondError(rc, "pond_face_iters")
         return out
 
+    def failed_instances(self):
+        out = np.zeros(self.n_inst, dtype=np.int32)
+        rc = load().pond_failed_instances(self._h, out.ctypes.data_as(ctypes.POINTER(ctypes.c_int32)))
+        if rc != OK:
+            raise PondError(rc, "pond_failed_instances")
+        return out != 0
+
     def time(self):
         t = np.zeros(self.n_inst)
         rc = load().pond_time(self._h, _ptr(t))
@@ -306,3 +337,91 @@ class Context:
         out = np.zeros(4)
         load().pond_kernel_times(self._h, _ptr(out))
         return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3]}
+
+
+    # ---- learned seed ----
+    def mlp_features(self, X_ptr: int, ref_ptr: int):
+        rc = load().pond_mlp_features(self._h, ctypes.c_void_p(X_ptr), ctypes.c_void_p(ref_ptr))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_features")
+
+    def mlp_targets(self, X_ptr: int, ref_ptr: int, T_ptr: int):
+        rc = load().pond_mlp_targets(self._h, ctypes.c_void_p(X_ptr), ctypes.c_void_p(ref_ptr),
+                                     ctypes.c_void_p(T_ptr))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_targets")
+
+    def load_mlp(self, mlp: "Mlp", hard_iters: int = 2):
+        rc = load().pond_load_mlp(self._h, mlp._h, int(hard_iters))
+        if rc != OK:
+            raise PondError(rc, "pond_load_mlp")
+
+
+def _fptr(a):
+    return a.ctypes.data_as(ctypes.POINTER(ctypes.c_float))
+
+
+class Mlp:
+    """The seed network (BF16 MFMA kernels, FP32 master weights). Device arrays are passed
+    as raw device pointers (e.g. torch.Tensor.data_ptr())."""
+
+    def __init__(self, params=None, seed: int = 0):
+        lib = load()
+        self.nparams = int(lib.pond_mlp_nparams())
+        h = _P()
+        if params is not None:
+            p = np.ascontiguousarray(np.asarray(params, dtype=np.float32)).ravel()
+            if p.size != self.nparams:
+                raise ValueError("wrong parameter count")
+            rc = lib.pond_mlp_create(_fptr(p), ctypes.c_uint64(seed), ctypes.byref(h))
+        else:
+            rc = lib.pond_mlp_create(None, ctypes.c_uint64(seed), ctypes.byref(h))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_create")
+        self._h = h
+
+    def close(self):
+        h = getattr(self, "_h", None)
+        if h and _lib is not None:
+            _lib.pond_mlp_free(h)
+        self._h = None
+
+    __del__ = close
+
+    def params(self):
+        p = np.zeros(self.nparams, dtype=np.float32)
+        rc = load().pond_mlp_get(self._h, _fptr(p))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_get")
+        return p
+
+    def set_params(self, params):
+        p = np.ascontiguousarray(np.asarray(params, dtype=np.float32)).ravel()
+        rc = load().pond_mlp_set(self._h, _fptr(p))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_set")
+
+    def forward(self, X_ptr: int, n: int, Y_ptr: int, stream: int | None = None):
+        rc = load().pond_mlp_forward(self._h, ctypes.c_void_p(X_ptr), int(n), ctypes.c_void_p(Y_ptr),
+                                     ctypes.c_void_p(stream or 0))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_forward")
+
+    def grad(self, X_ptr: int, T_ptr: int, n: int):
+        g = np.zeros(self.nparams, dtype=np.float32)
+        loss = ctypes.c_float()
+        rc = load().pond_mlp_grad(self._h, ctypes.c_void_p(X_ptr), ctypes.c_void_p(T_ptr), int(n),
+                                  _fptr(g), ctypes.byref(loss))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_grad")
+        return g, loss.value
+
+    def train(self, X_ptr: int, T_ptr: int, n: int, epochs=10, batch=4096, lr=1e-3,
+              beta1=0.9, beta2=0.999, eps=1e-8):
+        cfg = TrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps))
+        out = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        rc = load().pond_mlp_train(self._h, ctypes.c_void_p(X_ptr), ctypes.c_void_p(T_ptr), int(n),
+                                   ctypes.byref(cfg), _fptr(out))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_train")
+        return out[: int(epochs)]

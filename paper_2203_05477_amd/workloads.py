@@ -224,10 +224,11 @@ TUBES_SEED = 220305477
 
 
 def tube_batch(n_tubes=4096, seed=TUBES_SEED, len_lo=200, len_hi=4000, gamma=1.4, cfl=0.2,
-               mu=1e-3, tol=TOL_FP32, max_iter=32):
+               mu=1e-3, tol=TOL_FP32, max_iter=32, rho_decades=5.0, p_decades=6.0, mach=5.0):
     """Independent 1D shock tubes on [0,1] with the interface at 0.5 and outflow ends.
     Drawn in this order from PCG64(seed): cell count N ~ integers[len_lo, len_hi];
-    density ratio 10^U[0,5); pressure ratio 10^U[0,6); Mach numbers M_L, M_R ~ U[-5,5];
+    density ratio 10^U[0,rho_decades); pressure ratio 10^U[0,p_decades); Mach numbers
+    M_L, M_R ~ U[-mach, mach] (defaults 5, 6 and 5);
     two fair coins for the dense and the high-pressure side. The dense side has
     rho = 1, the other 1/ratio; the high side p = 1, the other 1/ratio;
     u = M sqrt(gamma p / rho). Tubes whose exact solution would open a vacuum
@@ -236,9 +237,9 @@ def tube_batch(n_tubes=4096, seed=TUBES_SEED, len_lo=200, len_hi=4000, gamma=1.4
     lens, states = [], []
     while len(lens) < n_tubes:
         N = int(rng.integers(len_lo, len_hi, endpoint=True))
-        r_rho = 10.0 ** rng.uniform(0.0, 5.0)
-        r_p = 10.0 ** rng.uniform(0.0, 6.0)
-        ML, MR = rng.uniform(-5.0, 5.0), rng.uniform(-5.0, 5.0)
+        r_rho = 10.0 ** rng.uniform(0.0, rho_decades)
+        r_p = 10.0 ** rng.uniform(0.0, p_decades)
+        ML, MR = rng.uniform(-mach, mach), rng.uniform(-mach, mach)
         dense_left = rng.integers(0, 2) == 1
         high_left = rng.integers(0, 2) == 1
         rhoL, rhoR = (1.0, 1.0 / r_rho) if dense_left else (1.0 / r_rho, 1.0)

@@ -116,3 +116,18 @@ def test_periodic_conservation_gpu(orc, precision):
     U1 = g.conserved().sum(axis=1)
     scale = np.abs(g.conserved()).sum(axis=1)
     assert np.all(np.abs(U1 - U0) <= 1e-13 * scale)
+
+
+def test_2d_tiles_bitwise_identical(orc):
+    """Every 2D tile shape gives bitwise-identical FP64 results (the LDS halo is complete)."""
+    from paper_2203_05477_amd import pond
+
+    cfg, f = W.double_mach(70, 30)
+    outs = []
+    for bx, by in ((8, 8), (16, 16), (32, 2), (64, 4)):
+        g = pond.Context(cfg, f, precision="fp64")
+        g.set_tiles(bx, by, 256)
+        g.step(12)
+        outs.append((g.conserved(), g.face_frames()))
+    for U, F in outs[1:]:
+        assert np.array_equal(U, outs[0][0]) and np.array_equal(F, outs[0][1])
