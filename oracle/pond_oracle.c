@@ -809,6 +809,24 @@ int orc_step(orc_sim *s, double t_end, orc_stats *st)
                 rate = fmax(rate, r);
             }
         }
+    /* the prescribed boundary states stream into the domain through the boundary faces,
+     * so their particle speeds belong to the same maximum */
+    for (int side = 0; side < 2 * D; ++side) {
+        int kind = s->cfg.bc[side];
+        const double *used[2] = {NULL, NULL};
+        if (kind == ORC_BC_FIXED || kind == ORC_BC_SPLIT_FIXED_REFLECT)
+            used[0] = s->cfg.bc_state[side];
+        if (kind == ORC_BC_FIXED_WINDOW || kind == ORC_BC_MOVING_SHOCK) {
+            used[0] = s->cfg.bc_state[side];
+            used[1] = s->cfg.bc_alt[side];
+        }
+        for (int k = 0; k < 2; ++k) {
+            if (!used[k]) continue;
+            double T = used[k][3] / used[k][0];
+            for (int a = 0; a < D; ++a)
+                rate = fmax(rate, (fabs(used[k][1 + a]) + sqrt(T / TL) * cmax) / s->dx[a]);
+        }
+    }
     double dt = s->cfg.cfl / rate;
     if (s->t + dt > t_end) dt = t_end - s->t;
 

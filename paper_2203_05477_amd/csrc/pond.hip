@@ -296,6 +296,21 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
             P.bc_param[s][q] = cfg->bc_param[s][q];
         }
     }
+    // fastest particle speed, per axis, of the states the boundary conditions prescribe
+    for (int s = 0; s < 2 * cfg->dim; ++s) {
+        const double *used[2] = {nullptr, nullptr};
+        if (P.bc[s] == BC_FIXED || P.bc[s] == BC_SPLIT) used[0] = cfg->bc_state[s];
+        if (P.bc[s] == BC_FIXED_WINDOW || P.bc[s] == BC_MOVING) {
+            used[0] = cfg->bc_state[s];
+            used[1] = cfg->bc_alt[s];
+        }
+        for (const double *st : used) {
+            if (!st) continue;
+            double T = st[3] / st[0];
+            for (int a = 0; a < cfg->dim; ++a)
+                P.bc_speed[a] = std::max(P.bc_speed[a], std::fabs(st[1 + a]) + std::sqrt(T) * CMAX);
+        }
+    }
     // per-instance layout (1D tubes concatenated; each tube spans [x0, x1])
     std::vector<int64_t> coff(P.n_inst + 1, 0), poff(P.n_inst + 1, 0);
     std::vector<int> len(P.n_inst);

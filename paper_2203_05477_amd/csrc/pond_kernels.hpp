@@ -37,6 +37,7 @@ struct Params {
     int limiter, max_iter;
     int bc[4];
     double bc_state[4][4], bc_alt[4][4], bc_param[4][4];
+    double bc_speed[2]; // per axis: fastest particle speed of the prescribed boundary states
     int64_t ncell, nface, nfx;
 };
 
@@ -124,6 +125,10 @@ __global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
     int k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= P.n_inst) return;
     double rate = __longlong_as_double((long long)S.vmax[slot * P.n_inst + k]);
+    // boundary states enter through the boundary faces: their speeds bound dt as well
+    double dxa = S.dxk ? S.dxk[k] : P.dx;
+    rate = fmax(rate, P.bc_speed[0] / dxa);
+    if (P.dim == 2) rate = fmax(rate, P.bc_speed[1] / P.dy);
     double t = S.t[k];
     double dt = P.cfl / rate;
     if (!(rate > 0.0) || S.inst_err[k]) dt = 0.0; // a failed instance stays frozen

@@ -202,3 +202,21 @@ def test_exact_riemann_solver_relations():
     # rarefaction: isentropic
     fan = (xi > -1.1) & (xi < 0.0) & (np.abs(u) > 1e-3) & (u < us - 1e-3)
     assert np.allclose(p[fan] / r[fan] ** g, left[2] / left[0] ** g, rtol=1e-10)
+
+
+def test_time_step_includes_the_prescribed_boundary_states(orc):
+    """CFL = max over every population that crosses a face of |v_a| dt / dx_a (Sec. IV):
+    at t = 0 the jet's interior is ambient gas at rest, and the fastest populations are
+    those the fixed jet inflow sends through the left boundary, so
+    dt = CFL dx / (30 + sqrt(T_jet) c_max) with c_max = sqrt(3 + sqrt 6)."""
+    cfg, f = W.jet(32, 32, tol=1e-10)
+    s = _sim(orc, cfg, f)
+    s.step()
+    cmax = math.sqrt(3.0 + math.sqrt(6.0))
+    dx = 1.0 / 32
+    assert s.last["dt"] == pytest.approx(0.2 * dx / (30.0 + math.sqrt(0.4127 / 5.0) * cmax), rel=1e-14)
+    # a closed periodic box has no boundary states: dt follows the interior alone
+    cfg, f = W.uniform(2, 8, 8, rho=1.0, u=(0.3, -0.2), p=0.7, tol=1e-13)
+    s = _sim(orc, cfg, f)
+    s.step()
+    assert s.last["dt"] == pytest.approx(0.2 / 8 / (0.3 + math.sqrt(0.7) * cmax), rel=1e-14)
