@@ -34,6 +34,9 @@
  *    cells next to the face; later steps: the face frame of the previous step;
  *  - the face equilibrium used to recover phi from phi-bar is the co-moving
  *    equilibrium of the face's final frame, applied to the moments;
+ *  - the time step: CFL = max |v_ia| dt/dx_a over the populations of every cell and of
+ *    every state a boundary condition prescribes (they enter through boundary faces),
+ *    recomputed every step from the cell frames at its start;
  *  - two ghost layers; x-ghosts are filled for the interior rows first, then the
  *    y-ghosts of every column (so corner ghosts take the y rule of an x-ghost);
  *  - a corrector frame with rho <= 0 or T <= 0 restarts the iteration once from
