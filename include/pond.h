@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 1
+#define POND_ABI_VERSION 2
 
 typedef enum {
     POND_OK = 0,
@@ -103,6 +103,8 @@ typedef struct {
     double t_min, t_max;            /* time of the instances after the call            */
     double dt_min, dt_max;          /* time steps of the last step over instances      */
     int32_t failed_instances;       /* instances frozen after producing an invalid cell */
+    int64_t tail_faces;             /* 2D: faces finished by the tail kernel           */
+    int64_t tail_iters;             /* 2D: iterations run by the tail kernel           */
 } pond_stats;
 
 typedef struct pond_ctx pond_ctx;
@@ -173,12 +175,24 @@ pond_status pond_set_tiles(pond_ctx *ctx, int32_t bx, int32_t by, int32_t cell_b
 pond_status pond_get_tiles(const pond_ctx *ctx, int32_t *bx, int32_t *by, int32_t *cell_block);
 pond_status pond_autotune(pond_ctx *ctx);
 
-/* Average device time in ms per launch of each kernel over the last pond_step call,
- * measured with HIP events on the context's stream: out[0] dt/time kernel,
- * out[1] face kernel, out[2] cell update kernel, out[3] seed (MLP) kernel.
+/* 2D: the face kernel runs each face's frame iteration (Sec. III.B.3) for at most k
+ * iterations; faces still iterating then continue, from the same state, in a tail kernel
+ * that gives every face 16 lanes instead of one (a wave otherwise runs as long as its
+ * slowest face). Results are those of the same iteration (rounding order aside).
+ * k = 0 runs every face to the end in the face kernel. Default 3 (FP64) or 2 (mixed).
+ * The tail sums its moments in another order than the face kernel, so different k
+ * give results that differ by rounding (tile shapes do not change results at all);
+ * pond_autotune therefore leaves k alone. Ignored in 1D.
+ * POND_EINVAL for k < 0. */
+pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
+
+/* Average device time in ms per step of each kernel over the last pond_step call,
+ * measured with HIP events on the context's stream, into a caller array of 5:
+ * out[0] dt/time kernel, out[1] face kernel including its tail kernel, out[2] cell
+ * update kernel, out[3] seed (MLP) kernel, out[4] tail kernel alone.
  * Timing is recorded only after pond_enable_timing(ctx, 1). */
 pond_status pond_enable_timing(pond_ctx *ctx, int32_t on);
-pond_status pond_kernel_times(const pond_ctx *ctx, double *out4);
+pond_status pond_kernel_times(const pond_ctx *ctx, double *out);
 
 
 /* ---------------------------------------------------------------------------------------

@@ -38,6 +38,9 @@ struct pond_ctx {
     int *err = nullptr;
     int *inst_err = nullptr;
     double *scratch = nullptr; // read-out staging (4 x ncell doubles)
+    // 2D: faces handed from the face kernel to the tail kernel
+    int *tail_f = nullptr, *tail_meta = nullptr, *tail_count = nullptr;
+    void *tail_s = nullptr;
     // host mirrors
     std::vector<int64_t> h_cell_off;
     int tube_span = 0;
@@ -45,9 +48,9 @@ struct pond_ctx {
     int64_t steps_done = 0;
     // launch shapes
     int bx = 256, by = 1, cell_block = 256;
-    // timing: one set of 5 events per step of a pond_step call, read once at its end
+    // timing: one set of 6 events per step of a pond_step call, read once at its end
     int timing = 0;
-    double ktime[4] = {0, 0, 0, 0};
+    double ktime[5] = {0, 0, 0, 0, 0};
     std::vector<hipEvent_t> evs;
     hipEvent_t *ev = nullptr;
     // learned seed
@@ -94,6 +97,10 @@ State<R> state_of(pond_ctx *c)
     S.stats = c->stats;
     S.err = c->err;
     S.inst_err = c->inst_err;
+    S.tail_f = c->tail_f;
+    S.tail_s = reinterpret_cast<R *>(c->tail_s);
+    S.tail_meta = c->tail_meta;
+    S.tail_count = c->tail_count;
     return S;
 }
 
@@ -135,6 +142,13 @@ hipError_t launch_face(pond_ctx *c, int bx, int by)
         dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
         size_t lds = face_lds_bytes(c, bx, by, 0);
         face_kernel_2d<R><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        if (c->ev) (void)hipEventRecord(c->ev[3], c->stream);
+        if (c->P.iter_split > 0) {
+            // 16 faces per block; enough blocks for every listed face in one pass
+            const int64_t most = std::max<int64_t>(c->P.nfx, c->P.nface - c->P.nfx);
+            dim3 tgrid((unsigned)std::min<int64_t>(blocks(most, 16), 2048), 2);
+            face_tail_kernel_2d<R><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+        }
     }
     return hipGetLastError();
 }
@@ -154,9 +168,10 @@ hipError_t launch_step(pond_ctx *c, double t_end)
     if (tm) (void)hipEventRecord(c->ev[2], c->stream);
     hipError_t e = launch_face<D, R>(c, c->bx, c->by);
     if (e != hipSuccess) return e;
-    if (tm) (void)hipEventRecord(c->ev[3], c->stream);
-    cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+    if (tm && D == 1) (void)hipEventRecord(c->ev[3], c->stream);
     if (tm) (void)hipEventRecord(c->ev[4], c->stream);
+    cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+    if (tm) (void)hipEventRecord(c->ev[5], c->stream);
     c->slot ^= 1;
     return hipGetLastError();
 }
@@ -170,6 +185,7 @@ hipError_t step_once(pond_ctx *c, double t_end)
 
 hipError_t face_once(pond_ctx *c, int bx, int by)
 {
+    if (c->tail_count) tail_reset_kernel<<<1, 64, 0, c->stream>>>(c->tail_count);
     if (c->D == 1)
         return c->precision == POND_FP64 ? launch_face<1, double>(c, bx, by) : launch_face<1, float>(c, bx, by);
     return c->precision == POND_FP64 ? launch_face<2, double>(c, bx, by) : launch_face<2, float>(c, bx, by);
@@ -240,7 +256,8 @@ void init_launch(pond_ctx *c, const double *dprim)
 void free_all(pond_ctx *c)
 {
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
-                    c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch};
+                    c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch,
+                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -362,6 +379,13 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         alloc((void **)&c->face_inst, sizeof(int) * nf);
         alloc((void **)&c->dxk, sizeof(double) * P.n_inst);
     }
+    if (c->D == 2) {
+        alloc((void **)&c->tail_f, sizeof(int) * nf);
+        alloc((void **)&c->tail_meta, sizeof(int) * nf);
+        alloc(&c->tail_s, c->rsize * 6 * nf);
+        alloc((void **)&c->tail_count, sizeof(int) * 2);
+        P.iter_split = (cfg->precision == POND_FP64) ? 3 : 2;
+    }
     if (!ok) {
         free_all(c);
         delete c;
@@ -427,9 +451,9 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
     if (!c || nsteps < 0) return POND_EINVAL;
     if (c->cfg.seed_mode == POND_SEED_MLP && !c->mlp.ready) return POND_ESTATE;
     HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
-    double kt[4] = {0, 0, 0, 0};
+    double kt[5] = {0, 0, 0, 0, 0};
     if (c->timing) {
-        size_t need = (size_t)5 * std::max(nsteps, 1);
+        size_t need = (size_t)6 * std::max(nsteps, 1);
         while (c->evs.size() < need) {
             hipEvent_t e;
             HIPCHK(hipEventCreate(&e));
@@ -437,24 +461,26 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         }
     }
     for (int s = 0; s < nsteps; ++s) {
-        c->ev = c->timing ? &c->evs[(size_t)5 * s] : nullptr;
+        c->ev = c->timing ? &c->evs[(size_t)6 * s] : nullptr;
         HIPCHK(step_once(c, t_end));
     }
     if (c->timing && nsteps > 0) {
         HIPCHK(hipStreamSynchronize(c->stream));
         for (int s = 0; s < nsteps; ++s) {
-            hipEvent_t *e = &c->evs[(size_t)5 * s];
+            hipEvent_t *e = &c->evs[(size_t)6 * s];
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e[0], e[1]);
             kt[0] += ms;
-            (void)hipEventElapsedTime(&ms, e[2], e[3]);
+            (void)hipEventElapsedTime(&ms, e[2], e[4]);
             kt[1] += ms;
-            (void)hipEventElapsedTime(&ms, e[3], e[4]);
+            (void)hipEventElapsedTime(&ms, e[4], e[5]);
             kt[2] += ms;
             (void)hipEventElapsedTime(&ms, e[1], e[2]);
             kt[3] += ms;
+            (void)hipEventElapsedTime(&ms, e[3], e[4]);
+            kt[4] += ms;
         }
-        for (int q = 0; q < 4; ++q) c->ktime[q] = kt[q] / nsteps;
+        for (int q = 0; q < 5; ++q) c->ktime[q] = kt[q] / nsteps;
     }
     c->ev = nullptr;
     unsigned long long hs[ST_N];
@@ -477,6 +503,8 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         st->nonconverged = (int64_t)hs[ST_NONCONV];
         st->fallback = (int64_t)hs[ST_FALLBACK];
         st->departure_out = (int64_t)hs[ST_DEPOUT];
+        st->tail_faces = (int64_t)hs[ST_TAIL_FACES];
+        st->tail_iters = (int64_t)hs[ST_TAIL_ITERS];
         st->t_min = *std::min_element(ht.begin(), ht.end());
         st->t_max = *std::max_element(ht.begin(), ht.end());
         st->dt_min = *std::min_element(hdt.begin(), hdt.end());
@@ -689,6 +717,13 @@ pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_blo
     return POND_OK;
 }
 
+pond_status pond_set_iter_split(pond_ctx *c, int32_t k)
+{
+    if (!c || k < 0) return POND_EINVAL;
+    if (c->D == 2) c->P.iter_split = k;
+    return POND_OK;
+}
+
 pond_status pond_get_tiles(const pond_ctx *c, int32_t *bx, int32_t *by, int32_t *cell_block)
 {
     if (!c || !bx || !by || !cell_block) return POND_EINVAL;
@@ -777,10 +812,10 @@ pond_status pond_enable_timing(pond_ctx *c, int32_t on)
     return POND_OK;
 }
 
-pond_status pond_kernel_times(const pond_ctx *c, double *out4)
+pond_status pond_kernel_times(const pond_ctx *c, double *out)
 {
-    if (!c || !out4) return POND_EINVAL;
-    for (int q = 0; q < 4; ++q) out4[q] = c->ktime[q];
+    if (!c || !out) return POND_EINVAL;
+    for (int q = 0; q < 5; ++q) out[q] = c->ktime[q];
     return POND_OK;
 }
 

@@ -26,7 +26,8 @@ namespace pond {
 
 enum { BC_PERIODIC = 0, BC_OUTFLOW, BC_REFLECT, BC_FIXED, BC_FIXED_WINDOW, BC_SPLIT, BC_MOVING };
 
-enum { ST_CELLS = 0, ST_CONV_CELLS, ST_FACES, ST_ITERS, ST_NONCONV, ST_FALLBACK, ST_DEPOUT, ST_ITMAX, ST_N };
+enum { ST_CELLS = 0, ST_CONV_CELLS, ST_FACES, ST_ITERS, ST_NONCONV, ST_FALLBACK, ST_DEPOUT, ST_ITMAX,
+       ST_TAIL_FACES, ST_TAIL_ITERS, ST_N };
 
 enum { ERR_NONPHYS = 1, ERR_DEPART = 2, ERR_NONCONV = 4 };
 
@@ -38,6 +39,8 @@ struct Params {
     int bc[4];
     double bc_state[4][4], bc_alt[4][4], bc_param[4][4];
     double bc_speed[2]; // per axis: fastest particle speed of the prescribed boundary states
+    int iter_split;     // 2D: iterations done in the face kernel before a face moves to the
+                        // tail kernel (0: the face kernel runs every face to the end)
     int64_t ncell, nface, nfx;
 };
 
@@ -57,6 +60,13 @@ struct State {
     unsigned long long *stats; // ST_N counters
     int *err;
     int *inst_err;             // per instance: nonzero once a step produced an invalid cell
+    // faces handed from the face kernel to the tail kernel (2D): face index, iteration
+    // state (u_x, u_y, T, and the frame two iterations back: 6 planes of R), and
+    // it | have_pp << 16 | restarted << 17. x-faces fill [0, nfx), y-faces [nfx, nface).
+    int *tail_f;
+    R *tail_s;
+    int *tail_meta;
+    int *tail_count;           // 2 counters (x-faces, y-faces), cleared by dt_kernel
 };
 
 template <int D>
@@ -138,6 +148,10 @@ __global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
     S.dt[k] = dt;
     S.t[k] = t + dt;
     S.vmax[(slot ^ 1) * P.n_inst + k] = 0ull;
+    if (k == 0 && S.tail_count) {
+        S.tail_count[0] = 0;
+        S.tail_count[1] = 0;
+    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -695,6 +709,7 @@ PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_s
 
 struct FaceCount {
     unsigned long long iters, nonconv, fallback, depout, itmax;
+    unsigned long long tail_faces = 0, tail_iters = 0; // faces finished by the tail kernel
 };
 
 // 1D face f with LDS stencil indices idx = {L, R, L-1, R+1}
@@ -819,8 +834,9 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
     R upp[2] = {u[0], u[1]}, Tpp = T; // frame two iterations back
     bool have_pp = false;
     int it = 0;
-    bool conv = false, failed = false;
-    while (it < P.max_iter) {
+    bool conv = false, failed = false, stopped = false;
+    const int kcap = (P.iter_split > 0 && P.iter_split < P.max_iter) ? P.iter_split : P.max_iter;
+    while (it < kcap) {
         ++it;
         R s = sqrt(T), inv_s = R(1) / s;
         {
@@ -864,8 +880,31 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
             break;
         }
         // an iteration that returns to the frame two iterations back oscillates: stop
-        if (have_pp && delta2 <= R(1e-2) * delta) break;
+        if (have_pp && delta2 <= R(1e-2) * delta) {
+            stopped = true;
+            break;
+        }
         have_pp = true;
+    }
+    if (!conv && !failed && !stopped && it < P.max_iter) {
+        // this kernel's share of iterations is spent: the tail kernel continues the
+        // same iteration from this state (it, frames, flags), with 16 lanes per face
+        const int64_t base = AXIS ? P.nfx : 0;
+        const int64_t cap = AXIS ? P.nface - P.nfx : P.nfx;
+        const int64_t pos = atomicAdd(&S.tail_count[AXIS], 1);
+        if (pos < cap) { // always true: every face of the axis fits
+            const int64_t e = base + pos;
+            const int64_t nf = P.nface;
+            S.tail_f[e] = (int)f;
+            S.tail_s[0 * nf + e] = u[0];
+            S.tail_s[1 * nf + e] = u[1];
+            S.tail_s[2 * nf + e] = T;
+            S.tail_s[3 * nf + e] = upp[0];
+            S.tail_s[4 * nf + e] = upp[1];
+            S.tail_s[5 * nf + e] = Tpp;
+            S.tail_meta[e] = it | ((have_pp ? 1 : 0) << 16) | ((restarted ? 1 : 0) << 17);
+        }
+        return;
     }
     bool has_frame = true;
     if (failed || !conv) {
@@ -947,7 +986,7 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
         plus_record<1, R>(P, S, c, S.dt[k], L + (v - vlo), NT, 0);
     }
     __syncthreads();
-    FaceCount cnt{0, 0, 0, 0, 0};
+    FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     unsigned long long nfc = 0;
     if (f < P.nface) {
         const int k = S.face_inst ? S.face_inst[f] : 0;
@@ -993,7 +1032,7 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
     auto li = [&](int ci, int cj) { return (ci - i0 + 2) + TX * (cj - j0 + 2); };
-    FaceCount cnt{0, 0, 0, 0, 0};
+    FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     unsigned long long nfaces = 0;
     if (i <= P.nx && j < P.ny) {
         const int idx[2] = {li(i - 1, j), li(i, j)};
@@ -1012,6 +1051,318 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
     stat_add(S.stats, ST_DEPOUT, cnt.depout);
     stat_max(S.stats, ST_ITMAX, cnt.itmax);
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// ---------------------------------------------------------------------------------
+// tail kernel (2D): the faces whose iteration outlasts the face kernel's share
+// ---------------------------------------------------------------------------------
+//
+// A wave of the face kernel runs as long as its slowest face, so the few faces that need
+// many iterations would hold 64 lanes each. They continue here with 16 lanes per face: lanes
+// 0..7 build the phi-bar-plus records of the 8 stencil cells in LDS; in every iteration lane
+// q brings stencil cell q & 7 into the face frame (f for q < 8, g for q >= 8; the order-2
+// set of g shifts exactly as the first 6 entries of a degree-3 set), then reconstructs
+// population i = q from the 5 cells its upwind direction needs, and the moments are sums
+// over the 16 lanes. Same iteration, same stopping rules and finalization as face_2d.
+
+constexpr int TAIL_REC = 8 * Layout<2>::NL; // 8 stencil records
+constexpr int TAIL_COEF = 8 * 16;           // per stencil cell: f 10, g 6 coefficients
+constexpr int TAIL_GROUP = TAIL_REC + TAIL_COEF;
+
+// LDS written by some lanes of a wave and read by others of the same wave
+PD void wave_fence()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// sum over the 16 lanes of a group (butterfly: every lane ends with the same value)
+template <typename R>
+PD R group_sum(R v)
+{
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+    return v;
+}
+
+// cell (ci, cj) of stencil slot q (L, R, L-n, R+n, L-t, L+t, R-t, R+t) of face f
+template <int AXIS>
+PD void tail_cell(const Params &P, int64_t f, int q, int &ci, int &cj)
+{
+    int i, j; // the face's upper/right cell R
+    if (AXIS == 0) {
+        i = (int)(f % (P.nx + 1));
+        j = (int)(f / (P.nx + 1));
+    } else {
+        const int64_t g = f - P.nfx;
+        i = (int)(g % P.nx);
+        j = (int)(g / P.nx);
+    }
+    const int a = (q == 1 || q >= 6) ? 1 : (q == 2 ? -1 : (q == 3 ? 2 : 0)); // normal, from L
+    const int b = (q == 4 || q == 6) ? -1 : ((q == 5 || q == 7) ? 1 : 0);   // tangential
+    if (AXIS == 0) {
+        ci = i - 1 + a;
+        cj = j + b;
+    } else {
+        ci = i + b;
+        cj = j - 1 + a;
+    }
+}
+
+// One face per 16-lane group. Every lane of the wave runs every instruction of the
+// iteration (a group that is done, or has no face, computes and discards), so the cross-lane
+// sums and the LDS exchange never run under a partial execution mask.
+template <typename R, int AXIS>
+PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e, bool has,
+                  int q, double dt, double t, FaceCount &cnt)
+{
+    const int64_t nf = P.nface;
+    const int64_t f = has ? S.tail_f[e] : 0;
+    if (has && q < 8) {
+        int ci, cj;
+        tail_cell<AXIS>(P, f, q, ci, cj);
+        CellRef c = map2d(P, ci, cj, t);
+        plus_record<2, R>(P, S, c, dt, rec + q, 8, 0);
+    }
+    wave_fence();
+    const double dn = AXIS ? P.dy : P.dx, dtn = AXIS ? P.dx : P.dy;
+    const R hdn = (R)(0.5 * dt / dn), hdt = (R)(0.5 * dt / dtn);
+    R u[2] = {R(0), R(0)}, T = R(1), upp[2] = {R(0), R(0)}, Tpp = R(1);
+    int it = 0;
+    bool have_pp = false, restarted = false;
+    if (has) {
+        u[0] = S.tail_s[0 * nf + e];
+        u[1] = S.tail_s[1 * nf + e];
+        T = S.tail_s[2 * nf + e];
+        upp[0] = S.tail_s[3 * nf + e];
+        upp[1] = S.tail_s[4 * nf + e];
+        Tpp = S.tail_s[5 * nf + e];
+        const int meta = S.tail_meta[e];
+        it = meta & 0xffff;
+        have_pp = (meta >> 16) & 1;
+        restarted = (meta >> 17) & 1;
+    }
+    const int it0 = it;
+    R um[2] = {R(0), R(0)}, T_m = R(1);
+    if (has) mean_frame<2, R>(rec, 8, 0, 1, P, um, T_m);
+    // population of this lane: node (cx, cy), Hermite basis values, weight
+    const int ix = q & 3, iy = q >> 2;
+    const R cx = node<R>(ix), cy = node<R>(iy);
+    const R cx2 = cx * cx, cy2 = cy * cy;
+    const R bas[10] = {R(1),          cx,         cy,           cx2 - R(1),   cx * cy,
+                       cy2 - R(1),    cx * (cx2 - R(3)), (cx2 - R(1)) * cy, cx * (cy2 - R(1)),
+                       cy * (cy2 - R(3))};
+    const R wgt = weight1<R>(ix) * weight1<R>(iy);
+    const R cn = node<R>(AXIS ? iy : ix), ct = node<R>(AXIS ? ix : iy);
+    // stencil cell transformed by this lane
+    const int tc = q & 7;
+    const bool tg = q >= 8;
+    R ul[2] = {u[0], u[1]}, sl = sqrt(T);
+    R pf = R(0), pg = R(0);
+    bool conv = false, failed = false;
+    bool active = has && it < P.max_iter;
+    while (__any(active)) {
+        if (active) ++it;
+        const R s = sqrt(T), inv_s = R(1) / s;
+        {
+            const R r = rec[2 * 8 + tc] * inv_s, dx = (rec[tc] - u[0]) * inv_s,
+                    dy = (rec[8 + tc] - u[1]) * inv_s;
+            R h[10], mu[10];
+            if (!tg) {
+                h[0] = rec[3 * 8 + tc];
+                h[1] = R(0);
+                h[2] = R(0);
+#pragma unroll
+                for (int k = 0; k < 7; ++k) h[3 + k] = rec[(4 + k) * 8 + tc];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) h[k] = rec[(11 + k) * 8 + tc];
+#pragma unroll
+                for (int k = 6; k < 10; ++k) h[k] = R(0);
+            }
+            h2mu_2d(h, mu, 10);
+            shift_2d(mu, r, dx, dy, 10);
+            mu2h_2d(mu, h, 10);
+            R *dst = coef + tc * 16 + (tg ? 10 : 0);
+            const int nw = tg ? 6 : 10;
+#pragma unroll
+            for (int k = 0; k < 10; ++k)
+                if (k < nw) dst[k] = h[k];
+        }
+        wave_fence();
+        const R un = AXIS ? u[1] : u[0], ut = AXIS ? u[0] : u[1];
+        const R vn = s * cn + un, vt = s * ct + ut;
+        const bool up = vn >= R(0);
+        // upwind, downwind, behind-upwind, tangential - and + of the upwind cell
+        const int cl[5] = {up ? 0 : 1, up ? 1 : 0, up ? 2 : 3, up ? 4 : 6, up ? 5 : 7};
+        R vf[5], vg[5];
+#pragma unroll
+        for (int m = 0; m < 5; ++m) {
+            const R *h = coef + cl[m] * 16;
+            R a = h[0], b = h[10];
+#pragma unroll
+            for (int k = 1; k < 10; ++k) a += h[k] * bas[k];
+#pragma unroll
+            for (int k = 1; k < 6; ++k) b += h[10 + k] * bas[k];
+            vf[m] = a;
+            vg[m] = b;
+        }
+        wave_fence(); // coefficients are rewritten by the next iteration
+        const R off = (up ? R(0.5) : R(-0.5)) - vn * hdn, offt = -vt * hdt;
+        auto recon = [&](const R *v) {
+            const R A = up ? v[0] - v[2] : v[0] - v[1];
+            const R B = up ? v[1] - v[0] : v[2] - v[0];
+            const R o = v[0] + off * limit(A, B, P.limiter);
+            return o + offt * limit(v[0] - v[3], v[4] - v[0], P.limiter);
+        };
+        const R pfn = recon(vf), pgn = recon(vg);
+        const R wf = wgt * pfn;
+        const R rho = group_sum(wf);
+        const R m1x = group_sum(wf * cx), m1y = group_sum(wf * cy);
+        const R m2 = group_sum(wf * (cx2 + cy2));
+        const R g0 = group_sum(wgt * pgn);
+        if (active) {
+            pf = pfn;
+            pg = pgn;
+            const R irho = R(1) / rho;
+            const R dux = s * m1x * irho, duy = s * m1y * irho;
+            const R rhoe = R(0.5) * s * s * (m2 - (m1x * m1x + m1y * m1y) * irho) + g0;
+            const R Tn = rhoe / ((R)P.Cv * rho);
+            if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(dux) || !isfinite(duy)) {
+                if (!restarted) {
+                    restarted = true;
+                    u[0] = um[0];
+                    u[1] = um[1];
+                    T = T_m;
+                    have_pp = false;
+                } else {
+                    failed = true;
+                    active = false;
+                }
+            } else {
+                const R unx = u[0] + dux, uny = u[1] + duy;
+                const R isq = R(1) / sqrt(Tn);
+                const R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, fabs(Tn - T) / Tn);
+                const R delta2 =
+                    fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, fabs(Tn - Tpp) / Tn);
+                upp[0] = u[0];
+                upp[1] = u[1];
+                Tpp = T;
+                ul[0] = u[0];
+                ul[1] = u[1];
+                sl = s;
+                u[0] = unx;
+                u[1] = uny;
+                T = Tn;
+                if (delta <= (R)P.tol) {
+                    conv = true;
+                    active = false;
+                } else if (have_pp && delta2 <= R(1e-2) * delta) {
+                    active = false; // a 2-cycle: stop, not converged
+                } else {
+                    have_pp = true;
+                }
+            }
+            if (active && it >= P.max_iter) active = false;
+        }
+    }
+    // moments of the last reconstruction (frame ul, sl), degree <= 3 (f) and <= 2 (g)
+    R mf[10], mg[10];
+    {
+        const R mono[10] = {R(1), cx, cy, cx2, cx * cy, cy2, cx2 * cx, cx2 * cy, cx * cy2, cy2 * cy};
+        const R wf = wgt * pf, wg = wgt * pg;
+#pragma unroll
+        for (int k = 0; k < 10; ++k) mf[k] = group_sum(wf * mono[k]);
+#pragma unroll
+        for (int k = 0; k < 6; ++k) mg[k] = group_sum(wg * mono[k]);
+#pragma unroll
+        for (int k = 6; k < 10; ++k) mg[k] = R(0);
+    }
+    if (has) {
+        bool has_frame = true;
+        if (failed || !conv) {
+            R sm = sqrt(T_m), inv_sm = R(1) / sm;
+            R a[10], b[10];
+            own_half_2d<R, false, AXIS>(rec, 8, 0, false, um[0], um[1], inv_sm, a);
+            own_half_2d<R, false, AXIS>(rec, 8, 1, true, um[0], um[1], inv_sm, b);
+            for (int k = 0; k < 10; ++k) mf[k] = a[k] + b[k];
+            own_half_2d<R, true, AXIS>(rec, 8, 0, false, um[0], um[1], inv_sm, a);
+            own_half_2d<R, true, AXIS>(rec, 8, 1, true, um[0], um[1], inv_sm, b);
+            for (int k = 0; k < 10; ++k) mg[k] = a[k] + b[k];
+            R rho = mf[0];
+            R dux = sm * mf[1] / rho, duy = sm * mf[2] / rho;
+            R Tn = (R(0.5) * sm * sm * (mf[3] + mf[5] - (mf[1] * mf[1] + mf[2] * mf[2]) / rho) + mg[0]) /
+                   ((R)P.Cv * rho);
+            ul[0] = um[0];
+            ul[1] = um[1];
+            sl = sm;
+            if (rho > R(0) && Tn > R(0) && isfinite(Tn) && isfinite(dux) && isfinite(duy)) {
+                u[0] = um[0] + dux;
+                u[1] = um[1] + duy;
+                T = Tn;
+            } else {
+                has_frame = false;
+                u[0] = um[0];
+                u[1] = um[1];
+                T = T_m;
+            }
+            if (q == 0) cnt.fallback += 1;
+        }
+        if (q == 0) {
+            R s = sqrt(T);
+            R vx = s * node<R>(3) + fabs(u[0]), vy = s * node<R>(3) + fabs(u[1]);
+            if (vx * (R)(0.5 * dt) > (R)(0.5 * P.dx) || vy * (R)(0.5 * dt) > (R)(0.5 * P.dy)) cnt.depout += 1;
+            if (!conv) cnt.nonconv += 1;
+            cnt.iters += it;
+            cnt.tail_faces += 1;
+            cnt.tail_iters += it - it0;
+            if ((unsigned long long)it > cnt.itmax) cnt.itmax = it;
+            face_write<2, R>(P, S, f, mf, mg, ul, sl, u, T, has_frame, dt);
+            S.fiter[f] = it | ((conv ? 0 : 1) << 16) | ((failed ? 1 : 0) << 17);
+        }
+    }
+    wave_fence(); // the records are rebuilt for the group's next face
+}
+
+template <typename R>
+__global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
+{
+    __shared__ R lds[16 * TAIL_GROUP];
+    const double dt = S.dt[0];
+    if (!(dt > 0.0)) return;
+    const double t = S.tstart[0];
+    const int axis = blockIdx.y;
+    const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
+    R *rec = lds + grp * TAIL_GROUP, *coef = rec + TAIL_REC;
+    const int64_t base = axis ? P.nfx : 0;
+    const int64_t cap = axis ? P.nface - P.nfx : P.nfx;
+    const int64_t count = min((int64_t)S.tail_count[axis], cap);
+    FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
+    // wave-uniform loop: a group without a face in this round takes part with has = false
+    for (int64_t k0 = (int64_t)blockIdx.x * 16; __any(k0 + grp < count); k0 += (int64_t)gridDim.x * 16) {
+        const int64_t k = k0 + grp;
+        const bool has = k < count;
+        const int64_t e = base + (has ? k : 0);
+        if (axis == 0)
+            tail_face<R, 0>(P, S, rec, coef, e, has, q, dt, t, cnt);
+        else
+            tail_face<R, 1>(P, S, rec, coef, e, has, q, dt, t, cnt);
+    }
+    stat_add(S.stats, ST_ITERS, cnt.iters);
+    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
+    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
+    stat_add(S.stats, ST_DEPOUT, cnt.depout);
+    stat_max(S.stats, ST_ITMAX, cnt.itmax);
+    stat_add(S.stats, ST_TAIL_FACES, cnt.tail_faces);
+    stat_add(S.stats, ST_TAIL_ITERS, cnt.tail_iters);
+    if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// clears the tail counters where no dt_kernel runs before a face kernel (the autotuner)
+__global__ void tail_reset_kernel(int *count)
+{
+    if (threadIdx.x < 2) count[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------------

@@ -55,6 +55,7 @@ class Stats(ctypes.Structure):
         ("t_min", ctypes.c_double), ("t_max", ctypes.c_double),
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
         ("failed_instances", ctypes.c_int32),
+        ("tail_faces", ctypes.c_int64), ("tail_iters", ctypes.c_int64),
     ]
 
     def as_dict(self):
@@ -106,6 +107,7 @@ def load(path: str | None = None):
         "pond_get_tiles": (S, [_P, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_int32),
                                ctypes.POINTER(ctypes.c_int32)]),
         "pond_autotune": (S, [_P]),
+        "pond_set_iter_split": (S, [_P, ctypes.c_int32]),
         "pond_enable_timing": (S, [_P, ctypes.c_int32]),
         "pond_kernel_times": (S, [_P, _D]),
         "pond_free": (None, [_P]),
@@ -139,7 +141,8 @@ def exported_symbols():
             "pond_populations", "pond_nfaces", "pond_face_frames", "pond_set_face_frames",
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
-            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_enable_timing",
+            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split",
+            "pond_enable_timing",
             "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
             "pond_mlp_nparams", "pond_mlp_create", "pond_mlp_get", "pond_mlp_set",
             "pond_mlp_forward", "pond_mlp_grad", "pond_mlp_train", "pond_mlp_free",
@@ -334,9 +337,14 @@ class Context:
         load().pond_enable_timing(self._h, 1 if on else 0)
 
     def kernel_times(self):
-        out = np.zeros(4)
+        out = np.zeros(5)
         load().pond_kernel_times(self._h, _ptr(out))
-        return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3]}
+        return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3], "tail": out[4]}
+
+    def set_iter_split(self, k: int):
+        rc = load().pond_set_iter_split(self._h, int(k))
+        if rc != OK:
+            raise PondError(rc, "pond_set_iter_split")
 
 
     # ---- learned seed ----

@@ -82,12 +82,17 @@ def test_periodic_random_2d_fp64(orc, nx, ny, steps):
     assert np.mean(np.abs(it_g) == np.abs(it_o)) > 0.99
 
 
-def test_double_mach_small_fp64(orc):
+@pytest.mark.parametrize("split", [None, 0, 1])
+def test_double_mach_small_fp64(orc, split):
     """Double Mach reflection on 96 x 24 cells, 30 steps: fixed, split fixed/reflecting,
-    moving-shock and outflow boundaries, strong shocks, restarts and fallbacks."""
+    moving-shock and outflow boundaries, strong shocks, restarts and fallbacks. With the
+    default hand-over to the tail kernel, without tail kernel (split 0), and with every
+    iteration after the first in the tail kernel (split 1)."""
     cfg, f = W.double_mach(96, 24)
-    _print("case", name="dmr", nx=96, ny=24)
+    _print("case", name="dmr", nx=96, ny=24, split=split)
     g, o = _pair(orc, cfg, f)
+    if split is not None:
+        g.set_iter_split(split)
     for k in range(30):
         o.step()
         g.step(1)
