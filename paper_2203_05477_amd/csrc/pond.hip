@@ -159,7 +159,7 @@ hipError_t launch_step(pond_ctx *c, double t_end)
     State<R> S = state_of<R>(c);
     const bool tm = c->ev != nullptr;
     if (tm) (void)hipEventRecord(c->ev[0], c->stream);
-    dt_kernel<D, R><<<blocks(c->P.n_inst, 64), 64, 0, c->stream>>>(c->P, S, t_end, c->slot);
+    dt_kernel<D, R><<<c->P.n_inst, 64, 0, c->stream>>>(c->P, S, t_end, c->slot);
     if (tm) (void)hipEventRecord(c->ev[1], c->stream);
     if (c->cfg.seed_mode == POND_SEED_MLP && c->mlp.ready) {
         hipError_t e = mlp_seed_launch<D, R>(c->mlp, c->P, S, c->stream);
@@ -369,8 +369,9 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     alloc((void **)&c->t, sizeof(double) * P.n_inst);
     alloc((void **)&c->tstart, sizeof(double) * P.n_inst);
     alloc((void **)&c->dt, sizeof(double) * P.n_inst);
-    alloc((void **)&c->vmax, sizeof(unsigned long long) * 2 * P.n_inst);
-    alloc((void **)&c->stats, sizeof(unsigned long long) * ST_N);
+    P.vslots = (P.n_inst == 1) ? NSLOT : 1;
+    alloc((void **)&c->vmax, sizeof(unsigned long long) * 2 * P.n_inst * P.vslots);
+    alloc((void **)&c->stats, sizeof(unsigned long long) * ST_N * NSLOT);
     alloc((void **)&c->err, sizeof(int));
     alloc((void **)&c->inst_err, sizeof(int) * P.n_inst);
     alloc((void **)&c->scratch, sizeof(double) * 4 * std::max(n, nf));
@@ -406,7 +407,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         prim4[3 * n + i] = p[i];
     }
     std::vector<double> zeros(P.n_inst, 0.0);
-    std::vector<unsigned long long> zv(2 * P.n_inst, 0ull), zs(ST_N, 0ull);
+    std::vector<unsigned long long> zv((size_t)2 * P.n_inst * P.vslots, 0ull), zs((size_t)ST_N * NSLOT, 0ull);
     bool up = hip_ok(hipMemcpy(c->scratch, prim4.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->cell_off, coff.data(), sizeof(int64_t) * coff.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->pad_off, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice)) &&
@@ -414,7 +415,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
               hip_ok(hipMemcpy(c->tstart, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->dt, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->vmax, zv.data(), sizeof(unsigned long long) * zv.size(), hipMemcpyHostToDevice)) &&
-              hip_ok(hipMemcpy(c->stats, zs.data(), sizeof(unsigned long long) * ST_N, hipMemcpyHostToDevice)) &&
+              hip_ok(hipMemcpy(c->stats, zs.data(), sizeof(unsigned long long) * zs.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemset(c->err, 0, sizeof(int))) &&
               hip_ok(hipMemset(c->inst_err, 0, sizeof(int) * P.n_inst));
     if (up && P.n_inst > 1) {
@@ -450,7 +451,7 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
 {
     if (!c || nsteps < 0) return POND_EINVAL;
     if (c->cfg.seed_mode == POND_SEED_MLP && !c->mlp.ready) return POND_ESTATE;
-    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
+    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N * NSLOT, c->stream));
     double kt[5] = {0, 0, 0, 0, 0};
     if (c->timing) {
         size_t need = (size_t)6 * std::max(nsteps, 1);
@@ -483,15 +484,24 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         for (int q = 0; q < 5; ++q) c->ktime[q] = kt[q] / nsteps;
     }
     c->ev = nullptr;
-    unsigned long long hs[ST_N];
+    std::vector<unsigned long long> hsl((size_t)ST_N * NSLOT);
     int herr = 0;
-    HIPCHK(hipMemcpyAsync(hs, c->stats, sizeof(hs), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(hipMemcpyAsync(hsl.data(), c->stats, sizeof(unsigned long long) * hsl.size(), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(&herr, c->err, sizeof(int), hipMemcpyDeviceToHost, c->stream));
     std::vector<double> ht(c->P.n_inst), hdt(c->P.n_inst);
     HIPCHK(hipMemcpyAsync(ht.data(), c->t, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(hdt.data(), c->dt, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     c->steps_done += nsteps;
+    unsigned long long hs[ST_N];
+    for (int q = 0; q < ST_N; ++q) {
+        unsigned long long a = 0;
+        for (int w = 0; w < NSLOT; ++w) {
+            const unsigned long long v = hsl[(size_t)q * NSLOT + w];
+            a = (q == ST_ITMAX) ? std::max(a, v) : a + v;
+        }
+        hs[q] = a;
+    }
     if (st) {
         memset(st, 0, sizeof(*st));
         st->steps = nsteps;
@@ -762,10 +772,10 @@ pond_status pond_autotune(pond_ctx *c)
     {
         State<double> S = state_of<double>(c);
         // the dt kernel only touches t, tstart, dt and the other vmax slot: all restored below
-        std::vector<unsigned long long> vm(2 * c->P.n_inst);
+        std::vector<unsigned long long> vm((size_t)2 * c->P.n_inst * c->P.vslots);
         (void)hipMemcpyAsync(vm.data(), c->vmax, sizeof(unsigned long long) * vm.size(), hipMemcpyDeviceToHost, c->stream);
         (void)hipStreamSynchronize(c->stream);
-        dt_kernel<1, double><<<blocks(c->P.n_inst, 64), 64, 0, c->stream>>>(c->P, S, INFINITY, c->slot);
+        dt_kernel<1, double><<<c->P.n_inst, 64, 0, c->stream>>>(c->P, S, INFINITY, c->slot);
         for (auto &cd : cand) {
             if (c->D == 2 && ((cd.first * cd.second) % 64 != 0)) continue;
             if (face_lds_bytes(c, cd.first, cd.second, compute_span(c, cd.first)) > 160 * 1024) continue;
@@ -795,7 +805,7 @@ pond_status pond_autotune(pond_ctx *c)
     (void)hipMemcpyAsync(c->t, sdt + c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->tstart, sdt + 2 * c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->F, save, fbytes, hipMemcpyDeviceToDevice, c->stream);
-    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N, c->stream));
+    HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N * NSLOT, c->stream));
     HIPCHK(hipMemsetAsync(c->err, 0, sizeof(int), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     (void)hipFree(sdt);

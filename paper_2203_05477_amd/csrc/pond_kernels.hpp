@@ -41,6 +41,8 @@ struct Params {
     double bc_speed[2]; // per axis: fastest particle speed of the prescribed boundary states
     int iter_split;     // 2D: iterations done in the face kernel before a face moves to the
                         // tail kernel (0: the face kernel runs every face to the end)
+    int vslots;         // copies of each instance's CFL-rate maximum (NSLOT for one
+                        // instance, 1 for a batch, whose tubes spread the atomics anyway)
     int64_t ncell, nface, nfx;
 };
 
@@ -56,7 +58,7 @@ struct State {
     const int64_t *pad_off;  // per instance: padded offset (cell_off + 4k)
     double *t, *tstart, *dt;   // per instance
     const double *dxk;         // per instance cell size (1D tubes), or null: P.dx
-    unsigned long long *vmax;  // 2 x n_inst (slot by step parity)
+    unsigned long long *vmax;  // 2 x n_inst x vslots (step parity, instance, copy)
     unsigned long long *stats; // ST_N counters
     int *err;
     int *inst_err;             // per instance: nonzero once a step produced an invalid cell
@@ -95,10 +97,30 @@ PD unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
+// Counters and maxima are spread over NSLOT copies, one picked by the wave's global index:
+// atomics on one address serialize in its L2 channel (about 10 ns each), so one counter
+// hit once per wave would cost a kernel of 14,400 waves some 150 us. Readers combine the
+// copies.
+constexpr int NSLOT = 256;
+
+PD unsigned wave_slot()
+{
+    const unsigned blk = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+    const unsigned nthr = blockDim.x * blockDim.y * blockDim.z;
+    const unsigned tid = threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z);
+    return (blk * ((nthr + 63) / 64) + tid / 64) & (NSLOT - 1);
+}
+
+PD bool wave_leader()
+{
+    return ((threadIdx.x + blockDim.x * (threadIdx.y + blockDim.y * threadIdx.z)) & 63) == 0;
+}
+
+// all lanes of the wave must call these
 PD void stat_add(unsigned long long *stats, int k, unsigned long long v)
 {
     v = wave_sum(v);
-    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0 && v) atomicAdd(&stats[k], v);
+    if (wave_leader() && v) atomicAdd(&stats[k * NSLOT + wave_slot()], v);
 }
 
 PD void stat_max(unsigned long long *stats, int k, unsigned long long v)
@@ -108,7 +130,7 @@ PD void stat_max(unsigned long long *stats, int k, unsigned long long v)
         unsigned long long w = __shfl_xor(v, o, 64);
         v = w > v ? w : v;
     }
-    if ((threadIdx.x + threadIdx.y * blockDim.x) % 64 == 0 && v) atomicMax(&stats[k], v);
+    if (wave_leader() && v) atomicMax(&stats[k * NSLOT + wave_slot()], v);
 }
 
 // rho, u, T from conserved variables (ideal gas, R = 1): rho E = C_v rho T + rho |u|^2 / 2
@@ -125,16 +147,53 @@ PD void prim(const double *U, int64_t n, int64_t c, double &rho, double u[2], do
     T = (U[(1 + D) * n + c] / rho - 0.5 * ke) / Cv;
 }
 
+PD size_t vmax_at(const Params &P, int parity, int k, int copy)
+{
+    return ((size_t)parity * P.n_inst + k) * P.vslots + copy;
+}
+
+// largest CFL rate of the cells this wave updates, into its instance's maximum (all lanes
+// of the wave call this; `bits` is a non-negative double as its bit pattern, 0 for none)
+template <typename R>
+PD void vmax_update(const Params &P, const State<R> &S, int parity, int k, bool has,
+                    unsigned long long bits)
+{
+    const int k_first = __shfl(k, 0, 64);
+    if (__all(k == k_first)) {
+        unsigned long long m = has ? bits : 0ull;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            unsigned long long w = __shfl_xor(m, o, 64);
+            m = w > m ? w : m;
+        }
+        if (wave_leader() && m) atomicMax(S.vmax + vmax_at(P, parity, k, wave_slot() & (P.vslots - 1)), m);
+    } else if (has && bits) {
+        atomicMax(S.vmax + vmax_at(P, parity, k, 0), bits);
+    }
+}
+
 // ---------------------------------------------------------------------------------
-// dt kernel: one thread per instance
+// dt kernel: one 64-thread block per instance
 // ---------------------------------------------------------------------------------
 
 template <int D, typename R>
-__global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
+__global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_end, int slot)
 {
-    int k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= P.n_inst) return;
-    double rate = __longlong_as_double((long long)S.vmax[slot * P.n_inst + k]);
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    unsigned long long m = 0ull;
+    for (int c = lane; c < P.vslots; c += 64) {
+        unsigned long long v = S.vmax[vmax_at(P, slot, k, c)];
+        m = v > m ? v : m;
+        S.vmax[vmax_at(P, slot ^ 1, k, c)] = 0ull;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        unsigned long long w = __shfl_xor(m, o, 64);
+        m = w > m ? w : m;
+    }
+    if (lane != 0) return;
+    double rate = __longlong_as_double((long long)m);
     // boundary states enter through the boundary faces: their speeds bound dt as well
     double dxa = S.dxk ? S.dxk[k] : P.dx;
     rate = fmax(rate, P.bc_speed[0] / dxa);
@@ -147,7 +206,6 @@ __global__ void dt_kernel(Params P, State<R> S, double t_end, int slot)
     S.tstart[k] = t;
     S.dt[k] = dt;
     S.t[k] = t + dt;
-    S.vmax[(slot ^ 1) * P.n_inst + k] = 0ull;
     if (k == 0 && S.tail_count) {
         S.tail_count[0] = 0;
         S.tail_count[1] = 0;
@@ -891,7 +949,14 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
         // same iteration from this state (it, frames, flags), with 16 lanes per face
         const int64_t base = AXIS ? P.nfx : 0;
         const int64_t cap = AXIS ? P.nface - P.nfx : P.nfx;
-        const int64_t pos = atomicAdd(&S.tail_count[AXIS], 1);
+        // one atomic per wave: every active lane here appends a face
+        const unsigned long long mask = __ballot(1);
+        const int lane = __lane_id();
+        const int leader = __builtin_ctzll(mask);
+        int first = 0;
+        if (lane == leader) first = atomicAdd(&S.tail_count[AXIS], __popcll(mask));
+        first = __shfl(first, leader, 64);
+        const int64_t pos = first + __popcll(mask & ((1ull << lane) - 1ull));
         if (pos < cap) { // always true: every face of the axis fits
             const int64_t e = base + pos;
             const int64_t nf = P.nface;
@@ -1432,21 +1497,7 @@ __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slo
     unsigned long long bits = 0ull;
     bool all_conv = false;
     if (work) cell_update<D, R>(P, S, c, k, dt, slot, bits, all_conv);
-    unsigned long long *vm = S.vmax + (size_t)(slot ^ 1) * P.n_inst + k;
-    // one atomic per wave when the whole wave belongs to one instance
-    int k_first = __shfl(k, 0, 64);
-    bool same = __all(k == k_first);
-    if (same) {
-        unsigned long long m = bits;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            unsigned long long w = __shfl_xor(m, o, 64);
-            m = w > m ? w : m;
-        }
-        if ((threadIdx.x & 63) == 0 && m) atomicMax(vm, m);
-    } else if (work) {
-        atomicMax(vm, bits);
-    }
+    vmax_update<R>(P, S, slot ^ 1, k, work, bits);
     stat_add(S.stats, ST_CELLS, work ? 1 : 0);
     stat_add(S.stats, ST_CONV_CELLS, (work && all_conv) ? 1 : 0);
 }
@@ -1626,7 +1677,10 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = P.ncell;
+    int k = 0;
+    unsigned long long bits = 0ull;
     if (c < n) {
+        k = S.cell_inst ? S.cell_inst[c] : 0;
         double rho = prim4[c], ux = prim4[n + c], uy = prim4[2 * n + c], p = prim4[3 * n + c];
         double T = p / rho;
         S.U[c] = rho;
@@ -1635,11 +1689,11 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
         double ke = ux * ux + (D == 2 ? uy * uy : 0.0);
         S.U[(1 + D) * n + c] = P.Cv * rho * T + 0.5 * rho * ke;
         for (int q = 0; q < nh; ++q) S.H[q * n + c] = R(0);
-        const int k = S.cell_inst ? S.cell_inst[c] : 0;
         double rate = (fabs(ux) + sqrt(T) * CMAX) / ((D == 1 && S.dxk) ? S.dxk[k] : P.dx);
         if (D == 2) rate = fmax(rate, (fabs(uy) + sqrt(T) * CMAX) / P.dy);
-        atomicMax(S.vmax + k, (unsigned long long)__double_as_longlong(rate));
+        bits = (unsigned long long)__double_as_longlong(rate);
     }
+    vmax_update<R>(P, S, 0, k, c < n, bits);
     if (c < P.nface) S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
 }
 
