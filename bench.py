@@ -37,13 +37,40 @@ FLOPS_FACE_FINAL = {1: 60, 2: 330}
 PEAK_VALU_TFLOPS = 78.6
 
 
-def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True):
+TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "double_mach_1920x480_face_traffic.md")
+KERNEL_SOURCES = ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip")
+
+
+def measured_traffic():
+    """HBM bytes per face-kernel launch from the committed counter summary (FETCH_SIZE and
+    WRITE_SIZE scaled by a known-size copy), or None once the kernel sources have changed
+    since those counters were taken."""
+    import hashlib
+
+    if not os.path.exists(TRAFFIC_PROFILE):
+        return None
+    rec = None
+    for line in open(TRAFFIC_PROFILE):
+        if line.startswith("traffic-json:"):
+            rec = json.loads(line.split(":", 1)[1])
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2203_05477_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES))
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec
+
+
+def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True, tiles=None):
     from paper_2203_05477_amd import pond
 
     ctx = pond.Context(cfg, fields, precision=precision, seed=seed)
     if warmup:
         ctx.step(warmup)
-    if autotune:
+    if tiles:
+        ctx.set_tiles(tiles[0], tiles[1], 256)
+    elif autotune:
         ctx.autotune()
     ctx.enable_timing(True)
     import torch
@@ -89,6 +116,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--tiles", type=str, default=None,
+                    help="face tile BXxBY for both forms instead of the autotuner's choice")
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="only run a plain 1 GiB device-to-device copy 5 times (the known-size "
+                         "kernel that scales the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the PonD step is built and timed on a single MI355X; "
@@ -101,6 +133,15 @@ def main():
     if not torch.cuda.is_available():
         raise RuntimeError("bench.py needs a GPU")
     torch.cuda.set_device(0)
+    if args.calibrate_copy:
+        n = 1 << 28  # 2^28 floats = 1 GiB read + 1 GiB written per copy
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
     from paper_2203_05477_amd import pond
     from paper_2203_05477_amd import workloads as W
 
@@ -110,12 +151,13 @@ def main():
     cfg64, _ = W.double_mach(args.nx, args.ny, tol=tol64)
     ncell = args.nx * args.ny
 
+    tiles = tuple(int(v) for v in args.tiles.split("x")) if args.tiles else None
     ctx32, st32, el32, kt32 = run_form(cfg32, fields, "mixed", args.warmup, args.steps,
-                                       autotune=not args.no_autotune)
+                                       autotune=not args.no_autotune, tiles=tiles)
     rec = {}
     if not args.no_fp64:
         ctx64, st64, el64, kt64 = run_form(cfg64, fields, "fp64", args.warmup, args.steps,
-                                           autotune=not args.no_autotune)
+                                           autotune=not args.no_autotune, tiles=tiles)
         U32, U64 = ctx32.conserved(), ctx64.conserved()
         l1 = [float(np.abs(U32[k] - U64[k]).sum() / np.abs(U64[k]).sum()) for k in range(4)]
         rec["fp64_plain"] = {
@@ -136,6 +178,7 @@ def main():
     main_finals = (st32["faces"] - st32["tail_faces"]) / args.steps
     face_flops = main_iters * FLOPS_FACE_ITER[2] + main_finals * FLOPS_FACE_FINAL[2]
     face_main_ms = kt32["face"] - kt32["tail"]
+    traffic = measured_traffic()
     achieved = face_flops / (face_main_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
@@ -155,7 +198,10 @@ def main():
                    "tol": tol32, "cfl": cfg32["cfl"], "mu": cfg32["mu"],
                    "steps_from_t0": args.warmup + args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
-                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS, "traffic": None,
+                     "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
+                     "traffic": traffic["bytes_per_launch"] if traffic else None,
+                     "traffic_unit": "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
+                     "traffic_tiles": traffic["tiles"] if traffic else None,
                      "kernel": "face_kernel_2d<float>", "kernel_ms": face_main_ms,
                      "flop_per_launch": face_flops},
         "cell_updates": st32["cell_updates"],
