@@ -1142,12 +1142,36 @@ PD void wave_fence()
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 }
 
-// sum over the 16 lanes of a group (butterfly: every lane ends with the same value)
+// lane permutations inside rows of 16 lanes (DPP): quad_perm [1,0,3,2] and [2,3,0,1]
+// (xor 1, xor 2), row_half_mirror (lane i <-> 7 - i in each half-row), row_mirror
+// (i <-> 15 - i). Callers run with every lane of the wave active.
+constexpr int DPP_XOR1 = 0xB1, DPP_XOR2 = 0x4E, DPP_HALF_MIRROR = 0x141, DPP_MIRROR = 0x140;
+
+template <int CTRL>
+PD float dpp(float v)
+{
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+
+template <int CTRL>
+PD double dpp(double v)
+{
+    const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b & 0xffffffffull), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(unsigned)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double((long long)(((unsigned long long)(unsigned)hi << 32) | (unsigned)lo));
+}
+
+// sum over the 16 lanes of a group: quads first, then pairs of quads, then the two
+// halves; each stage adds the same two operands in every lane, so all 16 lanes end with
+// the same bits
 template <typename R>
 PD R group_sum(R v)
 {
-#pragma unroll
-    for (int o = 1; o < 16; o <<= 1) v += __shfl_xor(v, o, 16);
+    v += dpp<DPP_XOR1>(v);
+    v += dpp<DPP_XOR2>(v);
+    v += dpp<DPP_HALF_MIRROR>(v);
+    v += dpp<DPP_MIRROR>(v);
     return v;
 }
 
