@@ -202,7 +202,7 @@ def main():
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_unit": "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "traffic_tiles": traffic["tiles"] if traffic else None,
-                     "kernel": "face_kernel_2d<float>", "kernel_ms": face_main_ms,
+                     "kernel": "face_kernel_2d<float, 0>", "kernel_ms": face_main_ms,
                      "flop_per_launch": face_flops},
         "cell_updates": st32["cell_updates"],
         "converged_fraction": st32["converged_cell_updates"] / max(st32["cell_updates"], 1),

@@ -137,17 +137,26 @@ hipError_t launch_face(pond_ctx *c, int bx, int by)
     if (D == 1) {
         int span = (bx == c->bx) ? c->tube_span : compute_span(c, bx);
         size_t lds = face_lds_bytes(c, bx, 1, span);
-        face_kernel_1d<R><<<blocks(c->P.nface, bx), bx, lds, c->stream>>>(c->P, S, span);
+        if (c->P.limiter == POND_LIM_MINMOD)
+            face_kernel_1d<R, 1><<<blocks(c->P.nface, bx), bx, lds, c->stream>>>(c->P, S, span);
+        else
+            face_kernel_1d<R, 0><<<blocks(c->P.nface, bx), bx, lds, c->stream>>>(c->P, S, span);
     } else {
         dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
         size_t lds = face_lds_bytes(c, bx, by, 0);
-        face_kernel_2d<R><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        if (c->P.limiter == POND_LIM_MINMOD)
+            face_kernel_2d<R, 1><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        else
+            face_kernel_2d<R, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         if (c->ev) (void)hipEventRecord(c->ev[3], c->stream);
         if (c->P.iter_split > 0) {
             // 16 faces per block; enough blocks for every listed face in one pass
             const int64_t most = std::max<int64_t>(c->P.nfx, c->P.nface - c->P.nfx);
             dim3 tgrid((unsigned)std::min<int64_t>(blocks(most, 16), 2048), 2);
-            face_tail_kernel_2d<R><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+            if (c->P.limiter == POND_LIM_MINMOD)
+                face_tail_kernel_2d<R, 1><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+            else
+                face_tail_kernel_2d<R, 0><<<tgrid, 256, 0, c->stream>>>(c->P, S);
         }
     }
     return hipGetLastError();

@@ -771,7 +771,7 @@ struct FaceCount {
 };
 
 // 1D face f with LDS stencil indices idx = {L, R, L-1, R+1}
-template <typename R>
+template <typename R, int LIM>
 PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[4], int64_t f,
                 double dt, double dx, FaceCount &cnt)
 {
@@ -796,8 +796,8 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
         ++it;
         R s = sqrt(T), inv_s = R(1) / s;
         R qf[4], qg[4];
-        recon_1d<R, false>(L, NT, idx, u[0], s, inv_s, hdx, P.limiter, qf);
-        recon_1d<R, true>(L, NT, idx, u[0], s, inv_s, hdx, P.limiter, qg);
+        recon_1d<R, false>(L, NT, idx, u[0], s, inv_s, hdx, LIM, qf);
+        recon_1d<R, true>(L, NT, idx, u[0], s, inv_s, hdx, LIM, qg);
         moments_1d(qf, mf, 4);
         moments_1d(qg, mg, 3);
         R rho = mf[0];
@@ -871,7 +871,7 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
     S.fiter[f] = it | ((conv ? 0 : 1) << 16) | ((failed ? 1 : 0) << 17);
 }
 
-template <typename R, int AXIS>
+template <typename R, int AXIS, int LIM>
 PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[2], int sn,
                 int stn, int64_t f, double dt, FaceCount &cnt)
 {
@@ -900,8 +900,8 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
         {
             const int b0 = idx[0];
             const int sidx[8] = {b0, b0 + sn, b0 - sn, b0 + 2 * sn, b0 - stn, b0 + stn, b0 + sn - stn, b0 + sn + stn};
-            recon_2d<R, false, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, mf);
-            recon_2d<R, true, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, P.limiter, mg);
+            recon_2d<R, false, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
+            recon_2d<R, true, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
         }
         R rho = mf[0];
         R irho = R(1) / rho;
@@ -1018,7 +1018,7 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
 
 // 1D: one thread per face. Tubes are laid out in a padded index space with two ghost
 // slots on each side: face f of tube k has its stencil at padded slots f + 3k .. f + 3k + 3.
-template <typename R>
+template <typename R, int LIM>
 __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int tube_span)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -1059,7 +1059,7 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
         if (dt > 0.0) {
             const int base = (int)(f + 3 * (int64_t)k - vlo);
             const int idx[4] = {base + 1, base + 2, base, base + 3};
-            face_1d<R>(P, S, L, NT, idx, f, dt, S.dxk ? S.dxk[k] : P.dx, cnt);
+            face_1d<R, LIM>(P, S, L, NT, idx, f, dt, S.dxk ? S.dxk[k] : P.dx, cnt);
             nfc = 1;
         }
     }
@@ -1074,7 +1074,7 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
 
 // 2D: thread (i, j) owns x-face (i, j) (if j < ny) and y-face (i, j) (if i < nx).
 // LDS tile: cells i0-2 .. i0+BX, j0-2 .. j0+BY.
-template <typename R>
+template <typename R, int LIM>
 __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -1101,12 +1101,12 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
     unsigned long long nfaces = 0;
     if (i <= P.nx && j < P.ny) {
         const int idx[2] = {li(i - 1, j), li(i, j)};
-        face_2d<R, 0>(P, S, L, NT, idx, 1, TX, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
+        face_2d<R, 0, LIM>(P, S, L, NT, idx, 1, TX, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
         ++nfaces;
     }
     if (i < P.nx && j <= P.ny) {
         const int idx[2] = {li(i, j - 1), li(i, j)};
-        face_2d<R, 1>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
+        face_2d<R, 1, LIM>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
         ++nfaces;
     }
     stat_add(S.stats, ST_FACES, nfaces);
@@ -1202,7 +1202,7 @@ PD void tail_cell(const Params &P, int64_t f, int q, int &ci, int &cj)
 // One face per 16-lane group. Every lane of the wave runs every instruction of the
 // iteration (a group that is done, or has no face, computes and discards), so the cross-lane
 // sums and the LDS exchange never run under a partial execution mask.
-template <typename R, int AXIS>
+template <typename R, int AXIS, int LIM>
 PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e, bool has,
                   int q, double dt, double t, FaceCount &cnt)
 {
@@ -1302,8 +1302,8 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         auto recon = [&](const R *v) {
             const R A = up ? v[0] - v[2] : v[0] - v[1];
             const R B = up ? v[1] - v[0] : v[2] - v[0];
-            const R o = v[0] + off * limit(A, B, P.limiter);
-            return o + offt * limit(v[0] - v[3], v[4] - v[0], P.limiter);
+            const R o = v[0] + off * limit(A, B, LIM);
+            return o + offt * limit(v[0] - v[3], v[4] - v[0], LIM);
         };
         const R pfn = recon(vf), pgn = recon(vg);
         const R wf = wgt * pfn;
@@ -1414,7 +1414,7 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
     wave_fence(); // the records are rebuilt for the group's next face
 }
 
-template <typename R>
+template <typename R, int LIM>
 __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
 {
     __shared__ R lds[16 * TAIL_GROUP];
@@ -1434,9 +1434,9 @@ __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
         const bool has = k < count;
         const int64_t e = base + (has ? k : 0);
         if (axis == 0)
-            tail_face<R, 0>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 0, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
         else
-            tail_face<R, 1>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 1, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
     }
     stat_add(S.stats, ST_ITERS, cnt.iters);
     stat_add(S.stats, ST_NONCONV, cnt.nonconv);

@@ -101,6 +101,27 @@ def test_double_mach_small_fp64(orc, split):
     _print("dmr", err=e.max(), fallback=o.last["nonphysical"])
 
 
+@pytest.mark.parametrize("dim", [1, 2])
+def test_minmod_limiter_fp64(orc, dim):
+    """The minmod limiter (a separate kernel instantiation): 1D shock tube and 2D double
+    Mach reflection against the oracle."""
+    if dim == 1:
+        cfg, f = W.shock_tube(200)
+        steps = 120
+    else:
+        cfg, f = W.double_mach(64, 16)
+        steps = 20
+    cfg["limiter"] = "minmod"
+    _print("case", name="minmod", dim=dim)
+    g, o = _pair(orc, cfg, f)
+    for _ in range(steps):
+        o.step()
+        g.step(1)
+    e = _relerr(g.conserved(), o.conserved())
+    _print("minmod", dim=dim, err=e.max())
+    assert e.max() <= TOL64
+
+
 def test_uniform_state_is_kept_gpu(orc):
     from paper_2203_05477_amd import pond
 
