@@ -1543,16 +1543,26 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
     bool all_conv = true;
     R mfo[10], mgo[10];
     const double dxc = (D == 1 && S.dxk) ? S.dxk[k] : P.dx;
+    // The update of Sec. III.B.2 is linear in the populations, and the new state keeps only
+    // their moments of degree <= 3 (f) and <= 2 (g) in the cell frame, so it is done on those
+    // moments (mu_a = sum_i W_i p_i c_i^a, dimensionless, in the old cell frame):
+    //   mu' = A mu(f~) + Bc mu(f_eq) - sum_faces (dt/dx_n) sgn (s mu_{a+e_n}(q) + u_n mu_a(q)),
+    // q the face populations in the cell frame. With the Gauss-Hermite nodes (exact to degree
+    // 7 per axis) these equal the sums over the Q populations exactly; the degree-4 moments
+    // of the degree-3 expansion q follow from E[c^4] = 3, E[c^4 He_2] = 12, E[c^3 He_1] = 3.
     if (D == 1) {
         R h[4] = {(R)rho, R(0), S.H[c], S.H[n + c]};
         R hg[4] = {(R)(geq - T * (double)h[2]), S.H[2 * n + c], S.H[3 * n + c], R(0)};
-        R pf[4], pg[4];
-        eval_1d(h, pf, 3);
-        eval_1d(hg, pg, 2);
-        for (int i = 0; i < 4; ++i) {
-            pf[i] = A * pf[i] + Bc * (R)rho;
-            pg[i] = A * pg[i] + Bc * (R)geq;
+        h2mu_1d(h, mfo);
+        h2mu_1d(hg, mgo);
+        for (int q = 0; q < 4; ++q) {
+            mfo[q] *= A;
+            mgo[q] *= A;
         }
+        mfo[0] += Bc * (R)rho;
+        mfo[2] += Bc * (R)rho;
+        mgo[0] += Bc * (R)geq;
+        mgo[2] += Bc * (R)geq;
         const int64_t fl = c + k; // left face of this cell (tube k)
         for (int side = 0; side < 2; ++side) {
             const int64_t f = fl + side;
@@ -1561,29 +1571,32 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             R r = sqrt(fT) * inv_su, d = (fu - ux) * inv_su;
             R hf[4] = {S.F[2 * nf + f], S.F[3 * nf + f], S.F[4 * nf + f], S.F[5 * nf + f]};
             R hgf[4] = {S.F[6 * nf + f], S.F[7 * nf + f], S.F[8 * nf + f], R(0)};
-            R mu[4], q[4];
+            R mu[4], mg[4];
             h2mu_1d(hf, mu);
             shift_1d(mu, r, d, 4);
             mu2h_1d(mu, hf);
-            eval_1d(hf, q, 3);
-            h2mu_1d(hgf, mu);
-            shift_1d(mu, r, d, 3);
-            mu2h_1d(mu, hgf);
-            R qg[4];
-            eval_1d(hgf, qg, 2);
+            h2mu_1d(hf, mu);
+            const R mu4 = R(3) * hf[0] + R(12) * hf[2];
+            h2mu_1d(hgf, mg);
+            shift_1d(mg, r, d, 3);
+            mg[3] = R(0);
+            mu2h_1d(mg, hgf);
+            hgf[3] = R(0);
+            h2mu_1d(hgf, mg);
             const R kf = (R)(dt / dxc) * sgn;
-            for (int i = 0; i < 4; ++i) {
-                R v = su * node<R>(i) + ux;
-                pf[i] -= kf * v * q[i];
-                pg[i] -= kf * v * qg[i];
-            }
+            const R ks = kf * su, ku = kf * ux;
+            mfo[0] -= ks * mu[1] + ku * mu[0];
+            mfo[1] -= ks * mu[2] + ku * mu[1];
+            mfo[2] -= ks * mu[3] + ku * mu[2];
+            mfo[3] -= ks * mu4 + ku * mu[3];
+            mgo[0] -= ks * mg[1] + ku * mg[0];
+            mgo[1] -= ks * mg[2] + ku * mg[1];
+            mgo[2] -= ks * mg[3] + ku * mg[2];
             double fl3[4];
             face_flux<1, R>(P, S, f, 0, fl3);
             for (int q3 = 0; q3 < 3; ++q3) dU[q3] -= (dt / dxc) * (double)sgn * fl3[q3];
             all_conv = all_conv && !(S.fiter[f] >> 16);
         }
-        moments_1d(pf, mfo, 4);
-        moments_1d(pg, mgo, 3);
     } else {
         const int i = (int)(c % P.nx), j = (int)(c / P.nx);
         R h[10] = {(R)rho, R(0), R(0)};
@@ -1591,14 +1604,18 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
         R hg[10];
         hg[0] = (R)(geq - T * ((double)h[3] + (double)h[5]));
         for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
-        R pf[16], pg[16];
-        eval_2d(h, pf, 3);
-        eval_2d(hg, pg, 2);
+        h2mu_2d(h, mfo, 10);
+        h2mu_2d(hg, mgo, 6);
 #pragma unroll
-        for (int q = 0; q < 16; ++q) {
-            pf[q] = A * pf[q] + Bc * (R)rho;
-            pg[q] = A * pg[q] + Bc * (R)geq;
-        }
+        for (int q = 0; q < 10; ++q) mfo[q] *= A;
+#pragma unroll
+        for (int q = 0; q < 6; ++q) mgo[q] *= A;
+        mfo[0] += Bc * (R)rho;
+        mfo[3] += Bc * (R)rho;
+        mfo[5] += Bc * (R)rho;
+        mgo[0] += Bc * (R)geq;
+        mgo[3] += Bc * (R)geq;
+        mgo[5] += Bc * (R)geq;
 #pragma unroll 1
         for (int side = 0; side < 4; ++side) {
             const int axis = side >> 1;
@@ -1608,30 +1625,65 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             const R sgn = hi ? R(1) : R(-1);
             R fux = S.F[f], fuy = S.F[nf + f], fT = S.F[2 * nf + f];
             R r = sqrt(fT) * inv_su, dx = (fux - ux) * inv_su, dy = (fuy - uy) * inv_su;
-            R hf[10], mu[10], q[16];
+            R hf[10], mu[10], hgf[10], mg[10];
 #pragma unroll
             for (int m = 0; m < 10; ++m) hf[m] = S.F[(3 + m) * nf + f];
+#pragma unroll
+            for (int m = 0; m < 6; ++m) hgf[m] = S.F[(13 + m) * nf + f];
+            // face populations in the cell frame: coefficients, then raw moments
             h2mu_2d(hf, mu, 10);
             shift_2d(mu, r, dx, dy, 10);
             mu2h_2d(mu, hf, 10);
-            eval_2d(hf, q, 3);
+            h2mu_2d(hf, mu, 10);
+            h2mu_2d(hgf, mg, 6);
+            shift_2d(mg, r, dx, dy, 6);
+            mu2h_2d(mg, hgf, 6);
+#pragma unroll
+            for (int m = 6; m < 10; ++m) hgf[m] = R(0);
+            h2mu_2d(hgf, mg, 10);
             const R kf = (R)(dt / (axis ? P.dy : P.dx)) * sgn;
-            const R ua = axis ? uy : ux;
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                R v = su * node<R>(axis ? (m >> 2) : (m & 3)) + ua;
-                pf[m] -= kf * v * q[m];
-            }
-#pragma unroll
-            for (int m = 0; m < 6; ++m) hf[m] = S.F[(13 + m) * nf + f];
-            h2mu_2d(hf, mu, 6);
-            shift_2d(mu, r, dx, dy, 6);
-            mu2h_2d(mu, hf, 6);
-            eval_2d(hf, q, 2);
-#pragma unroll
-            for (int m = 0; m < 16; ++m) {
-                R v = su * node<R>(axis ? (m >> 2) : (m & 3)) + ua;
-                pg[m] -= kf * v * q[m];
+            const R ks = kf * su, ku = kf * (axis ? uy : ux);
+            // degree-4 moments of the f expansion that the normal flux needs
+            const R m22 = hf[0] + R(2) * (hf[3] + hf[5]);
+            const R m31 = R(3) * hf[4]; // mu_31 = mu_13 = 3 h11
+            if (axis == 0) {
+                const R m40 = R(3) * hf[0] + R(12) * hf[3];
+                // alpha + e_x: 00->10 10->20 01->11 20->30 11->21 02->12 30->40 21->31 12->22 03->13
+                mfo[0] -= ks * mu[1] + ku * mu[0];
+                mfo[1] -= ks * mu[3] + ku * mu[1];
+                mfo[2] -= ks * mu[4] + ku * mu[2];
+                mfo[3] -= ks * mu[6] + ku * mu[3];
+                mfo[4] -= ks * mu[7] + ku * mu[4];
+                mfo[5] -= ks * mu[8] + ku * mu[5];
+                mfo[6] -= ks * m40 + ku * mu[6];
+                mfo[7] -= ks * m31 + ku * mu[7];
+                mfo[8] -= ks * m22 + ku * mu[8];
+                mfo[9] -= ks * m31 + ku * mu[9];
+                mgo[0] -= ks * mg[1] + ku * mg[0];
+                mgo[1] -= ks * mg[3] + ku * mg[1];
+                mgo[2] -= ks * mg[4] + ku * mg[2];
+                mgo[3] -= ks * mg[6] + ku * mg[3];
+                mgo[4] -= ks * mg[7] + ku * mg[4];
+                mgo[5] -= ks * mg[8] + ku * mg[5];
+            } else {
+                const R m04 = R(3) * hf[0] + R(12) * hf[5];
+                // alpha + e_y: 00->01 10->11 01->02 20->21 11->12 02->03 30->31 21->22 12->13 03->04
+                mfo[0] -= ks * mu[2] + ku * mu[0];
+                mfo[1] -= ks * mu[4] + ku * mu[1];
+                mfo[2] -= ks * mu[5] + ku * mu[2];
+                mfo[3] -= ks * mu[7] + ku * mu[3];
+                mfo[4] -= ks * mu[8] + ku * mu[4];
+                mfo[5] -= ks * mu[9] + ku * mu[5];
+                mfo[6] -= ks * m31 + ku * mu[6];
+                mfo[7] -= ks * m22 + ku * mu[7];
+                mfo[8] -= ks * m31 + ku * mu[8];
+                mfo[9] -= ks * m04 + ku * mu[9];
+                mgo[0] -= ks * mg[2] + ku * mg[0];
+                mgo[1] -= ks * mg[4] + ku * mg[1];
+                mgo[2] -= ks * mg[5] + ku * mg[2];
+                mgo[3] -= ks * mg[7] + ku * mg[3];
+                mgo[4] -= ks * mg[8] + ku * mg[4];
+                mgo[5] -= ks * mg[9] + ku * mg[5];
             }
             double fl4[4];
             face_flux<2, R>(P, S, f, axis, fl4);
@@ -1639,8 +1691,6 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             for (int q4 = 0; q4 < 4; ++q4) dU[q4] -= kd * fl4[q4];
             all_conv = all_conv && !(S.fiter[f] >> 16);
         }
-        moments_2d(pf, mfo, 10);
-        moments_2d(pg, mgo, 6);
     }
     // FP64 conserved update (flux form: exact telescoping between neighbours)
     double Un[4];
