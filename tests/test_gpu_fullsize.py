@@ -1,0 +1,127 @@
+"""GPU parity at the full sizes of the 2D workloads, in the launch configuration the
+benchmark times (autotuned face tiles, default hand-over to the tail kernel), for the first
+steps, against the FP64 oracle run on the host's cores.
+
+FP64: element-wise to 1e-12 while every face ends its iteration the same way on both sides;
+a face whose iteration sits at the iteration cap may end differently under another
+rounding order, and then only the cells next to it may differ (the comparison stops
+there). Mixed precision: relative L1 distance to the oracle below 1e-4 per conserved field.
+"""
+import numpy as np
+import pytest
+
+from paper_2203_05477_amd import workloads as W
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-12
+
+
+def _face_cells(cfg, faces):
+    nx = cfg["nx"]
+    nfx = (nx + 1) * cfg["ny"]
+    cells = set()
+    for k in faces:
+        if k < nfx:
+            i, j = k % (nx + 1), k // (nx + 1)
+            cells.update({(j, i - 1), (j, i)})
+        else:
+            i, j = (k - nfx) % nx, (k - nfx) // nx
+            cells.update({(j - 1, i), (j, i)})
+    return cells
+
+
+def _bench_context(cfg, f, precision):
+    from paper_2203_05477_amd import pond
+
+    g = pond.Context(cfg, f, precision=precision)
+    g.autotune()
+    return g
+
+
+def _oracle(orc, cfg, f):
+    return orc.Sim(cfg, f["rho"], f["ux"], f["uy"], f["p"])
+
+
+def _lockstep_fp64(orc, cfg, f, steps, name):
+    g = _bench_context(cfg, f, "fp64")
+    o = _oracle(orc, cfg, f)
+    nx, ny = cfg["nx"], cfg["ny"]
+    compared = 0
+    for k in range(steps):
+        o.step()
+        g.step(1)
+        assert g.time()[0] == pytest.approx(o.t, rel=1e-14)
+        Ug, Uo = g.conserved(), o.conserved()
+        scale = np.abs(Uo).max(axis=1, keepdims=True)
+        scale[1:-1] = np.abs(Uo[1:-1]).max()
+        d = (np.abs(Ug - Uo) / scale).max(axis=0).reshape(ny, nx)
+        split = np.nonzero((g.face_iters() > 0) != (o.face_iters() > 0))[0]
+        print(name, "step", k, "max rel err", d.max(), "split faces", len(split), flush=True)
+        if len(split) == 0:
+            assert d.max() <= TOL64, (k, d.max())
+            compared += 1
+            continue
+        off = {tuple(c) for c in np.argwhere(d > TOL64)}
+        assert off <= _face_cells(cfg, split), (k, sorted(off - _face_cells(cfg, split))[:5])
+        break
+    return compared
+
+
+def test_double_mach_full_size_fp64(orc):
+    """1920 x 480 double Mach reflection, first 3 steps."""
+    cfg, f = W.double_mach(1920, 480)
+    print("case dmr 1920x480 fp64", flush=True)
+    assert _lockstep_fp64(orc, cfg, f, 3, "dmr") >= 1
+
+
+def test_shocked_interface_full_size_fp64(orc):
+    """2048 x 512 shocked interface, first 3 steps."""
+    cfg, f = W.shocked_interface(tol=1e-13)
+    print("case shocked interface 2048x512 fp64", flush=True)
+    assert _lockstep_fp64(orc, cfg, f, 3, "shocked_interface") >= 1
+
+
+def test_jet_full_size_fp64(orc):
+    """2048 x 2048 Mach-80 jet: the first step element-wise; in the second, the front of the
+    jet one cell inside the inflow boundary reaches T < 0 (with mu = 1e-3 a mean free path
+    spans several cells of this grid, and the first Mach-80 shock is not resolved by the
+    third-order closure), in the oracle as on the GPU: the same cells fail on both sides."""
+    cfg, f = W.jet(tol=1e-13)
+    print("case jet 2048x2048 fp64", flush=True)
+    g = _bench_context(cfg, f, "fp64")
+    o = _oracle(orc, cfg, f)
+    o.step()
+    g.step(1)
+    Ug, Uo = g.conserved(), o.conserved()
+    scale = np.abs(Uo).max(axis=1, keepdims=True)
+    scale[1:-1] = np.abs(Uo[1:-1]).max()
+    err = (np.abs(Ug - Uo) / scale).max()
+    print("jet step 0 max rel err", err, flush=True)
+    assert err <= TOL64
+    o.step()
+    st = g.step(1, check=False)
+    To = o.fields()[3]
+    Tg = g.moments()[3]
+    bad_o = set(np.nonzero(~(To > 0))[0].tolist())
+    bad_g = set(np.nonzero(~(Tg > 0))[0].tolist())
+    print("jet step 1 non-physical cells: oracle", len(bad_o), "gpu", len(bad_g), "status", st["status"], flush=True)
+    assert len(bad_o) > 0 and bad_g == bad_o
+    assert st["failed_instances"] == 1
+
+
+def test_double_mach_full_size_mixed(orc):
+    """1920 x 480 double Mach reflection in mixed precision (FP32 iteration tolerance
+    1e-5), 5 steps: relative L1 distance to the FP64 oracle (tolerance 1e-10) below 1e-4."""
+    cfg, f = W.double_mach(1920, 480, tol=W.TOL_FP32)
+    cfo, _ = W.double_mach(1920, 480, tol=W.TOL_FP64)
+    print("case dmr 1920x480 mixed", flush=True)
+    g = _bench_context(cfg, f, "mixed")
+    o = _oracle(orc, cfo, f)
+    for _ in range(5):
+        o.step()
+        g.step(1)
+    Ug, Uo = g.conserved(), o.conserved()
+    l1 = np.abs(Ug - Uo).sum(axis=1) / np.abs(Uo).sum(axis=1)
+    print("dmr mixed rel L1", l1, flush=True)
+    assert np.all(l1 < 1e-4)
