@@ -62,10 +62,12 @@ def measured_traffic():
     return rec
 
 
-def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True, tiles=None):
+def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True, tiles=None, mlp=None):
     from paper_2203_05477_amd import pond
 
     ctx = pond.Context(cfg, fields, precision=precision, seed=seed)
+    if mlp is not None:
+        ctx.load_mlp(mlp, hard_iters=2)
     if warmup:
         ctx.step(warmup)
     if tiles:
@@ -116,6 +118,7 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-seed form")
     ap.add_argument("--tiles", type=str, default=None,
                     help="face tile BXxBY for both forms instead of the autotuner's choice")
     ap.add_argument("--calibrate-copy", action="store_true",
@@ -154,12 +157,42 @@ def main():
     tiles = tuple(int(v) for v in args.tiles.split("x")) if args.tiles else None
     ctx32, st32, el32, kt32 = run_form(cfg32, fields, "mixed", args.warmup, args.steps,
                                        autotune=not args.no_autotune, tiles=tiles)
+    # learned seed + FP32: a network trained on the GPU on face frames the solver itself
+    # produced (first 300 steps of the same problem on a 4x coarser grid), then the same
+    # timed run with the network seeding the faces that needed two or more iterations
+    learned, Ul = None, None
+    if not args.no_learned:
+        from paper_2203_05477_amd import learned_seed as LS
+
+        t0 = time.perf_counter()
+        cfgh, fh = W.double_mach(args.nx // 4, args.ny // 4, tol=tol32)
+        data = LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2)
+        net, losses, nsamp = LS.train([data], epochs=20, batch=4096, lr=2e-3)
+        t_train = time.perf_counter() - t0
+        ctxl, stl, ell, ktl = run_form(cfg32, fields, "mixed", args.warmup, args.steps,
+                                       autotune=not args.no_autotune, tiles=tiles, seed="mlp", mlp=net)
+        Ul = ctxl.conserved()
+        learned = {
+            "value": stl["converged_cell_updates"] / ell / 1e6,
+            "ms_per_step": 1e3 * ell / args.steps,
+            "mean_iters": stl["iters_total"] / max(stl["faces"], 1),
+            "nonconverged_faces": stl["nonconverged"],
+            "kernel_ms": {"seed": ktl["seed"], "face": ktl["face"], "face_tail": ktl["tail"],
+                          "cell": ktl["cell"]},
+            "train": {"samples": nsamp, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+                      "seconds": t_train},
+        }
+        ctxl.close()
+
     rec = {}
     if not args.no_fp64:
         ctx64, st64, el64, kt64 = run_form(cfg64, fields, "fp64", args.warmup, args.steps,
                                            autotune=not args.no_autotune, tiles=tiles)
         U32, U64 = ctx32.conserved(), ctx64.conserved()
         l1 = [float(np.abs(U32[k] - U64[k]).sum() / np.abs(U64[k]).sum()) for k in range(4)]
+        if learned is not None:
+            learned["rel_l1_vs_fp64"] = {q: float(np.abs(Ul[k] - U64[k]).sum() / np.abs(U64[k]).sum())
+                                         for k, q in enumerate(("rho", "rho_u", "rho_v", "rho_E"))}
         rec["fp64_plain"] = {
             "value": st64["converged_cell_updates"] / el64 / 1e6,
             "ms_per_step": 1e3 * el64 / args.steps,
@@ -216,6 +249,8 @@ def main():
         "t_end": st32["t_max"],
     }
     line.update(rec)
+    if learned is not None:
+        line["learned_mixed"] = learned
     ctx32.close()
     if not args.no_cpu_baseline:
         cfgc, fc = W.double_mach(args.nx, args.ny, tol=tol64)

@@ -106,6 +106,45 @@ State<R> state_of(pond_ctx *c)
 
 unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// 2D face tiles the autotuner tries (the first is the default)
+const std::pair<int, int> kTiles2D[] = {{8, 8}, {16, 4}, {16, 8}, {16, 16}, {32, 8}, {64, 4}, {32, 2}};
+
+// entries one sub-list of the tail list must hold for a face launch with bx x by tiles: the
+// waves of its slot (the global wave index modulo NSLOT) times 64 faces of one axis
+int64_t tail_cap_for(const pond_ctx *c, int bx, int by)
+{
+    const int64_t nb = (int64_t)blocks(c->P.nx + 1, bx) * blocks(c->P.ny + 1, by);
+    const int64_t waves = nb * ((bx * by + 63) / 64);
+    return 64 * ((waves + NSLOT - 1) / NSLOT);
+}
+
+// grow the tail list for a launch shape that needs more room (between steps)
+bool ensure_tail(pond_ctx *c, int bx, int by)
+{
+    const int64_t need = tail_cap_for(c, bx, by);
+    if (need <= c->P.tail_cap) return true;
+    if (hipStreamSynchronize(c->stream) != hipSuccess) return false;
+    const int64_t n = 2 * NSLOT * need;
+    int *f = nullptr, *m = nullptr;
+    void *st = nullptr;
+    if (hipMalloc(&f, sizeof(int) * n) != hipSuccess || hipMalloc(&m, sizeof(int) * n) != hipSuccess ||
+        hipMalloc(&st, c->rsize * 6 * n) != hipSuccess) {
+        (void)hipFree(f);
+        (void)hipFree(m);
+        (void)hipFree(st);
+        return false;
+    }
+    (void)hipFree(c->tail_f);
+    (void)hipFree(c->tail_meta);
+    (void)hipFree(c->tail_s);
+    c->tail_f = f;
+    c->tail_meta = m;
+    c->tail_s = st;
+    c->P.tail_cap = (int)need;
+    c->P.tail_n = n;
+    return true;
+}
+
 size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
 {
     if (c->D == 1) return (size_t)(bx + 3 + 3 * span) * Layout<1>::NL * c->rsize;
@@ -150,9 +189,8 @@ hipError_t launch_face(pond_ctx *c, int bx, int by)
             face_kernel_2d<R, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         if (c->ev) (void)hipEventRecord(c->ev[3], c->stream);
         if (c->P.iter_split > 0) {
-            // 16 faces per block; enough blocks for every listed face in one pass
-            const int64_t most = std::max<int64_t>(c->P.nfx, c->P.nface - c->P.nfx);
-            dim3 tgrid((unsigned)std::min<int64_t>(blocks(most, 16), 2048), 2);
+            // 4 blocks of 16 faces per sub-list and axis
+            dim3 tgrid(NSLOT * 4, 2);
             if (c->P.limiter == POND_LIM_MINMOD)
                 face_tail_kernel_2d<R, 1><<<tgrid, 256, 0, c->stream>>>(c->P, S);
             else
@@ -390,10 +428,14 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         alloc((void **)&c->dxk, sizeof(double) * P.n_inst);
     }
     if (c->D == 2) {
-        alloc((void **)&c->tail_f, sizeof(int) * nf);
-        alloc((void **)&c->tail_meta, sizeof(int) * nf);
-        alloc(&c->tail_s, c->rsize * 6 * nf);
-        alloc((void **)&c->tail_count, sizeof(int) * 2);
+        int64_t cap = 0;
+        for (const auto &t : kTiles2D) cap = std::max(cap, tail_cap_for(c, t.first, t.second));
+        P.tail_cap = (int)cap;
+        P.tail_n = 2 * NSLOT * cap;
+        alloc((void **)&c->tail_f, sizeof(int) * P.tail_n);
+        alloc((void **)&c->tail_meta, sizeof(int) * P.tail_n);
+        alloc(&c->tail_s, c->rsize * 6 * P.tail_n);
+        alloc((void **)&c->tail_count, sizeof(int) * 2 * NSLOT);
         P.iter_split = (cfg->precision == POND_FP64) ? 3 : 2;
     }
     if (!ok) {
@@ -729,6 +771,7 @@ pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_blo
     }
     int span = compute_span(c, bx);
     if (face_lds_bytes(c, bx, by, span) > 160 * 1024) return POND_EINVAL;
+    if (c->D == 2 && !ensure_tail(c, bx, by)) return POND_ENOMEM;
     c->bx = bx;
     c->by = by;
     c->cell_block = cell_block;
@@ -766,7 +809,7 @@ pond_status pond_autotune(pond_ctx *c)
     if (c->D == 1)
         cand = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
     else
-        cand = {{8, 8}, {16, 4}, {16, 8}, {16, 16}, {32, 8}, {64, 4}, {32, 2}};
+        cand.assign(std::begin(kTiles2D), std::end(kTiles2D));
     double best = 1e30;
     int bbx = c->bx, bby = c->by;
     hipEvent_t e0, e1;
@@ -1092,8 +1135,8 @@ pond_status pond_load_mlp(pond_ctx *c, const pond_mlp *m, int32_t hard_iters)
     if (!M.master) {
         pond_status s = mlp_alloc(M, 1);
         if (s != POND_OK) return s;
-        if (hipMalloc(&M.list, sizeof(int) * c->P.nface) != hipSuccess ||
-            hipMalloc(&M.count, sizeof(int)) != hipSuccess) {
+        if (hipMalloc(&M.list, sizeof(int) * NSLOT * slot_cap(c->P.nface)) != hipSuccess ||
+            hipMalloc(&M.count, sizeof(int) * NSLOT) != hipSuccess) {
             mlp_free(M);
             return POND_ENOMEM;
         }

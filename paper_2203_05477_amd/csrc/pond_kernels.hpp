@@ -41,6 +41,9 @@ struct Params {
     double bc_speed[2]; // per axis: fastest particle speed of the prescribed boundary states
     int iter_split;     // 2D: iterations done in the face kernel before a face moves to the
                         // tail kernel (0: the face kernel runs every face to the end)
+    int tail_cap;       // 2D: entries per sub-list of the tail list (one sub-list per axis
+                        // and slot); tail_n = 2 * NSLOT * tail_cap entries in all
+    int64_t tail_n;
     int vslots;         // copies of each instance's CFL-rate maximum (NSLOT for one
                         // instance, 1 for a batch, whose tubes spread the atomics anyway)
     int64_t ncell, nface, nfx;
@@ -63,12 +66,13 @@ struct State {
     int *err;
     int *inst_err;             // per instance: nonzero once a step produced an invalid cell
     // faces handed from the face kernel to the tail kernel (2D): face index, iteration
-    // state (u_x, u_y, T, and the frame two iterations back: 6 planes of R), and
-    // it | have_pp << 16 | restarted << 17. x-faces fill [0, nfx), y-faces [nfx, nface).
+    // state (u_x, u_y, T, and the frame two iterations back: 6 planes of tail_n R), and
+    // it | have_pp << 16 | restarted << 17. Entry (axis * NSLOT + slot) * tail_cap + pos:
+    // every wave appends to the sub-list of its slot.
     int *tail_f;
     R *tail_s;
     int *tail_meta;
-    int *tail_count;           // 2 counters (x-faces, y-faces), cleared by dt_kernel
+    int *tail_count;           // 2 x NSLOT sub-list lengths, cleared by dt_kernel
 };
 
 template <int D>
@@ -187,6 +191,8 @@ __global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_e
         m = v > m ? v : m;
         S.vmax[vmax_at(P, slot ^ 1, k, c)] = 0ull;
     }
+    if (k == 0 && S.tail_count)
+        for (int c = lane; c < 2 * NSLOT; c += 64) S.tail_count[c] = 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         unsigned long long w = __shfl_xor(m, o, 64);
@@ -206,10 +212,6 @@ __global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_e
     S.tstart[k] = t;
     S.dt[k] = dt;
     S.t[k] = t + dt;
-    if (k == 0 && S.tail_count) {
-        S.tail_count[0] = 0;
-        S.tail_count[1] = 0;
-    }
 }
 
 // ---------------------------------------------------------------------------------
@@ -947,19 +949,19 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
     if (!conv && !failed && !stopped && it < P.max_iter) {
         // this kernel's share of iterations is spent: the tail kernel continues the
         // same iteration from this state (it, frames, flags), with 16 lanes per face
-        const int64_t base = AXIS ? P.nfx : 0;
-        const int64_t cap = AXIS ? P.nface - P.nfx : P.nfx;
-        // one atomic per wave: every active lane here appends a face
+        // one atomic per wave, on the counter of the wave's own sub-list: every active
+        // lane here appends a face
+        const int sl = AXIS * NSLOT + (int)wave_slot();
         const unsigned long long mask = __ballot(1);
         const int lane = __lane_id();
         const int leader = __builtin_ctzll(mask);
         int first = 0;
-        if (lane == leader) first = atomicAdd(&S.tail_count[AXIS], __popcll(mask));
+        if (lane == leader) first = atomicAdd(&S.tail_count[sl], __popcll(mask));
         first = __shfl(first, leader, 64);
         const int64_t pos = first + __popcll(mask & ((1ull << lane) - 1ull));
-        if (pos < cap) { // always true: every face of the axis fits
-            const int64_t e = base + pos;
-            const int64_t nf = P.nface;
+        if (pos < P.tail_cap) { // always true: tail_cap covers every wave of the slot
+            const int64_t e = (int64_t)sl * P.tail_cap + pos;
+            const int64_t nf = P.tail_n;
             S.tail_f[e] = (int)f;
             S.tail_s[0 * nf + e] = u[0];
             S.tail_s[1 * nf + e] = u[1];
@@ -1206,7 +1208,7 @@ template <typename R, int AXIS, int LIM>
 PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e, bool has,
                   int q, double dt, double t, FaceCount &cnt)
 {
-    const int64_t nf = P.nface;
+    const int64_t nf = P.tail_n;
     const int64_t f = has ? S.tail_f[e] : 0;
     if (has && q < 8) {
         int ci, cj;
@@ -1424,12 +1426,14 @@ __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
     const int axis = blockIdx.y;
     const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
     R *rec = lds + grp * TAIL_GROUP, *coef = rec + TAIL_REC;
-    const int64_t base = axis ? P.nfx : 0;
-    const int64_t cap = axis ? P.nface - P.nfx : P.nfx;
-    const int64_t count = min((int64_t)S.tail_count[axis], cap);
+    // block b works on sub-list b mod NSLOT of its axis, beside the other blocks of it
+    const int sl = axis * NSLOT + (int)(blockIdx.x % NSLOT);
+    const int sub = blockIdx.x / NSLOT, nsub = gridDim.x / NSLOT;
+    const int64_t base = (int64_t)sl * P.tail_cap;
+    const int64_t count = min((int64_t)S.tail_count[sl], (int64_t)P.tail_cap);
     FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     // wave-uniform loop: a group without a face in this round takes part with has = false
-    for (int64_t k0 = (int64_t)blockIdx.x * 16; __any(k0 + grp < count); k0 += (int64_t)gridDim.x * 16) {
+    for (int64_t k0 = (int64_t)sub * 16; __any(k0 + grp < count); k0 += (int64_t)nsub * 16) {
         const int64_t k = k0 + grp;
         const bool has = k < count;
         const int64_t e = base + (has ? k : 0);
@@ -1451,7 +1455,7 @@ __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
 // clears the tail counters where no dt_kernel runs before a face kernel (the autotuner)
 __global__ void tail_reset_kernel(int *count)
 {
-    if (threadIdx.x < 2) count[threadIdx.x] = 0;
+    for (int c = threadIdx.x; c < 2 * NSLOT; c += blockDim.x) count[c] = 0;
 }
 
 // ---------------------------------------------------------------------------------

@@ -562,9 +562,19 @@ __global__ void mlp_pack_kernel(const float *master, __bf16 *wbf)
 // learned seed inside the step
 // ---------------------------------------------------------------------------------
 
+// Per-slot capacity of a list that the waves of a launch over n items (64 per wave) append
+// to: each wave appends to the sub-list of its slot (wave_slot), so that no counter is hit
+// by more than a handful of waves.
+inline int64_t slot_cap(int64_t n)
+{
+    const int64_t waves = 4 * ((n + 255) / 256); // 256-thread blocks
+
+    return 64 * ((waves + NSLOT - 1) / NSLOT);
+}
+
 // faces that took at least `hard` iterations in the previous step (or did not converge)
 template <typename R>
-__global__ void mlp_select_kernel(Params P, State<R> S, int hard, int *list, int *count)
+__global__ void mlp_select_kernel(Params P, State<R> S, int hard, int *list, int *count, int cap)
 {
     const int64_t f = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool take = false;
@@ -573,30 +583,35 @@ __global__ void mlp_select_kernel(Params P, State<R> S, int hard, int *list, int
         const int v = S.fiter[f];
         take = (S.dt[k] > 0.0) && (((v & 0xffff) >= hard) || ((v >> 16) & 1));
     }
-    // wave-aggregated append
+    // wave-aggregated append to the wave's sub-list
     unsigned long long m = __ballot(take);
     int nt = __popcll(m);
     int base = 0;
     const int lane = threadIdx.x & 63;
-    if (lane == 0 && nt) base = atomicAdd(count, nt);
+    const unsigned slot = wave_slot();
+    if (lane == 0 && nt) base = atomicAdd(&count[slot], nt);
     base = __shfl(base, 0, 64);
-    if (take) list[base + __popcll(m & ((1ull << lane) - 1ull))] = (int)f;
+    const int pos = base + __popcll(m & ((1ull << lane) - 1ull));
+    if (take && pos < cap) list[(int64_t)slot * cap + pos] = (int)f;
 }
 
 // features + network + seed write for the listed faces; one wave per 16 faces
+// block b works on sub-list b mod NSLOT, with the other blocks of that sub-list
 template <int D, typename R>
 __global__ __launch_bounds__(64) void mlp_seed_kernel(Params P, State<R> S, const __bf16 *wbf,
-                                                      const float *master, const int *list,
-                                                      const int *count)
+                                                      const float *master, const int *lists,
+                                                      const int *counts, int cap)
 {
     __shared__ float xs[16][MLP_IN + 1];
     __shared__ float rs[16][4];
     MlpRegs W;
     mlp_load_regs(wbf, master, W);
     const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
-    const int n = *count;
+    const int slot = blockIdx.x % NSLOT, sub = blockIdx.x / NSLOT, nsub = gridDim.x / NSLOT;
+    const int n = min(counts[slot], cap);
+    const int *list = lists + (int64_t)slot * cap;
     const int64_t nf = P.nface;
-    for (int t0 = blockIdx.x * 16; t0 < n; t0 += gridDim.x * 16) {
+    for (int t0 = sub * 16; t0 < n; t0 += nsub * 16) {
         if (l < 16) {
             if (t0 + l < n) {
                 float x[MLP_IN], ref[4];
@@ -650,10 +665,11 @@ inline void mlp_free(MlpDevice &M)
 template <int D, typename R>
 hipError_t mlp_seed_launch(const MlpDevice &M, const Params &P, const State<R> &S, hipStream_t st)
 {
-    hipError_t e = hipMemsetAsync(M.count, 0, sizeof(int), st);
+    hipError_t e = hipMemsetAsync(M.count, 0, sizeof(int) * NSLOT, st);
     if (e != hipSuccess) return e;
-    mlp_select_kernel<R><<<(unsigned)((P.nface + 255) / 256), 256, 0, st>>>(P, S, M.hard_iters, M.list, M.count);
-    mlp_seed_kernel<D, R><<<1024, 64, 0, st>>>(P, S, M.wbf, M.master, M.list, M.count);
+    const int cap = (int)slot_cap(P.nface);
+    mlp_select_kernel<R><<<(unsigned)((P.nface + 255) / 256), 256, 0, st>>>(P, S, M.hard_iters, M.list, M.count, cap);
+    mlp_seed_kernel<D, R><<<NSLOT * 4, 64, 0, st>>>(P, S, M.wbf, M.master, M.list, M.count, cap);
     return hipGetLastError();
 }
 
