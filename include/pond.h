@@ -175,6 +175,12 @@ pond_status pond_set_tiles(pond_ctx *ctx, int32_t bx, int32_t by, int32_t cell_b
 pond_status pond_get_tiles(const pond_ctx *ctx, int32_t *bx, int32_t *by, int32_t *cell_block);
 pond_status pond_autotune(pond_ctx *ctx);
 
+/* on != 0: pond_step replays two steps captured once as a HIP graph (kernel launches
+ * only; captured again when t_end, the step parity or any launch parameter changes)
+ * instead of launching every kernel; results are identical. Steps with timing enabled,
+ * and the last step of an odd count, are launched one by one. Default off. */
+pond_status pond_set_graph(pond_ctx *ctx, int32_t on);
+
 /* 2D: the face kernel runs each face's frame iteration (Sec. III.B.3) for at most k
  * iterations; faces still iterating then continue, from the same state, in a tail kernel
  * that gives every face 16 lanes instead of one (a wave otherwise runs as long as its

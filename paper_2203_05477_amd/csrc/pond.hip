@@ -55,7 +55,19 @@ struct pond_ctx {
     hipEvent_t *ev = nullptr;
     // learned seed
     MlpDevice mlp;
+    // optional replay of two captured steps (hipGraph); invalid after any change of launch
+    // parameters
+    int use_graph = 0;
+    hipGraphExec_t gexec = nullptr;
+    double g_tend = 0.0;
+    int g_slot = -1;
 };
+
+static void drop_graph(pond_ctx *c)
+{
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+}
 
 namespace {
 
@@ -512,7 +524,31 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
             c->evs.push_back(e);
         }
     }
-    for (int s = 0; s < nsteps; ++s) {
+    int s0 = 0;
+    if (c->use_graph && !c->timing && nsteps >= 2) {
+        if (!c->gexec || c->g_tend != t_end || c->g_slot != c->slot) {
+            drop_graph(c);
+            hipGraph_t g = nullptr;
+            HIPCHK(hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+            hipError_t e1 = step_once(c, t_end);
+            hipError_t e2 = step_once(c, t_end); // two steps: the step parity returns
+            hipError_t e3 = hipStreamEndCapture(c->stream, &g);
+            if (e1 != hipSuccess || e2 != hipSuccess || e3 != hipSuccess) {
+                if (g) (void)hipGraphDestroy(g);
+                return POND_EDEVICE;
+            }
+            hipError_t e4 = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+            (void)hipGraphDestroy(g);
+            if (e4 != hipSuccess) {
+                c->gexec = nullptr;
+                return POND_EDEVICE;
+            }
+            c->g_tend = t_end;
+            c->g_slot = c->slot;
+        }
+        for (; s0 + 2 <= nsteps; s0 += 2) HIPCHK(hipGraphLaunch(c->gexec, c->stream));
+    }
+    for (int s = s0; s < nsteps; ++s) {
         c->ev = c->timing ? &c->evs[(size_t)6 * s] : nullptr;
         HIPCHK(step_once(c, t_end));
     }
@@ -772,6 +808,7 @@ pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_blo
     int span = compute_span(c, bx);
     if (face_lds_bytes(c, bx, by, span) > 160 * 1024) return POND_EINVAL;
     if (c->D == 2 && !ensure_tail(c, bx, by)) return POND_ENOMEM;
+    drop_graph(c);
     c->bx = bx;
     c->by = by;
     c->cell_block = cell_block;
@@ -779,9 +816,18 @@ pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_blo
     return POND_OK;
 }
 
+pond_status pond_set_graph(pond_ctx *c, int32_t on)
+{
+    if (!c) return POND_EINVAL;
+    c->use_graph = on ? 1 : 0;
+    if (!on) drop_graph(c);
+    return POND_OK;
+}
+
 pond_status pond_set_iter_split(pond_ctx *c, int32_t k)
 {
     if (!c || k < 0) return POND_EINVAL;
+    drop_graph(c);
     if (c->D == 2) c->P.iter_split = k;
     return POND_OK;
 }
@@ -885,6 +931,7 @@ void pond_free(pond_ctx *c)
 {
     if (!c) return;
     (void)hipStreamSynchronize(c->stream);
+    drop_graph(c);
     free_all(c);
     for (auto &e : c->evs) (void)hipEventDestroy(e);
     if (c->own_stream) (void)hipStreamDestroy(c->own_stream);
@@ -1131,6 +1178,7 @@ pond_status pond_mlp_targets(pond_ctx *c, const float *X, const float *ref, floa
 pond_status pond_load_mlp(pond_ctx *c, const pond_mlp *m, int32_t hard_iters)
 {
     if (!c || !m || !m->dev.ready || hard_iters < 1) return POND_EINVAL;
+    drop_graph(c);
     MlpDevice &M = c->mlp;
     if (!M.master) {
         pond_status s = mlp_alloc(M, 1);

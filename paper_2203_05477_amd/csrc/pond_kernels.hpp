@@ -1772,7 +1772,10 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
         bits = (unsigned long long)__double_as_longlong(rate);
     }
     vmax_update<R>(P, S, 0, k, c < n, bits);
-    if (c < P.nface) S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
+    if (c < P.nface) {
+        S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
+        S.fiter[c] = 0; // read by the learned seed's selection before the first step
+    }
 }
 
 // rho, ux, uy, T planes from U

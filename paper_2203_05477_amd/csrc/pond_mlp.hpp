@@ -568,8 +568,12 @@ __global__ void mlp_pack_kernel(const float *master, __bf16 *wbf)
 inline int64_t slot_cap(int64_t n)
 {
     const int64_t waves = 4 * ((n + 255) / 256); // 256-thread blocks
-
     return 64 * ((waves + NSLOT - 1) / NSLOT);
+}
+
+__global__ void zero_ints_kernel(int *p, int n)
+{
+    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
 }
 
 // faces that took at least `hard` iterations in the previous step (or did not converge)
@@ -665,8 +669,8 @@ inline void mlp_free(MlpDevice &M)
 template <int D, typename R>
 hipError_t mlp_seed_launch(const MlpDevice &M, const Params &P, const State<R> &S, hipStream_t st)
 {
-    hipError_t e = hipMemsetAsync(M.count, 0, sizeof(int) * NSLOT, st);
-    if (e != hipSuccess) return e;
+    // cleared by a kernel, not a memset node, so that the sequence can be captured in a graph
+    zero_ints_kernel<<<1, 256, 0, st>>>(M.count, NSLOT);
     const int cap = (int)slot_cap(P.nface);
     mlp_select_kernel<R><<<(unsigned)((P.nface + 255) / 256), 256, 0, st>>>(P, S, M.hard_iters, M.list, M.count, cap);
     mlp_seed_kernel<D, R><<<NSLOT * 4, 64, 0, st>>>(P, S, M.wbf, M.master, M.list, M.count, cap);

@@ -108,6 +108,7 @@ def load(path: str | None = None):
                                ctypes.POINTER(ctypes.c_int32)]),
         "pond_autotune": (S, [_P]),
         "pond_set_iter_split": (S, [_P, ctypes.c_int32]),
+        "pond_set_graph": (S, [_P, ctypes.c_int32]),
         "pond_enable_timing": (S, [_P, ctypes.c_int32]),
         "pond_kernel_times": (S, [_P, _D]),
         "pond_free": (None, [_P]),
@@ -141,7 +142,7 @@ def exported_symbols():
             "pond_populations", "pond_nfaces", "pond_face_frames", "pond_set_face_frames",
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
-            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split",
+            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split", "pond_set_graph",
             "pond_enable_timing",
             "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
             "pond_mlp_nparams", "pond_mlp_create", "pond_mlp_get", "pond_mlp_set",
@@ -340,6 +341,11 @@ class Context:
         out = np.zeros(5)
         load().pond_kernel_times(self._h, _ptr(out))
         return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3], "tail": out[4]}
+
+    def set_graph(self, on: bool = True):
+        rc = load().pond_set_graph(self._h, int(bool(on)))
+        if rc != OK:
+            raise PondError(rc, "pond_set_graph")
 
     def set_iter_split(self, k: int):
         rc = load().pond_set_iter_split(self._h, int(k))
