@@ -329,6 +329,14 @@ PD double rcp_nr(double x)
     return r * (2.0 - x * r);
 }
 
+// Reciprocal and reciprocal square root of the frame update: in FP32 the hardware estimates
+// (about 1 ulp; the FP32 form is not held to bit equality with the FP64 oracle), in FP64 the
+// correctly rounded operations.
+PD float frcp(float x) { return __builtin_amdgcn_rcpf(x); }
+PD double frcp(double x) { return 1.0 / x; }
+PD float frsq(float x) { return __builtin_amdgcn_rsqf(x); }
+PD double frsq(double x) { return 1.0 / sqrt(x); }
+
 // slope limiters of the MUSCL reconstruction (Van Leer, minmod)
 template <typename R>
 PD R limit(R a, R b, int kind)

@@ -767,6 +767,39 @@ PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_s
 // the face iteration (Sec. III.B.3)
 // ---------------------------------------------------------------------------------
 
+// Frame-update arithmetic: FP32 uses the hardware reciprocal estimates (about 1 ulp), FP64
+// the correctly rounded operations in the oracle's form.
+template <typename R>
+PD void frame_scale(R T, R &s, R &inv_s)
+{
+    if constexpr (sizeof(R) == 4) {
+        inv_s = frsq(T);
+        s = T * inv_s;
+    } else {
+        s = sqrt(T);
+        inv_s = R(1) / s;
+    }
+}
+
+template <typename R>
+PD R temperature(R rhoe, R rho, R irho, double Cv)
+{
+    if constexpr (sizeof(R) == 4)
+        return rhoe * irho * (R)(1.0 / Cv);
+    else
+        return rhoe / ((R)Cv * rho);
+}
+
+// relative change |a - b| / T
+template <typename R>
+PD R rel(R a, R b, R T, R iT)
+{
+    if constexpr (sizeof(R) == 4)
+        return fabs(a - b) * iT;
+    else
+        return fabs(a - b) / T;
+}
+
 struct FaceCount {
     unsigned long long iters, nonconv, fallback, depout, itmax;
     unsigned long long tail_faces = 0, tail_iters = 0; // faces finished by the tail kernel
@@ -898,7 +931,8 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
     const int kcap = (P.iter_split > 0 && P.iter_split < P.max_iter) ? P.iter_split : P.max_iter;
     while (it < kcap) {
         ++it;
-        R s = sqrt(T), inv_s = R(1) / s;
+        R s, inv_s;
+        frame_scale(T, s, inv_s);
         {
             const int b0 = idx[0];
             const int sidx[8] = {b0, b0 + sn, b0 - sn, b0 + 2 * sn, b0 - stn, b0 + stn, b0 + sn - stn, b0 + sn + stn};
@@ -906,10 +940,10 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
             recon_2d<R, true, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
         }
         R rho = mf[0];
-        R irho = R(1) / rho;
+        R irho = (sizeof(R) == 4) ? frcp(rho) : R(1) / rho;
         R dux = s * mf[1] * irho, duy = s * mf[2] * irho;
         R rhoe = R(0.5) * s * s * (mf[3] + mf[5] - (mf[1] * mf[1] + mf[2] * mf[2]) * irho) + mg[0];
-        R Tn = rhoe / ((R)P.Cv * rho);
+        R Tn = temperature(rhoe, rho, irho, P.Cv);
         if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(dux) || !isfinite(duy)) {
             if (!restarted) {
                 restarted = true;
@@ -923,9 +957,9 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
             break;
         }
         const R unx = u[0] + dux, uny = u[1] + duy;
-        const R isq = R(1) / sqrt(Tn);
-        R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, fabs(Tn - T) / Tn);
-        R delta2 = fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, fabs(Tn - Tpp) / Tn);
+        const R isq = (sizeof(R) == 4) ? frsq(Tn) : R(1) / sqrt(Tn), iTn = isq * isq;
+        R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, rel(Tn, T, Tn, iTn));
+        R delta2 = fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, rel(Tn, Tpp, Tn, iTn));
         upp[0] = u[0];
         upp[1] = u[1];
         Tpp = T;
@@ -1255,7 +1289,8 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
     bool active = has && it < P.max_iter;
     while (__any(active)) {
         if (active) ++it;
-        const R s = sqrt(T), inv_s = R(1) / s;
+        R s, inv_s;
+        frame_scale(T, s, inv_s);
         {
             const R r = rec[2 * 8 + tc] * inv_s, dx = (rec[tc] - u[0]) * inv_s,
                     dy = (rec[8 + tc] - u[1]) * inv_s;
@@ -1316,10 +1351,10 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         if (active) {
             pf = pfn;
             pg = pgn;
-            const R irho = R(1) / rho;
+            const R irho = (sizeof(R) == 4) ? frcp(rho) : R(1) / rho;
             const R dux = s * m1x * irho, duy = s * m1y * irho;
             const R rhoe = R(0.5) * s * s * (m2 - (m1x * m1x + m1y * m1y) * irho) + g0;
-            const R Tn = rhoe / ((R)P.Cv * rho);
+            const R Tn = temperature(rhoe, rho, irho, P.Cv);
             if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(dux) || !isfinite(duy)) {
                 if (!restarted) {
                     restarted = true;
@@ -1333,10 +1368,10 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
                 }
             } else {
                 const R unx = u[0] + dux, uny = u[1] + duy;
-                const R isq = R(1) / sqrt(Tn);
-                const R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, fabs(Tn - T) / Tn);
+                const R isq = (sizeof(R) == 4) ? frsq(Tn) : R(1) / sqrt(Tn), iTn = isq * isq;
+                const R delta = fmax(fmax(fabs(dux), fabs(duy)) * isq, rel(Tn, T, Tn, iTn));
                 const R delta2 =
-                    fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, fabs(Tn - Tpp) / Tn);
+                    fmax(fmax(fabs(unx - upp[0]), fabs(uny - upp[1])) * isq, rel(Tn, Tpp, Tn, iTn));
                 upp[0] = u[0];
                 upp[1] = u[1];
                 Tpp = T;
