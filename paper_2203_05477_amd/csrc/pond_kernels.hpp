@@ -1167,7 +1167,10 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
 // over the 16 lanes. Same iteration, same stopping rules and finalization as face_2d.
 
 constexpr int TAIL_REC = 8 * Layout<2>::NL; // 8 stencil records
-constexpr int TAIL_COEF = 8 * 16;           // per stencil cell: f 10, g 6 coefficients
+// per stencil cell: f 10, g 6 coefficients, one pad (an odd stride keeps the cells that the
+// lanes of a wave read at one time on different LDS banks)
+constexpr int TAIL_CSTRIDE = 17;
+constexpr int TAIL_COEF = 8 * TAIL_CSTRIDE;
 constexpr int TAIL_GROUP = TAIL_REC + TAIL_COEF;
 
 // LDS written by some lanes of a wave and read by others of the same wave
@@ -1310,7 +1313,7 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
             h2mu_2d(h, mu, 10);
             shift_2d(mu, r, dx, dy, 10);
             mu2h_2d(mu, h, 10);
-            R *dst = coef + tc * 16 + (tg ? 10 : 0);
+            R *dst = coef + tc * TAIL_CSTRIDE + (tg ? 10 : 0);
             const int nw = tg ? 6 : 10;
 #pragma unroll
             for (int k = 0; k < 10; ++k)
@@ -1325,7 +1328,7 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         R vf[5], vg[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-            const R *h = coef + cl[m] * 16;
+            const R *h = coef + cl[m] * TAIL_CSTRIDE;
             R a = h[0], b = h[10];
 #pragma unroll
             for (int k = 1; k < 10; ++k) a += h[k] * bas[k];
