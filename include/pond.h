@@ -254,6 +254,18 @@ pond_status pond_mlp_targets(pond_ctx *ctx, const float *dev_X, const float *dev
 /* Attach a copy of the network to a context whose seed_mode is POND_SEED_MLP. */
 pond_status pond_load_mlp(pond_ctx *ctx, const pond_mlp *m, int32_t hard_iters);
 
+/* Checkpoint (a warm start of a long run): pond_save writes the carried state -- conserved
+ * variables, non-equilibrium coefficients, face states and seeds, iteration flags, clocks
+ * and time steps, the CFL maxima, failed-instance flags, step parity and count, and the
+ * tail hand-over point -- to a binary file at `path` (overwritten). pond_load reads such a
+ * file into a context created with the same configuration (the fields given to pond_init
+ * are replaced); the steps that follow give bitwise the results the saved run would have
+ * given. The learned seed's network is not part of the file. POND_EINVAL: null argument,
+ * file that cannot be opened, written or read, or that belongs to another configuration
+ * (then the context is unchanged); POND_EDEVICE: device copy failed. */
+pond_status pond_save(pond_ctx *ctx, const char *path);
+pond_status pond_load(pond_ctx *ctx, const char *path);
+
 void pond_free(pond_ctx *ctx);
 const char *pond_strerror(pond_status s);
 int32_t pond_abi_version(void);

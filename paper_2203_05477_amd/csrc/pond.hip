@@ -644,6 +644,108 @@ pond_status pond_moments(const pond_ctx *c, double *rho, double *ux, double *uy,
     return POND_OK;
 }
 
+// ---- checkpoint: the carried state of a context, in a flat binary file ----
+
+namespace {
+
+struct CkptHeader {
+    char magic[8];
+    int32_t abi, dim, precision, n_inst, nh, nfp, vslots, slot, iter_split, pad;
+    int64_t ncell, nface, steps_done;
+};
+
+struct Blob {
+    void *dev;
+    size_t bytes;
+};
+
+std::vector<Blob> ckpt_blobs(pond_ctx *c)
+{
+    const int64_t n = c->P.ncell, nf = c->P.nface, ni = c->P.n_inst;
+    return {{c->U, sizeof(double) * (c->D + 2) * n},
+            {c->H, c->rsize * c->nh * n},
+            {c->F, c->rsize * c->nfp * nf},
+            {c->fiter, sizeof(int) * nf},
+            {c->t, sizeof(double) * ni},
+            {c->tstart, sizeof(double) * ni},
+            {c->dt, sizeof(double) * ni},
+            {c->vmax, sizeof(unsigned long long) * 2 * ni * c->P.vslots},
+            {c->inst_err, sizeof(int) * ni}};
+}
+
+CkptHeader ckpt_header(const pond_ctx *c)
+{
+    CkptHeader h;
+    memset(&h, 0, sizeof(h));
+    memcpy(h.magic, "PONDCKP1", 8);
+    h.abi = POND_ABI_VERSION;
+    h.dim = c->D;
+    h.precision = c->precision;
+    h.n_inst = c->P.n_inst;
+    h.nh = c->nh;
+    h.nfp = c->nfp;
+    h.vslots = c->P.vslots;
+    h.slot = c->slot;
+    h.iter_split = c->P.iter_split;
+    h.ncell = c->P.ncell;
+    h.nface = c->P.nface;
+    h.steps_done = c->steps_done;
+    return h;
+}
+
+} // namespace
+
+pond_status pond_save(pond_ctx *c, const char *path)
+{
+    if (!c || !path) return POND_EINVAL;
+    FILE *fp = fopen(path, "wb");
+    if (!fp) return POND_EINVAL;
+    CkptHeader h = ckpt_header(c);
+    bool ok = fwrite(&h, sizeof(h), 1, fp) == 1;
+    std::vector<unsigned char> buf;
+    for (const Blob &b : ckpt_blobs(c)) {
+        if (!ok) break;
+        buf.resize(b.bytes);
+        if (hipMemcpyAsync(buf.data(), b.dev, b.bytes, hipMemcpyDeviceToHost, c->stream) != hipSuccess ||
+            hipStreamSynchronize(c->stream) != hipSuccess) {
+            fclose(fp);
+            return POND_EDEVICE;
+        }
+        ok = fwrite(buf.data(), 1, b.bytes, fp) == b.bytes;
+    }
+    ok = (fclose(fp) == 0) && ok;
+    return ok ? POND_OK : POND_EINVAL;
+}
+
+pond_status pond_load(pond_ctx *c, const char *path)
+{
+    if (!c || !path) return POND_EINVAL;
+    FILE *fp = fopen(path, "rb");
+    if (!fp) return POND_EINVAL;
+    CkptHeader h, mine = ckpt_header(c);
+    bool ok = fread(&h, sizeof(h), 1, fp) == 1 && memcmp(h.magic, mine.magic, 8) == 0 &&
+              h.abi == mine.abi && h.dim == mine.dim && h.precision == mine.precision &&
+              h.n_inst == mine.n_inst && h.nh == mine.nh && h.nfp == mine.nfp &&
+              h.vslots == mine.vslots && h.ncell == mine.ncell && h.nface == mine.nface;
+    std::vector<std::vector<unsigned char>> data;
+    for (const Blob &b : ckpt_blobs(c)) {
+        if (!ok) break;
+        data.emplace_back(b.bytes);
+        ok = fread(data.back().data(), 1, b.bytes, fp) == b.bytes;
+    }
+    fclose(fp);
+    if (!ok) return POND_EINVAL; // the context is left as it was
+    drop_graph(c);
+    const std::vector<Blob> blobs = ckpt_blobs(c);
+    for (size_t k = 0; k < blobs.size(); ++k)
+        HIPCHK(hipMemcpyAsync(blobs[k].dev, data[k].data(), blobs[k].bytes, hipMemcpyHostToDevice, c->stream));
+    HIPCHK(hipStreamSynchronize(c->stream));
+    c->slot = h.slot;
+    c->P.iter_split = h.iter_split;
+    c->steps_done = h.steps_done;
+    return POND_OK;
+}
+
 pond_status pond_conserved(const pond_ctx *c, double *U)
 {
     if (!c || !U) return POND_EINVAL;

@@ -109,6 +109,8 @@ def load(path: str | None = None):
         "pond_autotune": (S, [_P]),
         "pond_set_iter_split": (S, [_P, ctypes.c_int32]),
         "pond_set_graph": (S, [_P, ctypes.c_int32]),
+        "pond_save": (S, [_P, ctypes.c_char_p]),
+        "pond_load": (S, [_P, ctypes.c_char_p]),
         "pond_enable_timing": (S, [_P, ctypes.c_int32]),
         "pond_kernel_times": (S, [_P, _D]),
         "pond_free": (None, [_P]),
@@ -143,6 +145,7 @@ def exported_symbols():
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
             "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split", "pond_set_graph",
+            "pond_save", "pond_load",
             "pond_enable_timing",
             "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
             "pond_mlp_nparams", "pond_mlp_create", "pond_mlp_get", "pond_mlp_set",
@@ -341,6 +344,16 @@ class Context:
         out = np.zeros(5)
         load().pond_kernel_times(self._h, _ptr(out))
         return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3], "tail": out[4]}
+
+    def save(self, path: str):
+        rc = load().pond_save(self._h, str(path).encode())
+        if rc != OK:
+            raise PondError(rc, "pond_save")
+
+    def load_state(self, path: str):
+        rc = load().pond_load(self._h, str(path).encode())
+        if rc != OK:
+            raise PondError(rc, "pond_load")
 
     def set_graph(self, on: bool = True):
         rc = load().pond_set_graph(self._h, int(bool(on)))

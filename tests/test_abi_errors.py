@@ -99,6 +99,8 @@ def test_null_handles_and_strerror():
     assert lib.pond_autotune(P()) == EINVAL
     assert lib.pond_kernel_times(P(), None) == EINVAL
     assert lib.pond_nfaces(P()) == 0
+    assert lib.pond_save(P(), b"/tmp/x.ckpt") == EINVAL
+    assert lib.pond_load(P(), b"/tmp/x.ckpt") == EINVAL
     lib.pond_free(P())  # no-op
     names = [lib.pond_strerror(s).decode() for s in range(8)]
     assert names[0] == "ok" and len(set(names)) == 8
