@@ -220,47 +220,6 @@ PD void eval_2d(const R h[10], R p[16], int order)
 }
 
 
-// Half of the 2D populations: the 8 whose node component along the face normal (AXIS)
-// has magnitude c_m (m = 0: ca, 1: cb). out[2 t + s]: tangential node t = 0..3, normal
-// sign s (0: -c_m, 1: +c_m). Sum factorization over the tangential direction first.
-template <typename R, int AXIS>
-PD void eval_half_2d(const R h[10], int m, R out[8], int order)
-{
-    const bool o3 = order > 2;
-    const R h30 = o3 ? h[6] : R(0), h21 = o3 ? h[7] : R(0), h12 = o3 ? h[8] : R(0), h03 = o3 ? h[9] : R(0);
-    // coefficients as g[n][q]: n = normal degree, q = tangential degree
-    R g00 = h[0], g10, g01, g20, g11, g02, g30, g21, g12, g03;
-    if (AXIS == 0) {
-        g10 = h[1]; g01 = h[2]; g20 = h[3]; g11 = h[4]; g02 = h[5];
-        g30 = h30; g21 = h21; g12 = h12; g03 = h03;
-    } else {
-        g10 = h[2]; g01 = h[1]; g20 = h[5]; g11 = h[4]; g02 = h[3];
-        g30 = h03; g21 = h12; g12 = h21; g03 = h30;
-    }
-    const R cn = m ? Lat<R>::cb : Lat<R>::ca;
-    const R e2n = m ? Lat<R>::he2b : Lat<R>::he2a;
-    const R e3n = m ? Lat<R>::he3b : Lat<R>::he3a;
-#pragma unroll
-    for (int mt = 0; mt < 2; ++mt) {
-        const R ct = mt ? Lat<R>::cb : Lat<R>::ca;
-        const R e2t = mt ? Lat<R>::he2b : Lat<R>::he2a;
-        const R e3t = mt ? Lat<R>::he3b : Lat<R>::he3a;
-        const int tp = mt ? 3 : 2, tm = mt ? 0 : 1;
-        // B_n(+-ct) = sum_q g[n][q] He_q(+-ct)
-        R E0 = g00 + g02 * e2t, O0 = g01 * ct + g03 * e3t;
-        R E1 = g10 + g12 * e2t, O1 = g11 * ct;
-        R E2 = g20, O2 = g21 * ct;
-        const R B0[2] = {E0 - O0, E0 + O0}, B1[2] = {E1 - O1, E1 + O1}, B2[2] = {E2 - O2, E2 + O2};
-#pragma unroll
-        for (int sgt = 0; sgt < 2; ++sgt) {
-            const int t = sgt ? tp : tm;
-            R En = B0[sgt] + B2[sgt] * e2n, On = B1[sgt] * cn + g30 * e3n;
-            out[2 * t + 0] = En - On;
-            out[2 * t + 1] = En + On;
-        }
-    }
-}
-
 // raw moments mu = sum_i W_i p_i c^k (1D), up to degree n-1
 template <typename R>
 PD void moments_1d(const R p[4], R mu[4], int n)

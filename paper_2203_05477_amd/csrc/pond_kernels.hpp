@@ -496,132 +496,6 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
     moments_2d(A, M, G ? 6 : 10);
 }
 
-// half of the populations of stencil cell c in frame (u, s), normal magnitude c_m
-template <typename R, bool G, int AXIS>
-PD void cell_half_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int m, R p[8])
-{
-    R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
-    R h[10], mu[10];
-    if (!G) {
-        h[0] = L[3 * NT + c];
-        h[1] = R(0);
-        h[2] = R(0);
-#pragma unroll
-        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
-        h2mu_2d(h, mu, 10);
-        shift_2d(mu, r, dx, dy, 10);
-        mu2h_2d(mu, h, 10);
-        eval_half_2d<R, AXIS>(h, m, p, 3);
-    } else {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
-        h2mu_2d(h, mu, 6);
-        shift_2d(mu, r, dx, dy, 6);
-        mu2h_2d(mu, h, 6);
-        eval_half_2d<R, AXIS>(h, m, p, 2);
-    }
-}
-
-// MUSCL reconstruction of one half of the populations (normal magnitude c_m) at the
-// departure points, 2D, face normal along AXIS. The stencil cells are visited one at a
-// time (L, R, L-n, R+n, L-t, L+t, R-t, R+t: LDS index base + a*sn + b*st), which keeps
-// only four half-population arrays live. The reconstructed phi-bar_i / W_i are
-// accumulated into raw moments M (normal, tangential degree order of mu).
-template <typename R, bool G, int AXIS>
-PD void recon_half_2d(const R *L, int NT, int base, int sn, int st, R un, R ut, R ux, R uy,
-                      R s, R inv_s, R hdn, R hdt, int lim, int m, R M[10])
-{
-    R PL[8], PR[8], A[8], Bt[8];
-    const R cm = m ? Lat<R>::cb : Lat<R>::ca;
-    const R wm = m ? Lat<R>::wb : Lat<R>::wa;
-    R vn[2];
-    vn[0] = un - s * cm;
-    vn[1] = un + s * cm;
-    const bool up0 = vn[0] >= R(0), up1 = vn[1] >= R(0);
-#pragma unroll 1
-    for (int k = 0; k < 8; ++k) {
-        const int a = (k == 1 || k >= 6) ? 1 : (k == 2 ? -1 : (k == 3 ? 2 : 0));
-        const int b = (k == 4 || k == 6) ? -1 : ((k == 5 || k == 7) ? 1 : 0);
-        R X[8];
-        cell_half_2d<R, G, AXIS>(L, NT, base + a * sn + b * st, ux, uy, inv_s, m, X);
-        if (k == 0) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) PL[j] = X[j];
-        } else if (k == 1) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) PR[j] = X[j];
-        } else if (k == 2) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) A[j] = ((j & 1) ? up1 : up0) ? PL[j] - X[j] : PR[j] - PL[j];
-        } else if (k == 3) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) {
-                const bool u = (j & 1) ? up1 : up0;
-                R B = u ? PR[j] - PL[j] : X[j] - PR[j];
-                R sl = limit(A[j], B, lim);
-                R pu = u ? PL[j] : PR[j];
-                R off = (u ? R(0.5) : R(-0.5)) - vn[j & 1] * hdn;
-                PL[j] = pu;            // upwind value
-                PR[j] = pu + off * sl; // reconstruction so far
-            }
-        } else if (k == 4) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) A[j] = PL[j] - X[j];
-        } else if (k == 5) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j) Bt[j] = X[j] - PL[j];
-        } else if (k == 6) {
-#pragma unroll
-            for (int j = 0; j < 8; ++j)
-                if (!((j & 1) ? up1 : up0)) A[j] = PL[j] - X[j];
-        } else {
-#pragma unroll
-            for (int t = 0; t < 4; ++t) {
-                const R ct = node<R>(t);
-                const R off = -(s * ct + ut) * hdt;
-                R q[2];
-#pragma unroll
-                for (int sg = 0; sg < 2; ++sg) {
-                    const int j = 2 * t + sg;
-                    R B = (sg ? up1 : up0) ? Bt[j] : X[j] - PL[j];
-                    q[sg] = PR[j] + off * limit(A[j], B, lim);
-                }
-                // moments of the pair (+-c_m, c_t): even normal degree takes the sum,
-                // odd normal degree the difference
-                const R w = wm * weight1<R>(t);
-                const R Sw = w * (q[1] + q[0]), Dw = w * cm * (q[1] - q[0]);
-                const R ct2 = ct * ct;
-                M[0] += Sw;
-                M[2] += Sw * ct;
-                M[5] += Sw * ct2;
-                M[1] += Dw;
-                M[4] += Dw * ct;
-                M[3] += Sw * cm * cm;
-                if (!G) {
-                    M[9] += Sw * ct2 * ct;
-                    M[8] += Dw * ct2;
-                    M[7] += Sw * cm * cm * ct;
-                    M[6] += Dw * cm * cm;
-                }
-            }
-        }
-    }
-}
-
-// (normal, tangential) moment order -> (x, y) order for a y-normal face
-template <typename R, int AXIS>
-PD void to_xy(R M[10], int n)
-{
-    if (AXIS == 0) return;
-    R t;
-    t = M[1]; M[1] = M[2]; M[2] = t;
-    t = M[3]; M[3] = M[5]; M[5] = t;
-    if (n > 6) {
-        t = M[6]; M[6] = M[9]; M[9] = t;
-        t = M[7]; M[7] = M[8]; M[8] = t;
-    }
-}
-
 // ---------------------------------------------------------------------------------
 // face finalization: moments of phi-bar in frame `last` -> phi in the final frame
 // ---------------------------------------------------------------------------------
