@@ -220,6 +220,53 @@ PD void eval_2d(const R h[10], R p[16], int order)
 }
 
 
+// 2D reduced populations of the node columns in `cols` only (bit n: normal node n, in
+// node order -cb, -ca, +ca, +cb), normal axis AXIS, sum factorization over the normal
+// direction first; the populations of the other columns are set to 0. `cols` must be the
+// same in every lane of the wave (the column loop branches on it).
+template <typename R, int AXIS>
+PD void eval_cols_2d(const R h[10], int cols, R p[16], int order)
+{
+    const bool o3 = order > 2;
+    // coefficients as g[n][t]: n = normal degree, t = tangential degree
+    R g00 = h[0], g10, g01, g20, g11, g02, g30, g21, g12, g03;
+    if (AXIS == 0) {
+        g10 = h[1]; g01 = h[2]; g20 = h[3]; g11 = h[4]; g02 = h[5];
+        g30 = o3 ? h[6] : R(0); g21 = o3 ? h[7] : R(0); g12 = o3 ? h[8] : R(0); g03 = o3 ? h[9] : R(0);
+    } else {
+        g10 = h[2]; g01 = h[1]; g20 = h[5]; g11 = h[4]; g02 = h[3];
+        g30 = o3 ? h[9] : R(0); g21 = o3 ? h[8] : R(0); g12 = o3 ? h[7] : R(0); g03 = o3 ? h[6] : R(0);
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        R out[4] = {R(0), R(0), R(0), R(0)};
+        if (cols & (1 << n)) {
+            const R cn = node<R>(n);
+            const R e2 = (n == 1 || n == 2) ? Lat<R>::he2a : Lat<R>::he2b;
+            const R e3n = (n == 1 || n == 2) ? Lat<R>::he3a : Lat<R>::he3b;
+            const R e3 = (n < 2) ? -e3n : e3n; // He3 is odd
+            // A_t = sum_n' g[n'][t] He_n'(c_n); explicit fma throughout, so that a column's
+            // value does not depend on which other columns are evaluated (which products the
+            // compiler could otherwise share between columns and leave unfused)
+            const R A0 = fma(e3, g30, fma(e2, g20, fma(cn, g10, g00)));
+            const R A1 = fma(e2, g21, fma(cn, g11, g01));
+            const R A2 = fma(cn, g12, g02);
+            const R A3 = g03;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const R ct = m ? Lat<R>::cb : Lat<R>::ca;
+                const R t2 = m ? Lat<R>::he2b : Lat<R>::he2a;
+                const R t3 = m ? Lat<R>::he3b : Lat<R>::he3a;
+                const R E = fma(A2, t2, A0), O = fma(A3, t3, A1 * ct);
+                out[m ? 3 : 2] = E + O;
+                out[m ? 0 : 1] = E - O;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[AXIS ? (t + 4 * n) : (n + 4 * t)] = out[t];
+    }
+}
+
 // raw moments mu = sum_i W_i p_i c^k (1D), up to degree n-1
 template <typename R>
 PD void moments_1d(const R p[4], R mu[4], int n)

@@ -411,6 +411,32 @@ PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
     }
 }
 
+// the populations of stencil cell c in the node columns `cols` (wave-uniform) only
+template <typename R, bool G, int AXIS>
+PD void cell_cols_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int cols, R p[16])
+{
+    R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
+    R h[10], mu[10];
+    if (!G) {
+        h[0] = L[3 * NT + c];
+        h[1] = R(0);
+        h[2] = R(0);
+#pragma unroll
+        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
+        h2mu_2d(h, mu, 10);
+        shift_2d(mu, r, dx, dy, 10);
+        mu2h_2d(mu, h, 10);
+        eval_cols_2d<R, AXIS>(h, cols, p, 3);
+    } else {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
+        h2mu_2d(h, mu, 6);
+        shift_2d(mu, r, dx, dy, 6);
+        mu2h_2d(mu, h, 6);
+        eval_cols_2d<R, AXIS>(h, cols, p, 2);
+    }
+}
+
 // MUSCL reconstruction at the departure points, 1D. idx: L, R, L-1, R+1.
 // Returns the reduced populations phi-bar_i / W_i at the face.
 template <typename R, bool G>
@@ -439,7 +465,10 @@ PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx,
 }
 
 // 2D, face normal along AXIS. idx: L, R, L-n, R+n, L-t, L+t, R-t, R+t.
-template <typename R, bool G, int AXIS>
+// SUB: every lane of the wave takes the two negative normal node columns from the R side
+// and the two positive ones from the L side (|normal frame velocity| below s*ca, the usual
+// case); the side cells of the stencil are then evaluated in the two columns they feed only.
+template <typename R, bool G, int AXIS, bool SUB>
 PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
                  int lim, R M[10])
 {
@@ -447,51 +476,59 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
     const R un = AXIS ? uy : ux, ut = AXIS ? ux : uy;
     bool upn[4];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) upn[k] = (s * node<R>(k) + un) >= R(0);
+    for (int k = 0; k < 4; ++k) upn[k] = fma(s, node<R>(k), un) >= R(0);
     auto nk = [](int i) { return AXIS ? (i >> 2) : (i & 3); };
     auto tk = [](int i) { return AXIS ? (i & 3) : (i >> 2); };
+    // the SUB and full forms give bitwise the same values in every lane (the choice between
+    // them depends on the other lanes of the wave): products that feed sums are written as
+    // explicit fma, so the compiler's contraction choices cannot differ between the two
+    if (SUB) {
+#pragma unroll
+        for (int k = 0; k < 4; ++k) upn[k] = k >= 2;
+    }
+    constexpr int cup = SUB ? 0xC : 0xF, cdn = SUB ? 0x3 : 0xF;
     cell_pops_2d<R, G>(L, NT, idx[0], ux, uy, inv_s, PL);
     __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[1], ux, uy, inv_s, PR);
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[2], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[2], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = upn[nk(i)] ? PL[i] - T[i] : PR[i] - PL[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[3], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[3], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const bool up = upn[nk(i)];
-        R vn = s * node<R>(nk(i)) + un;
+        R vn = fma(s, node<R>(nk(i)), un);
         R B = up ? PR[i] - PL[i] : T[i] - PR[i];
         R sl = limit(A[i], B, lim);
-        R off = (up ? R(0.5) : R(-0.5)) - vn * hdn;
+        R off = fma(-vn, hdn, up ? R(0.5) : R(-0.5));
         R pu = up ? PL[i] : PR[i];
-        out[i] = pu + off * sl;
+        out[i] = fma(off, sl, pu);
         PL[i] = pu; // upwind value, kept for the tangential slope
     }
     // tangential slope of the upwind cell
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[4], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[4], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = PL[i] - T[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[6], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[6], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         if (!upn[nk(i)]) A[i] = PL[i] - T[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[5], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[5], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) PR[i] = T[i] - PL[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[7], ux, uy, inv_s, T);
+    cell_cols_2d<R, G, AXIS>(L, NT, idx[7], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
         R sl = limit(A[i], B, lim);
-        R vt = s * node<R>(tk(i)) + ut;
-        A[i] = out[i] + (-vt * hdt) * sl;
+        R vt = fma(s, node<R>(tk(i)), ut);
+        A[i] = fma(-vt * hdt, sl, out[i]);
     }
     moments_2d(A, M, G ? 6 : 10);
 }
@@ -810,8 +847,14 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
         {
             const int b0 = idx[0];
             const int sidx[8] = {b0, b0 + sn, b0 - sn, b0 + 2 * sn, b0 - stn, b0 + stn, b0 + sn - stn, b0 + sn + stn};
-            recon_2d<R, false, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
-            recon_2d<R, true, AXIS>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
+            const R un = AXIS ? u[1] : u[0];
+            if (__all(!(fma(s, node<R>(1), un) >= R(0)) && (fma(s, node<R>(2), un) >= R(0)))) {
+                recon_2d<R, false, AXIS, true>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
+                recon_2d<R, true, AXIS, true>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
+            } else {
+                recon_2d<R, false, AXIS, false>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
+                recon_2d<R, true, AXIS, false>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
+            }
         }
         R rho = mf[0];
         R irho = (sizeof(R) == 4) ? frcp(rho) : R(1) / rho;
