@@ -284,26 +284,32 @@ PD void moments_1d(const R p[4], R mu[4], int n)
 template <typename R>
 PD void moments_2d(const R p[16], R mu[10], int n)
 {
+    // weights times node powers, one product per (node pair, degree)
+    constexpr R w0a = Lat<R>::wa, w0b = Lat<R>::wb;
+    constexpr R w1a = R(Lat<double>::wa * Lat<double>::ca), w1b = R(Lat<double>::wb * Lat<double>::cb);
+    constexpr R w2a = R(Lat<double>::wa * Lat<double>::ca * Lat<double>::ca);
+    constexpr R w2b = R(Lat<double>::wb * Lat<double>::cb * Lat<double>::cb);
+    constexpr R w3a = R(Lat<double>::wa * Lat<double>::ca * Lat<double>::ca * Lat<double>::ca);
+    constexpr R w3b = R(Lat<double>::wb * Lat<double>::cb * Lat<double>::cb * Lat<double>::cb);
     // reduce over y for every column ix: Rl[ix] = sum_iy w_iy c_iy^l p(ix, iy)
     R R0[4], R1[4], R2[4], R3[4];
-    const R ca = Lat<R>::ca, cb = Lat<R>::cb;
 #pragma unroll
     for (int ix = 0; ix < 4; ++ix) {
-        R ea = Lat<R>::wa * (p[ix + 8] + p[ix + 4]), oa = Lat<R>::wa * (p[ix + 8] - p[ix + 4]);
-        R eb = Lat<R>::wb * (p[ix + 12] + p[ix]), ob = Lat<R>::wb * (p[ix + 12] - p[ix]);
-        R0[ix] = ea + eb;
-        R1[ix] = ca * oa + cb * ob;
-        R2[ix] = ca * ca * ea + cb * cb * eb;
-        R3[ix] = ca * ca * ca * oa + cb * cb * cb * ob;
+        R ea = p[ix + 8] + p[ix + 4], oa = p[ix + 8] - p[ix + 4];
+        R eb = p[ix + 12] + p[ix], ob = p[ix + 12] - p[ix];
+        R0[ix] = fma(w0b, eb, w0a * ea);
+        R1[ix] = fma(w1b, ob, w1a * oa);
+        R2[ix] = fma(w2b, eb, w2a * ea);
+        R3[ix] = fma(w3b, ob, w3a * oa);
     }
     // reduce over x
     auto red = [&](const R* Rl, R& m0, R& m1, R& m2, R& m3) {
-        R ea = Lat<R>::wa * (Rl[2] + Rl[1]), oa = Lat<R>::wa * (Rl[2] - Rl[1]);
-        R eb = Lat<R>::wb * (Rl[3] + Rl[0]), ob = Lat<R>::wb * (Rl[3] - Rl[0]);
-        m0 = ea + eb;
-        m1 = ca * oa + cb * ob;
-        m2 = ca * ca * ea + cb * cb * eb;
-        m3 = ca * ca * ca * oa + cb * cb * cb * ob;
+        R ea = Rl[2] + Rl[1], oa = Rl[2] - Rl[1];
+        R eb = Rl[3] + Rl[0], ob = Rl[3] - Rl[0];
+        m0 = fma(w0b, eb, w0a * ea);
+        m1 = fma(w1b, ob, w1a * oa);
+        m2 = fma(w2b, eb, w2a * ea);
+        m3 = fma(w3b, ob, w3a * oa);
     };
     R a0, a1, a2, a3;
     red(R0, a0, a1, a2, a3);
@@ -352,5 +358,18 @@ PD R limit(R a, R b, int kind)
     if (kind == 1) return (a > R(0)) ? fmin(a, b) : fmax(a, b);
     return R(2) * ab * rcp_nr(a + b);
 }
+
+// the limited slope divided by limit_scale(kind): Van Leer without its factor 2, which the
+// caller folds into the offset the slope multiplies (a power of two, so the product is
+// bitwise that of limit())
+template <typename R>
+PD R limit_part(R a, R b, int kind)
+{
+    R ab = a * b;
+    if (!(ab > R(0))) return R(0);
+    if (kind == 1) return (a > R(0)) ? fmin(a, b) : fmax(a, b);
+    return ab * rcp_nr(a + b);
+}
+PD constexpr int limit_scale(int kind) { return kind == 1 ? 1 : 2; }
 
 } // namespace pond

@@ -487,6 +487,7 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
         for (int k = 0; k < 4; ++k) upn[k] = k >= 2;
     }
     constexpr int cup = SUB ? 0xC : 0xF, cdn = SUB ? 0x3 : 0xF;
+    const R sc = R(limit_scale(lim)); // slopes come from limit_part
     cell_pops_2d<R, G>(L, NT, idx[0], ux, uy, inv_s, PL);
     __builtin_amdgcn_sched_barrier(0);
     cell_pops_2d<R, G>(L, NT, idx[1], ux, uy, inv_s, PR);
@@ -501,8 +502,8 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
         const bool up = upn[nk(i)];
         R vn = fma(s, node<R>(nk(i)), un);
         R B = up ? PR[i] - PL[i] : T[i] - PR[i];
-        R sl = limit(A[i], B, lim);
-        R off = fma(-vn, hdn, up ? R(0.5) : R(-0.5));
+        R sl = limit_part(A[i], B, lim);
+        R off = fma(-vn, hdn * sc, up ? R(0.5) * sc : R(-0.5) * sc);
         R pu = up ? PL[i] : PR[i];
         out[i] = fma(off, sl, pu);
         PL[i] = pu; // upwind value, kept for the tangential slope
@@ -526,9 +527,9 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
-        R sl = limit(A[i], B, lim);
+        R sl = limit_part(A[i], B, lim);
         R vt = fma(s, node<R>(tk(i)), ut);
-        A[i] = fma(-vt * hdt, sl, out[i]);
+        A[i] = fma(-vt * (hdt * sc), sl, out[i]);
     }
     moments_2d(A, M, G ? 6 : 10);
 }
@@ -1255,12 +1256,14 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
             vg[m] = b;
         }
         wave_fence(); // coefficients are rewritten by the next iteration
-        const R off = (up ? R(0.5) : R(-0.5)) - vn * hdn, offt = -vt * hdt;
+        // slopes from limit_part, offsets scaled by limit_scale
+        constexpr R sc = R(limit_scale(LIM));
+        const R off = (up ? R(0.5) * sc : R(-0.5) * sc) - vn * (hdn * sc), offt = -vt * (hdt * sc);
         auto recon = [&](const R *v) {
             const R A = up ? v[0] - v[2] : v[0] - v[1];
             const R B = up ? v[1] - v[0] : v[2] - v[0];
-            const R o = v[0] + off * limit(A, B, LIM);
-            return o + offt * limit(v[0] - v[3], v[4] - v[0], LIM);
+            const R o = v[0] + off * limit_part(A, B, LIM);
+            return o + offt * limit_part(v[0] - v[3], v[4] - v[0], LIM);
         };
         const R pfn = recon(vf), pgn = recon(vg);
         const R wf = wgt * pfn;
