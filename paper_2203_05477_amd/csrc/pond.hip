@@ -201,7 +201,7 @@ hipError_t launch_face(pond_ctx *c, int bx, int by)
             face_kernel_2d<R, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         if (c->ev) (void)hipEventRecord(c->ev[3], c->stream);
         if (c->P.iter_split > 0) {
-            // 4 blocks of 16 faces per sub-list and axis
+            // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
             dim3 tgrid(NSLOT * 4, 2);
             if (c->P.limiter == POND_LIM_MINMOD)
                 face_tail_kernel_2d<R, 1><<<tgrid, 256, 0, c->stream>>>(c->P, S);

@@ -1384,17 +1384,47 @@ __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
     const int axis = blockIdx.y;
     const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
     R *rec = lds + grp * TAIL_GROUP, *coef = rec + TAIL_REC;
-    // block b works on sub-list b mod NSLOT of its axis, beside the other blocks of it
-    const int sl = axis * NSLOT + (int)(blockIdx.x % NSLOT);
-    const int sub = blockIdx.x / NSLOT, nsub = gridDim.x / NSLOT;
-    const int64_t base = (int64_t)sl * P.tail_cap;
-    const int64_t count = min((int64_t)S.tail_count[sl], (int64_t)P.tail_cap);
+    // The faces of the axis's NSLOT sub-lists, concatenated, are dealt out 16 per block in
+    // turn, so that no block works through a long sub-list alone (the hard faces cluster in
+    // the sub-lists of the face-kernel waves that cover a shock). pre[s] = faces in the
+    // sub-lists before s (one sub-list per thread of the block).
+    static_assert(NSLOT == 256, "one sub-list per thread of a 256-thread block");
+    __shared__ int pre[NSLOT + 1];
+    __shared__ int wtot[4];
+    {
+        const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+        int x = min(S.tail_count[axis * NSLOT + tid], P.tail_cap);
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (lane >= d) x += y;
+        }
+        if (lane == 63) wtot[w] = x;
+        __syncthreads();
+        for (int v = 0; v < w; ++v) x += wtot[v];
+        pre[tid + 1] = x;
+        if (tid == 0) pre[0] = 0;
+        __syncthreads();
+    }
+    const int total = pre[NSLOT];
     FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     // wave-uniform loop: a group without a face in this round takes part with has = false
-    for (int64_t k0 = (int64_t)sub * 16; __any(k0 + grp < count); k0 += (int64_t)nsub * 16) {
+    for (int64_t k0 = (int64_t)blockIdx.x * 16; __any(k0 + grp < total); k0 += (int64_t)gridDim.x * 16) {
         const int64_t k = k0 + grp;
-        const bool has = k < count;
-        const int64_t e = base + (has ? k : 0);
+        const bool has = k < total;
+        int64_t e = 0;
+        if (has) {
+            // the last sub-list s with pre[s] <= k holds face k (empty sub-lists are skipped)
+            int lo = 0, hi = NSLOT - 1;
+            while (lo < hi) {
+                const int mid = (lo + hi + 1) >> 1;
+                if (pre[mid] <= k)
+                    lo = mid;
+                else
+                    hi = mid - 1;
+            }
+            e = (int64_t)(axis * NSLOT + lo) * P.tail_cap + (k - pre[lo]);
+        }
         if (axis == 0)
             tail_face<R, 0, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
         else
