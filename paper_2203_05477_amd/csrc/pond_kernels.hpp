@@ -1566,15 +1566,11 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             R mu[4], mg[4];
             h2mu_1d(hf, mu);
             shift_1d(mu, r, d, 4);
-            mu2h_1d(mu, hf);
-            h2mu_1d(hf, mu);
-            const R mu4 = R(3) * hf[0] + R(12) * hf[2];
+            // degree-4 moment of the degree-3 expansion: 3 h0 + 12 h2, h2 = (mu_2 - mu_0) / 2
+            const R mu4 = R(6) * mu[2] - R(3) * mu[0];
             h2mu_1d(hgf, mg);
             shift_1d(mg, r, d, 3);
-            mg[3] = R(0);
-            mu2h_1d(mg, hgf);
-            hgf[3] = R(0);
-            h2mu_1d(hgf, mg);
+            mg[3] = R(3) * mg[1]; // degree-3 moment of the order-2 g expansion: 3 h1
             const R kf = (R)(dt / dxc) * sgn;
             const R ks = kf * su, ku = kf * ux;
             mfo[0] -= ks * mu[1] + ku * mu[0];
@@ -1622,24 +1618,26 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             for (int m = 0; m < 10; ++m) hf[m] = S.F[(3 + m) * nf + f];
 #pragma unroll
             for (int m = 0; m < 6; ++m) hgf[m] = S.F[(13 + m) * nf + f];
-            // face populations in the cell frame: coefficients, then raw moments
+            // raw moments of the face populations in the cell frame
             h2mu_2d(hf, mu, 10);
             shift_2d(mu, r, dx, dy, 10);
-            mu2h_2d(mu, hf, 10);
-            h2mu_2d(hf, mu, 10);
             h2mu_2d(hgf, mg, 6);
             shift_2d(mg, r, dx, dy, 6);
-            mu2h_2d(mg, hgf, 6);
-#pragma unroll
-            for (int m = 6; m < 10; ++m) hgf[m] = R(0);
-            h2mu_2d(hgf, mg, 10);
+            // degree-3 moments of the order-2 g expansion: mu_30 = 3 h10, mu_21 = h01,
+            // mu_12 = h10, mu_03 = 3 h01, with h10 = mu_10, h01 = mu_01
+            mg[6] = R(3) * mg[1];
+            mg[7] = mg[2];
+            mg[8] = mg[1];
+            mg[9] = R(3) * mg[2];
             const R kf = (R)(dt / (axis ? P.dy : P.dx)) * sgn;
             const R ks = kf * su, ku = kf * (axis ? uy : ux);
-            // degree-4 moments of the f expansion that the normal flux needs
-            const R m22 = hf[0] + R(2) * (hf[3] + hf[5]);
-            const R m31 = R(3) * hf[4]; // mu_31 = mu_13 = 3 h11
+            // degree-4 moments of the degree-3 f expansion that the normal flux needs, from
+            // h00 = mu_00, h20 = (mu_20 - mu_00) / 2, h02 = (mu_02 - mu_00) / 2, h11 = mu_11:
+            // mu_22 = h00 + 2 h20 + 2 h02, mu_31 = mu_13 = 3 h11, mu_40 = 3 h00 + 12 h20
+            const R m22 = mu[3] + mu[5] - mu[0];
+            const R m31 = R(3) * mu[4];
             if (axis == 0) {
-                const R m40 = R(3) * hf[0] + R(12) * hf[3];
+                const R m40 = R(6) * mu[3] - R(3) * mu[0];
                 // alpha + e_x: 00->10 10->20 01->11 20->30 11->21 02->12 30->40 21->31 12->22 03->13
                 mfo[0] -= ks * mu[1] + ku * mu[0];
                 mfo[1] -= ks * mu[3] + ku * mu[1];
@@ -1658,7 +1656,7 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
                 mgo[4] -= ks * mg[7] + ku * mg[4];
                 mgo[5] -= ks * mg[8] + ku * mg[5];
             } else {
-                const R m04 = R(3) * hf[0] + R(12) * hf[5];
+                const R m04 = R(6) * mu[5] - R(3) * mu[0];
                 // alpha + e_y: 00->01 10->11 01->02 20->21 11->12 02->03 30->31 21->22 12->13 03->04
                 mfo[0] -= ks * mu[2] + ku * mu[0];
                 mfo[1] -= ks * mu[4] + ku * mu[1];
