@@ -146,7 +146,7 @@ def other_workload(args):
         out[prec] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
                      "cell_updates": st["cell_updates"], "mean_iters": st["iters_total"] / max(st["faces"], 1),
                      "failed_instances": st["failed_instances"], "status": st["status"],
-                     "kernel_ms": {"dt": kt["dt"], "face": kt["face"] - kt["tail"], "face_tail": kt["tail"],
+                     "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
                                    "cell": kt["cell"]}, "tiles": list(ctx.tiles())}
         ctx.close()
     cpu = None
@@ -267,7 +267,7 @@ def main():
             "ms_per_step": 1e3 * ell / args.steps,
             "mean_iters": stl["iters_total"] / max(stl["faces"], 1),
             "nonconverged_faces": stl["nonconverged"],
-            "kernel_ms": {"seed": ktl["seed"], "face": ktl["face"], "face_tail": ktl["tail"],
+            "kernel_ms": {"seed": ktl["seed"], "face": ktl["face"], "tail_with_cells": ktl["tail"],
                           "cell": ktl["cell"]},
             "train": {"samples": nsamp, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                       "seconds": t_train},
@@ -287,8 +287,8 @@ def main():
             "value": st64["converged_cell_updates"] / el64 / 1e6,
             "ms_per_step": 1e3 * el64 / args.steps,
             "mean_iters": st64["iters_total"] / max(st64["faces"], 1),
-            "face_kernel_ms": kt64["face"] - kt64["tail"], "tail_kernel_ms": kt64["tail"],
-            "cell_kernel_ms": kt64["cell"],
+            "kernel_ms": {"dt": kt64["dt"], "face": kt64["face"], "tail_with_cells": kt64["tail"],
+                          "cell": kt64["cell"]},
             "tiles": list(ctx64.tiles()),
         }
         rec["mixed_rel_l1_vs_fp64"] = {"rho": l1[0], "rho_u": l1[1], "rho_v": l1[2], "rho_E": l1[3]}
@@ -300,7 +300,7 @@ def main():
     main_iters = (st32["iters_total"] - st32["tail_iters"]) / args.steps
     main_finals = (st32["faces"] - st32["tail_faces"]) / args.steps
     face_flops = main_iters * FLOPS_FACE_ITER[2] + main_finals * FLOPS_FACE_FINAL[2]
-    face_main_ms = kt32["face"] - kt32["tail"]
+    face_main_ms = kt32["face"]
     traffic = measured_traffic()
     achieved = face_flops / (face_main_ms * 1e-3) / 1e12
     line = {
@@ -332,7 +332,9 @@ def main():
         "mean_iters_per_face": iters_per_face,
         "fallback_faces": st32["fallback"],
         "nonconverged_faces": st32["nonconverged"],
-        "kernel_ms": {"dt": kt32["dt"], "face": face_main_ms, "face_tail": kt32["tail"],
+        # face: the face kernel; tail_with_cells: the launch that finishes the deferred faces
+        # and updates every cell; cell: a separate cell update (none in 2D with a tail)
+        "kernel_ms": {"dt": kt32["dt"], "face": face_main_ms, "tail_with_cells": kt32["tail"],
                       "cell": kt32["cell"]},
         "tail_faces_per_step": st32["tail_faces"] / args.steps,
         "tiles": list(ctx32.tiles()),

@@ -192,10 +192,11 @@ pond_status pond_set_graph(pond_ctx *ctx, int32_t on);
  * POND_EINVAL for k < 0. */
 pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
 
-/* Average device time in ms per step of each kernel over the last pond_step call,
+/* Average device time in ms per step of each launch over the last pond_step call,
  * measured with HIP events on the context's stream, into a caller array of 5:
- * out[0] dt/time kernel, out[1] face kernel including its tail kernel, out[2] cell
- * update kernel, out[3] seed (MLP) kernel, out[4] tail kernel alone.
+ * out[0] dt/time kernel, out[1] face kernel, out[2] cell update kernel (1D, and 2D
+ * without a tail kernel; 0 otherwise), out[3] seed (MLP) kernels, out[4] 2D with a tail
+ * kernel: the launch that finishes the deferred faces and updates every cell (0 otherwise).
  * Timing is recorded only after pond_enable_timing(ctx, 1). */
 pond_status pond_enable_timing(pond_ctx *ctx, int32_t on);
 pond_status pond_kernel_times(const pond_ctx *ctx, double *out);

@@ -39,7 +39,7 @@ struct pond_ctx {
     int *inst_err = nullptr;
     double *scratch = nullptr; // read-out staging (4 x ncell doubles)
     // 2D: faces handed from the face kernel to the tail kernel
-    int *tail_f = nullptr, *tail_meta = nullptr, *tail_count = nullptr;
+    int *tail_f = nullptr, *tail_meta = nullptr, *tail_count = nullptr, *tblock = nullptr;
     void *tail_s = nullptr;
     // host mirrors
     std::vector<int64_t> h_cell_off;
@@ -113,10 +113,14 @@ State<R> state_of(pond_ctx *c)
     S.tail_s = reinterpret_cast<R *>(c->tail_s);
     S.tail_meta = c->tail_meta;
     S.tail_count = c->tail_count;
+    S.tblock = c->tblock;
     return S;
 }
 
 unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+// blocks per axis of the update of the cells in the tail faces' stencils
+constexpr unsigned kCellTailBlocks = 128;
 
 // 2D face tiles the autotuner tries (the first is the default)
 const std::pair<int, int> kTiles2D[] = {{8, 8}, {16, 4}, {16, 8}, {16, 16}, {32, 8}, {64, 4}, {32, 2}};
@@ -181,8 +185,9 @@ int compute_span(const pond_ctx *c, int B)
     return span;
 }
 
+// the face kernel, and in 2D (with_tail) the tail kernel after it
 template <int D, typename R>
-hipError_t launch_face(pond_ctx *c, int bx, int by)
+hipError_t launch_face(pond_ctx *c, int bx, int by, bool with_tail)
 {
     State<R> S = state_of<R>(c);
     if (D == 1) {
@@ -199,8 +204,7 @@ hipError_t launch_face(pond_ctx *c, int bx, int by)
             face_kernel_2d<R, 1><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         else
             face_kernel_2d<R, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
-        if (c->ev) (void)hipEventRecord(c->ev[3], c->stream);
-        if (c->P.iter_split > 0) {
+        if (with_tail && c->P.iter_split > 0) {
             // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
             dim3 tgrid(NSLOT * 4, 2);
             if (c->P.limiter == POND_LIM_MINMOD)
@@ -225,11 +229,22 @@ hipError_t launch_step(pond_ctx *c, double t_end)
         if (e != hipSuccess) return e;
     }
     if (tm) (void)hipEventRecord(c->ev[2], c->stream);
-    hipError_t e = launch_face<D, R>(c, c->bx, c->by);
+    hipError_t e = launch_face<D, R>(c, c->bx, c->by, false);
     if (e != hipSuccess) return e;
-    if (tm && D == 1) (void)hipEventRecord(c->ev[3], c->stream);
-    if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-    cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+    if (tm) (void)hipEventRecord(c->ev[3], c->stream);
+    if (D == 2 && c->P.iter_split > 0) {
+        // the tail beside the update of the cells outside its faces' stencils, then those
+        const unsigned nb = 2 * TAIL_BLOCKS + (unsigned)blocks(c->P.ncell, 256);
+        if (c->P.limiter == POND_LIM_MINMOD)
+            tail_cell_kernel_2d<R, 1><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+        else
+            tail_cell_kernel_2d<R, 0><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+        if (tm) (void)hipEventRecord(c->ev[4], c->stream);
+        cell_tail_kernel_2d<R><<<dim3(kCellTailBlocks, 2), 256, 0, c->stream>>>(c->P, S, c->slot);
+    } else {
+        if (tm) (void)hipEventRecord(c->ev[4], c->stream);
+        cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+    }
     if (tm) (void)hipEventRecord(c->ev[5], c->stream);
     c->slot ^= 1;
     return hipGetLastError();
@@ -246,8 +261,16 @@ hipError_t face_once(pond_ctx *c, int bx, int by)
 {
     if (c->tail_count) tail_reset_kernel<<<1, 64, 0, c->stream>>>(c->tail_count);
     if (c->D == 1)
-        return c->precision == POND_FP64 ? launch_face<1, double>(c, bx, by) : launch_face<1, float>(c, bx, by);
-    return c->precision == POND_FP64 ? launch_face<2, double>(c, bx, by) : launch_face<2, float>(c, bx, by);
+        return c->precision == POND_FP64 ? launch_face<1, double>(c, bx, by, true)
+                                         : launch_face<1, float>(c, bx, by, true);
+    hipError_t e = c->precision == POND_FP64 ? launch_face<2, double>(c, bx, by, true)
+                                             : launch_face<2, float>(c, bx, by, true);
+    // no cell update follows here: clear the stencil marks the face kernel set
+    if (e == hipSuccess && c->tblock) {
+        clear_ints_kernel<<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->tblock, c->P.ncell);
+        e = hipGetLastError();
+    }
+    return e;
 }
 
 pond_status validate(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
@@ -316,7 +339,7 @@ void free_all(pond_ctx *c)
 {
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
                     c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch,
-                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count};
+                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -448,6 +471,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         alloc((void **)&c->tail_meta, sizeof(int) * P.tail_n);
         alloc(&c->tail_s, c->rsize * 6 * P.tail_n);
         alloc((void **)&c->tail_count, sizeof(int) * 2 * NSLOT);
+        alloc((void **)&c->tblock, sizeof(int) * n);
         P.iter_split = (cfg->precision == POND_FP64) ? 3 : 2;
     }
     if (!ok) {
@@ -559,7 +583,7 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
             float ms = 0.0f;
             (void)hipEventElapsedTime(&ms, e[0], e[1]);
             kt[0] += ms;
-            (void)hipEventElapsedTime(&ms, e[2], e[4]);
+            (void)hipEventElapsedTime(&ms, e[2], e[3]);
             kt[1] += ms;
             (void)hipEventElapsedTime(&ms, e[4], e[5]);
             kt[2] += ms;

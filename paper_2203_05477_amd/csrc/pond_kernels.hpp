@@ -73,6 +73,8 @@ struct State {
     R *tail_s;
     int *tail_meta;
     int *tail_count;           // 2 x NSLOT sub-list lengths, cleared by dt_kernel
+    int *tblock;               // per cell: nonzero while it is in the stencil of a face that
+                               // the tail kernel finishes this step (0 between steps)
 };
 
 template <int D>
@@ -818,6 +820,30 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
     S.fiter[f] = it | ((conv ? 0 : 1) << 16) | ((failed ? 1 : 0) << 17);
 }
 
+// cell (ci, cj) of stencil slot q (L, R, L-n, R+n, L-t, L+t, R-t, R+t) of face f
+template <int AXIS>
+PD void tail_cell(const Params &P, int64_t f, int q, int &ci, int &cj)
+{
+    int i, j; // the face's upper/right cell R
+    if (AXIS == 0) {
+        i = (int)(f % (P.nx + 1));
+        j = (int)(f / (P.nx + 1));
+    } else {
+        const int64_t g = f - P.nfx;
+        i = (int)(g % P.nx);
+        j = (int)(g / P.nx);
+    }
+    const int a = (q == 1 || q >= 6) ? 1 : (q == 2 ? -1 : (q == 3 ? 2 : 0)); // normal, from L
+    const int b = (q == 4 || q == 6) ? -1 : ((q == 5 || q == 7) ? 1 : 0);   // tangential
+    if (AXIS == 0) {
+        ci = i - 1 + a;
+        cj = j + b;
+    } else {
+        ci = i + b;
+        cj = j - 1 + a;
+    }
+}
+
 template <typename R, int AXIS, int LIM>
 PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[2], int sn,
                 int stn, int64_t f, double dt, FaceCount &cnt)
@@ -922,6 +948,16 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
             S.tail_s[4 * nf + e] = upp[1];
             S.tail_s[5 * nf + e] = Tpp;
             S.tail_meta[e] = it | ((have_pp ? 1 : 0) << 16) | ((restarted ? 1 : 0) << 17);
+        }
+        // the tail reads the start state of the face's 8 stencil cells: they wait for the
+        // update after the tail (the update beside it takes the other cells)
+        const double t = S.tstart[0];
+#pragma unroll 1
+        for (int q = 0; q < 8; ++q) {
+            int ci, cj;
+            tail_cell<AXIS>(P, f, q, ci, cj);
+            const CellRef cr = map2d(P, ci, cj, t);
+            if (cr.src >= 0) S.tblock[cr.src] = 1;
         }
         return;
     }
@@ -1130,30 +1166,6 @@ PD R group_sum(R v)
     v += dpp<DPP_HALF_MIRROR>(v);
     v += dpp<DPP_MIRROR>(v);
     return v;
-}
-
-// cell (ci, cj) of stencil slot q (L, R, L-n, R+n, L-t, L+t, R-t, R+t) of face f
-template <int AXIS>
-PD void tail_cell(const Params &P, int64_t f, int q, int &ci, int &cj)
-{
-    int i, j; // the face's upper/right cell R
-    if (AXIS == 0) {
-        i = (int)(f % (P.nx + 1));
-        j = (int)(f / (P.nx + 1));
-    } else {
-        const int64_t g = f - P.nfx;
-        i = (int)(g % P.nx);
-        j = (int)(g / P.nx);
-    }
-    const int a = (q == 1 || q >= 6) ? 1 : (q == 2 ? -1 : (q == 3 ? 2 : 0)); // normal, from L
-    const int b = (q == 4 || q == 6) ? -1 : ((q == 5 || q == 7) ? 1 : 0);   // tangential
-    if (AXIS == 0) {
-        ci = i - 1 + a;
-        cj = j + b;
-    } else {
-        ci = i + b;
-        cj = j - 1 + a;
-    }
 }
 
 // One face per 16-lane group. Every lane of the wave runs every instruction of the
@@ -1374,57 +1386,72 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
     wave_fence(); // the records are rebuilt for the group's next face
 }
 
-template <typename R, int LIM>
-__global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
+// pre[s] = entries in the axis's sub-lists before s (s = 0..NSLOT), by the block's 256
+// threads, one sub-list each; wtot: 4 ints of scratch
+PD void tail_prefix(const Params &P, const int *tail_count, int axis, int *pre, int *wtot)
 {
-    __shared__ R lds[16 * TAIL_GROUP];
+    static_assert(NSLOT == 256, "one sub-list per thread of a 256-thread block");
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    int x = min(tail_count[axis * NSLOT + tid], P.tail_cap);
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        const int y = __shfl_up(x, d, 64);
+        if (lane >= d) x += y;
+    }
+    if (lane == 63) wtot[w] = x;
+    __syncthreads();
+    for (int v = 0; v < w; ++v) x += wtot[v];
+    pre[tid + 1] = x;
+    if (tid == 0) pre[0] = 0;
+    __syncthreads();
+}
+
+// tail list entry of the axis's k-th face (0 <= k < pre[NSLOT]): in the last sub-list s
+// with pre[s] <= k (empty sub-lists are skipped)
+PD int64_t tail_entry(const Params &P, const int *pre, int axis, int64_t k)
+{
+    int lo = 0, hi = NSLOT - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (pre[mid] <= k)
+            lo = mid;
+        else
+            hi = mid - 1;
+    }
+    return (int64_t)(axis * NSLOT + lo) * P.tail_cap + (k - pre[lo]);
+}
+
+// LDS of one tail block
+template <typename R>
+struct TailShared {
+    R rec[16 * TAIL_GROUP];
+    int pre[NSLOT + 1];
+    int wtot[4];
+};
+
+// block bx of nbx (256 threads) of the tail work of one axis
+template <typename R, int LIM>
+PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int axis, int bx, int nbx)
+{
+    R *lds = sh.rec;
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
     const double t = S.tstart[0];
-    const int axis = blockIdx.y;
     const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
     R *rec = lds + grp * TAIL_GROUP, *coef = rec + TAIL_REC;
     // The faces of the axis's NSLOT sub-lists, concatenated, are dealt out 16 per block in
     // turn, so that no block works through a long sub-list alone (the hard faces cluster in
-    // the sub-lists of the face-kernel waves that cover a shock). pre[s] = faces in the
-    // sub-lists before s (one sub-list per thread of the block).
-    static_assert(NSLOT == 256, "one sub-list per thread of a 256-thread block");
-    __shared__ int pre[NSLOT + 1];
-    __shared__ int wtot[4];
-    {
-        const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-        int x = min(S.tail_count[axis * NSLOT + tid], P.tail_cap);
-#pragma unroll
-        for (int d = 1; d < 64; d <<= 1) {
-            const int y = __shfl_up(x, d, 64);
-            if (lane >= d) x += y;
-        }
-        if (lane == 63) wtot[w] = x;
-        __syncthreads();
-        for (int v = 0; v < w; ++v) x += wtot[v];
-        pre[tid + 1] = x;
-        if (tid == 0) pre[0] = 0;
-        __syncthreads();
-    }
+    // the sub-lists of the face-kernel waves that cover a shock).
+    int *pre = sh.pre;
+    tail_prefix(P, S.tail_count, axis, pre, sh.wtot);
     const int total = pre[NSLOT];
     FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     // wave-uniform loop: a group without a face in this round takes part with has = false
-    for (int64_t k0 = (int64_t)blockIdx.x * 16; __any(k0 + grp < total); k0 += (int64_t)gridDim.x * 16) {
+    for (int64_t k0 = (int64_t)bx * 16; __any(k0 + grp < total); k0 += (int64_t)nbx * 16) {
         const int64_t k = k0 + grp;
         const bool has = k < total;
         int64_t e = 0;
-        if (has) {
-            // the last sub-list s with pre[s] <= k holds face k (empty sub-lists are skipped)
-            int lo = 0, hi = NSLOT - 1;
-            while (lo < hi) {
-                const int mid = (lo + hi + 1) >> 1;
-                if (pre[mid] <= k)
-                    lo = mid;
-                else
-                    hi = mid - 1;
-            }
-            e = (int64_t)(axis * NSLOT + lo) * P.tail_cap + (k - pre[lo]);
-        }
+        if (has) e = tail_entry(P, pre, axis, k);
         if (axis == 0)
             tail_face<R, 0, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
         else
@@ -1438,6 +1465,20 @@ __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
     stat_add(S.stats, ST_TAIL_FACES, cnt.tail_faces);
     stat_add(S.stats, ST_TAIL_ITERS, cnt.tail_iters);
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+template <typename R, int LIM>
+__global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
+{
+    __shared__ TailShared<R> sh;
+    tail_block<R, LIM>(P, S, sh, blockIdx.y, blockIdx.x, gridDim.x);
+}
+
+// clears n ints (grid-stride)
+__global__ void clear_ints_kernel(int *p, int64_t n)
+{
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x)
+        p[i] = 0;
 }
 
 // clears the tail counters where no dt_kernel runs before a face kernel (the autotuner)
@@ -1502,11 +1543,12 @@ template <int D, typename R>
 PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
                     unsigned long long &bits, bool &all_conv);
 
+// update of cell c (taken = false: no cell for this lane), with the wave-level CFL maximum
+// and counters; every lane of the wave calls it
 template <int D, typename R>
-__global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
+PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int slot)
 {
-    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    const bool active = c < P.ncell;
+    const bool active = taken && c < P.ncell;
     const int k = (active && S.cell_inst) ? S.cell_inst[c] : 0;
     const double dt = S.dt[k];
     const bool work = active && dt > 0.0;
@@ -1516,6 +1558,65 @@ __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slo
     vmax_update<R>(P, S, slot ^ 1, k, work, bits);
     stat_add(S.stats, ST_CELLS, work ? 1 : 0);
     stat_add(S.stats, ST_CONV_CELLS, (work && all_conv) ? 1 : 0);
+}
+
+template <int D, typename R>
+__global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
+{
+    cell_step<D, R>(P, S, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, true, slot);
+}
+
+// The tail work (blocks [0, 2 * TAIL_BLOCKS): TAIL_BLOCKS per axis) beside the update of
+// the cells outside the stencils of the tail's faces (the other blocks, 256 cells each),
+// whose waves fill the issue slots that the tail's dependency chains leave idle. Neither
+// reads a cell that the other writes.
+constexpr int TAIL_BLOCKS = 4 * NSLOT;
+
+template <typename R, int LIM>
+__global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S, int slot)
+{
+    __shared__ TailShared<R> sh;
+    if ((int)blockIdx.x < 2 * TAIL_BLOCKS) {
+        tail_block<R, LIM>(P, S, sh, (int)blockIdx.x / TAIL_BLOCKS, (int)blockIdx.x % TAIL_BLOCKS,
+                           TAIL_BLOCKS);
+        return;
+    }
+    const int64_t c = (int64_t)(blockIdx.x - 2 * TAIL_BLOCKS) * 256 + threadIdx.x;
+    cell_step<2, R>(P, S, c, c < P.ncell && !S.tblock[c], slot);
+}
+
+// After the tail: the cells in the stencils of its faces. Thread 8 k + q takes stencil cell
+// q of the axis's k-th tail face; the thread that clears the cell's mark updates it, so every
+// marked cell is updated once and the marks are 0 for the next step. Grid: (blocks, 2 axes).
+template <typename R>
+__global__ __launch_bounds__(256) void cell_tail_kernel_2d(Params P, State<R> S, int slot)
+{
+    __shared__ int pre[NSLOT + 1];
+    __shared__ int wtot[4];
+    const int axis = blockIdx.y;
+    tail_prefix(P, S.tail_count, axis, pre, wtot);
+    const int64_t total8 = 8 * (int64_t)pre[NSLOT];
+    const double t = S.tstart[0];
+    for (int64_t k0 = (int64_t)blockIdx.x * 256; __any(k0 + (int64_t)threadIdx.x < total8);
+         k0 += (int64_t)gridDim.x * 256) {
+        const int64_t kk = k0 + threadIdx.x;
+        int64_t cell = 0;
+        bool own = false;
+        if (kk < total8) {
+            const int64_t f = S.tail_f[tail_entry(P, pre, axis, kk >> 3)];
+            int ci, cj;
+            if (axis == 0)
+                tail_cell<0>(P, f, (int)(kk & 7), ci, cj);
+            else
+                tail_cell<1>(P, f, (int)(kk & 7), ci, cj);
+            const CellRef cr = map2d(P, ci, cj, t);
+            if (cr.src >= 0 && atomicExch(&S.tblock[cr.src], 0) != 0) {
+                own = true;
+                cell = cr.src;
+            }
+        }
+        cell_step<2, R>(P, S, cell, own, slot);
+    }
 }
 
 template <int D, typename R>
@@ -1758,6 +1859,7 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
         bits = (unsigned long long)__double_as_longlong(rate);
     }
     vmax_update<R>(P, S, 0, k, c < n, bits);
+    if (c < n && S.tblock) S.tblock[c] = 0;
     if (c < P.nface) {
         S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
         S.fiter[c] = 0; // read by the learned seed's selection before the first step

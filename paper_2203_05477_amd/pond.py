@@ -341,6 +341,9 @@ class Context:
         load().pond_enable_timing(self._h, 1 if on else 0)
 
     def kernel_times(self):
+        """Mean ms per step of each launch of the last step() with timing on: dt, face (the
+        face kernel), cell (the cell update kernel; 0 in 2D with a tail kernel), seed, tail
+        (2D: the launch that finishes the deferred faces and updates every cell)."""
         out = np.zeros(5)
         load().pond_kernel_times(self._h, _ptr(out))
         return {"dt": out[0], "face": out[1], "cell": out[2], "seed": out[3], "tail": out[4]}
