@@ -1442,6 +1442,16 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int ax
     // The faces of the axis's NSLOT sub-lists, concatenated, are dealt out 16 per block in
     // turn, so that no block works through a long sub-list alone (the hard faces cluster in
     // the sub-lists of the face-kernel waves that cover a shock).
+    {
+        // blocks past the axis's last face leave before the prefix (every wave finds the
+        // same total, so the whole block leaves)
+        const int lane = threadIdx.x & 63;
+        int x = 0;
+        for (int sl = lane; sl < NSLOT; sl += 64) x += min(S.tail_count[axis * NSLOT + sl], P.tail_cap);
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+        if ((int64_t)bx * 16 >= x) return;
+    }
     int *pre = sh.pre;
     tail_prefix(P, S.tail_count, axis, pre, sh.wtot);
     const int total = pre[NSLOT];
@@ -1491,51 +1501,59 @@ __global__ void tail_reset_kernel(int *count)
 // cell update (Sec. III.B.2) + reframe of the next step (Sec. III.B.4)
 // ---------------------------------------------------------------------------------
 
-// conserved flux through a face along `axis` (lab frame, FP64) from the face state:
-// mass sum f v_a, momentum sum f v_b v_a, energy sum (|v|^2/2) f v_a + sum g v_a
+// conserved flux through a face along `axis` (lab frame) from the face state: mass sum f v_a,
+// momentum sum f v_b v_a, energy sum (|v|^2/2) f v_a + sum g v_a. Computed in the precision
+// of the face state and written with explicit fma, so that the two cells of a face get the
+// same bits from whichever kernel updates them: the FP64 flux-form update then telescopes
+// exactly between neighbours.
 template <int D, typename R>
 PD void face_flux(const Params &P, const State<R> &S, int64_t f, int axis, double out[4])
 {
     const int64_t nf = P.nface;
-    double u[2], T, h[10], hg[6];
     if (D == 1) {
-        u[0] = S.F[f];
-        u[1] = 0.0;
-        T = S.F[nf + f];
+        const R u = S.F[f], T = S.F[nf + f];
+        R h[4], hg[2];
         for (int k = 0; k < 4; ++k) h[k] = S.F[(2 + k) * nf + f];
-        for (int k = 0; k < 3; ++k) hg[k] = S.F[(6 + k) * nf + f];
-        double s = sqrt(T), rho = h[0];
-        double m1 = h[1], m2 = h[0] + 2.0 * h[2], m3 = 3.0 * h[1] + 6.0 * h[3];
-        double uu = u[0];
-        out[0] = rho * uu + s * m1;
-        out[1] = rho * uu * uu + 2.0 * s * uu * m1 + s * s * m2;
-        out[2] = 0.5 * (rho * uu * uu * uu + 3.0 * s * uu * uu * m1 + 3.0 * s * s * uu * m2 +
-                        s * s * s * m3) +
-                 hg[0] * uu + s * hg[1];
+        for (int k = 0; k < 2; ++k) hg[k] = S.F[(6 + k) * nf + f];
+        const R s = sqrt(T), rho = h[0], s2 = s * s;
+        const R m1 = h[1], m2 = fma(R(2), h[2], h[0]), m3 = fma(R(6), h[3], R(3) * h[1]);
+        const R uu = u * u;
+        out[0] = (double)fma(rho, u, s * m1);
+        out[1] = (double)fma(rho, uu, fma(R(2) * s * u, m1, s2 * m2));
+        R e = rho * uu * u;
+        e = fma(R(3) * s * uu, m1, e);
+        e = fma(R(3) * s2 * u, m2, e);
+        e = fma(s2 * s, m3, e);
+        out[2] = (double)fma(R(0.5), e, fma(hg[0], u, s * hg[1]));
+        out[3] = 0.0;
     } else {
-        u[0] = S.F[f];
-        u[1] = S.F[nf + f];
-        T = S.F[2 * nf + f];
+        const R u[2] = {S.F[f], S.F[nf + f]};
+        const R T = S.F[2 * nf + f];
+        R h[10], hg[3];
         for (int k = 0; k < 10; ++k) h[k] = S.F[(3 + k) * nf + f];
-        for (int k = 0; k < 6; ++k) hg[k] = S.F[(13 + k) * nf + f];
-        double s = sqrt(T), rho = h[0];
-        double m1[2] = {h[1], h[2]};
-        double m2[2][2] = {{h[0] + 2.0 * h[3], h[4]}, {h[4], h[0] + 2.0 * h[5]}};
-        double m3x = 3.0 * h[1] + 6.0 * h[6], m3xxy = h[2] + 2.0 * h[7];
-        double m3xyy = h[1] + 2.0 * h[8], m3y = 3.0 * h[2] + 6.0 * h[9];
+        for (int k = 0; k < 3; ++k) hg[k] = S.F[(13 + k) * nf + f];
+        const R s = sqrt(T), rho = h[0], s2 = s * s;
+        const R m1[2] = {h[1], h[2]};
+        const R m2[2][2] = {{fma(R(2), h[3], h[0]), h[4]}, {h[4], fma(R(2), h[5], h[0])}};
+        // mu_30 + mu_12 (axis x) or mu_21 + mu_03 (axis y)
+        const R m3c = (axis == 0) ? fma(R(6), h[6], R(3) * h[1]) + fma(R(2), h[8], h[1])
+                                  : fma(R(2), h[7], h[2]) + fma(R(6), h[9], R(3) * h[2]);
         const int a = axis;
-        double ua = u[a];
-        double uu = u[0] * u[0] + u[1] * u[1];
-        double um1 = u[0] * m1[0] + u[1] * m1[1];
-        double trm2 = m2[0][0] + m2[1][1];
-        double ugm2 = u[0] * m2[0][a] + u[1] * m2[1][a];
-        double m3c = (a == 0) ? (m3x + m3xyy) : (m3xxy + m3y);
-        out[0] = rho * ua + s * m1[a];
+        const R ua = u[a], m1a = m1[a];
+        const R uu = fma(u[0], u[0], u[1] * u[1]);
+        const R um1 = fma(u[0], m1[0], u[1] * m1[1]);
+        const R trm2 = m2[0][0] + m2[1][1];
+        const R ugm2 = fma(u[0], m2[0][a], u[1] * m2[1][a]);
+        out[0] = (double)fma(rho, ua, s * m1a);
         for (int b = 0; b < 2; ++b)
-            out[1 + b] = rho * u[b] * ua + s * (u[b] * m1[a] + ua * m1[b]) + s * s * m2[b][a];
-        out[3] = 0.5 * (rho * uu * ua + s * uu * m1[a] + 2.0 * s * ua * um1 + 2.0 * s * s * ugm2 +
-                        s * s * ua * trm2 + s * s * s * m3c) +
-                 hg[0] * ua + s * hg[1 + a];
+            out[1 + b] = (double)fma(rho * u[b], ua, fma(s, fma(u[b], m1a, ua * m1[b]), s2 * m2[b][a]));
+        R e = rho * uu * ua;
+        e = fma(s * uu, m1a, e);
+        e = fma(R(2) * s * ua, um1, e);
+        e = fma(R(2) * s2, ugm2, e);
+        e = fma(s2 * ua, trm2, e);
+        e = fma(s2 * s, m3c, e);
+        out[3] = (double)fma(R(0.5), e, fma(hg[0], ua, s * hg[1 + a]));
     }
 }
 
