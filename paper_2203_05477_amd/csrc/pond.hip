@@ -119,9 +119,6 @@ State<R> state_of(pond_ctx *c)
 
 unsigned blocks(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
-// blocks per axis of the update of the cells in the tail faces' stencils
-constexpr unsigned kCellTailBlocks = 128;
-
 // 2D face tiles the autotuner tries (the first is the default)
 const std::pair<int, int> kTiles2D[] = {{8, 8}, {16, 4}, {16, 8}, {16, 16}, {32, 8}, {64, 4}, {32, 2}};
 
@@ -240,7 +237,7 @@ hipError_t launch_step(pond_ctx *c, double t_end)
         else
             tail_cell_kernel_2d<R, 0><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
         if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-        cell_tail_kernel_2d<R><<<dim3(kCellTailBlocks, 2), 256, 0, c->stream>>>(c->P, S, c->slot);
+        cell_marked_kernel_2d<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
     } else {
         if (tm) (void)hipEventRecord(c->ev[4], c->stream);
         cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);

@@ -144,13 +144,14 @@ template <int D>
 PD void prim(const double *U, int64_t n, int64_t c, double &rho, double u[2], double &T, double Cv)
 {
     rho = U[c];
+    const double irho = 1.0 / rho;
     double ke = 0.0;
     for (int a = 0; a < D; ++a) {
-        u[a] = U[(1 + a) * n + c] / rho;
+        u[a] = U[(1 + a) * n + c] * irho;
         ke += u[a] * u[a];
     }
     if (D == 1) u[1] = 0.0;
-    T = (U[(1 + D) * n + c] / rho - 0.5 * ke) / Cv;
+    T = (U[(1 + D) * n + c] * irho - 0.5 * ke) / Cv;
 }
 
 PD size_t vmax_at(const Params &P, int parity, int k, int copy)
@@ -1603,38 +1604,16 @@ __global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S,
     cell_step<2, R>(P, S, c, c < P.ncell && !S.tblock[c], slot);
 }
 
-// After the tail: the cells in the stencils of its faces. Thread 8 k + q takes stencil cell
-// q of the axis's k-th tail face; the thread that clears the cell's mark updates it, so every
-// marked cell is updated once and the marks are 0 for the next step. Grid: (blocks, 2 axes).
+// After the tail: the cells in the stencils of its faces (marked by the face kernel), one
+// thread per cell of the grid; each clears its mark for the next step.
 template <typename R>
-__global__ __launch_bounds__(256) void cell_tail_kernel_2d(Params P, State<R> S, int slot)
+__global__ __launch_bounds__(256) void cell_marked_kernel_2d(Params P, State<R> S, int slot)
 {
-    __shared__ int pre[NSLOT + 1];
-    __shared__ int wtot[4];
-    const int axis = blockIdx.y;
-    tail_prefix(P, S.tail_count, axis, pre, wtot);
-    const int64_t total8 = 8 * (int64_t)pre[NSLOT];
-    const double t = S.tstart[0];
-    for (int64_t k0 = (int64_t)blockIdx.x * 256; __any(k0 + (int64_t)threadIdx.x < total8);
-         k0 += (int64_t)gridDim.x * 256) {
-        const int64_t kk = k0 + threadIdx.x;
-        int64_t cell = 0;
-        bool own = false;
-        if (kk < total8) {
-            const int64_t f = S.tail_f[tail_entry(P, pre, axis, kk >> 3)];
-            int ci, cj;
-            if (axis == 0)
-                tail_cell<0>(P, f, (int)(kk & 7), ci, cj);
-            else
-                tail_cell<1>(P, f, (int)(kk & 7), ci, cj);
-            const CellRef cr = map2d(P, ci, cj, t);
-            if (cr.src >= 0 && atomicExch(&S.tblock[cr.src], 0) != 0) {
-                own = true;
-                cell = cr.src;
-            }
-        }
-        cell_step<2, R>(P, S, cell, own, slot);
-    }
+    const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const bool marked = c < P.ncell && S.tblock[c] != 0;
+    if (!__any(marked)) return;
+    if (marked) S.tblock[c] = 0;
+    cell_step<2, R>(P, S, c, marked, slot);
 }
 
 template <int D, typename R>
@@ -1645,10 +1624,12 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
     const int64_t nf = P.nface;
     double rho, ud[2], T;
     prim<D>(S.U, n, c, rho, ud, T, P.Cv);
-    const R su = (R)sqrt(T), inv_su = (R)(1.0 / sqrt(T));
+    const double sT = sqrt(T);
+    const R su = (R)sT, inv_su = (R)(1.0 / sT);
     const R ux = (R)ud[0], uy = (R)ud[1];
     const double eps = dt * rho * T / P.mu;
-    const R A = (R)((2.0 - eps) / (2.0 + eps)), Bc = (R)(2.0 * eps / (2.0 + eps));
+    const double i2e = 1.0 / (2.0 + eps);
+    const R A = (R)((2.0 - eps) * i2e), Bc = (R)(2.0 * eps * i2e);
     const double geq = (P.Cv - 0.5 * D) * rho * T;
     double dU[4] = {0.0, 0.0, 0.0, 0.0};
     bool all_conv = true;
@@ -1804,18 +1785,19 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
     // FP64 conserved update (flux form: exact telescoping between neighbours)
     double Un[4];
     for (int q = 0; q < D + 2; ++q) Un[q] = S.U[q * n + c] + dU[q];
-    double rn = Un[0], un[2] = {Un[1] / rn, D == 2 ? Un[2] / rn : 0.0};
+    const double rn = Un[0], irn = 1.0 / rn;
+    double un[2] = {Un[1] * irn, D == 2 ? Un[2] * irn : 0.0};
     double ke = un[0] * un[0] + un[1] * un[1];
-    double Tn = (Un[D + 1] / rn - 0.5 * ke) / P.Cv;
+    double Tn = (Un[D + 1] * irn - 0.5 * ke) / P.Cv;
     bool ok = (rn > 0.0) && (Tn > 0.0) && isfinite(Tn) && isfinite(ke);
     if (!ok) {
         atomicOr(S.err, ERR_NONPHYS);
         atomicOr(S.inst_err + k, 1);
     }
-    double sn = sqrt(fabs(Tn));
+    double sn = sqrt(fabs(Tn)), isn = 1.0 / sn;
     // reframe: non-equilibrium coefficients of the updated populations in the new
     // co-moving frame (Sec. II.C with u' = u, T' = T)
-    R r = (R)(sqrt(T) / sn), dxs = (R)((ud[0] - un[0]) / sn), dys = (R)((ud[1] - un[1]) / sn);
+    R r = (R)(sT * isn), dxs = (R)((ud[0] - un[0]) * isn), dys = (R)((ud[1] - un[1]) * isn);
     if (D == 1) {
         R hh[4];
         shift_1d(mfo, r, dxs, 4);
