@@ -333,7 +333,8 @@ PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double
         }
     }
     const double eps = dt * rho * T / P.mu;
-    const double Ap = (2.0 - 0.5 * eps) / (2.0 + eps), Bp = 1.5 * eps / (2.0 + eps);
+    const double i2e = 1.0 / (2.0 + eps);
+    const double Ap = (2.0 - 0.5 * eps) * i2e, Bp = 1.5 * eps * i2e;
     const double geq = (P.Cv - 0.5 * D) * rho * T;
     // g~'s zeroth coefficient from the energy: rho E = rho|u|^2/2 + T(tr h2 + D rho/2) + b0
     double trh2 = (D == 1) ? (double)fh[0] : (double)fh[0] + (double)fh[2];
@@ -576,7 +577,7 @@ PD void face_write(const Params &P, const State<R> &S, int64_t f, R *mf, R *mg, 
     } else {
         R h[10], hg[10];
         if (has_frame) {
-            R inv = R(1) / sf;
+            R inv = frcp(sf);
             R r = sl * inv, dx = (ul[0] - uf[0]) * inv, dy = (ul[1] - uf[1]) * inv;
             shift_2d(mf, r, dx, dy, 10);
             shift_2d(mg, r, dx, dy, 6);
@@ -617,12 +618,13 @@ PD void mean_frame(const R *L, int NT, int a, int b, const Params &P, R u[2], R 
         kb += ub[q] * ub[q];
     }
     e = 0.5 * (P.Cv * ra * Ta + 0.5 * ra * ka) + 0.5 * (P.Cv * rb * Tb + 0.5 * rb * kb);
+    const double ir = 1.0 / r;
     for (int q = 0; q < D; ++q) {
-        u[q] = (R)(m[q] / r);
-        ke += (m[q] / r) * (m[q] / r);
+        u[q] = (R)(m[q] * ir);
+        ke += (m[q] * ir) * (m[q] * ir);
     }
     if (D == 1) u[1] = R(0);
-    T = (R)((e / r - 0.5 * ke) / P.Cv);
+    T = (R)((e * ir - 0.5 * ke) / P.Cv);
 }
 
 // first-order upwind state from each neighbour's own frame (fallback), as raw moments
