@@ -114,6 +114,7 @@ State<R> state_of(pond_ctx *c)
     S.tail_meta = c->tail_meta;
     S.tail_count = c->tail_count;
     S.tblock = c->tblock;
+    S.seed_count = (c->cfg.seed_mode == POND_SEED_MLP && c->mlp.ready) ? c->mlp.count : nullptr;
     return S;
 }
 

@@ -73,6 +73,8 @@ struct State {
     R *tail_s;
     int *tail_meta;
     int *tail_count;           // 2 x NSLOT sub-list lengths, cleared by dt_kernel
+    int *seed_count;           // NSLOT lengths of the learned seed's face lists, cleared by
+                               // dt_kernel (null without a network)
     int *tblock;               // per cell: nonzero while it is in the stencil of a face that
                                // the tail kernel finishes this step (0 between steps)
 };
@@ -196,6 +198,8 @@ __global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_e
     }
     if (k == 0 && S.tail_count)
         for (int c = lane; c < 2 * NSLOT; c += 64) S.tail_count[c] = 0;
+    if (k == 0 && S.seed_count)
+        for (int c = lane; c < NSLOT; c += 64) S.seed_count[c] = 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         unsigned long long w = __shfl_xor(m, o, 64);

@@ -149,13 +149,14 @@ PD void face_features(const Params &P, const State<R> &S, int64_t f, float *x, f
     uc[0] = cells[4][1];
     uc[1] = cells[4][2];
     Tc = cells[4][3];
-    const double sc = sqrt(Tc), isc = 1.0 / sc;
+    // logarithms of ratios in FP32 (hardware log): the features feed a BF16 network
+    const double sc = sqrt(Tc), isc = 1.0 / sc, irc = 1.0 / rc, iTc = 1.0 / Tc;
 #pragma unroll
     for (int e = 0; e < 9; ++e) {
-        x[4 * e + 0] = (float)log(cells[e][0] / rc);
+        x[4 * e + 0] = __logf((float)(cells[e][0] * irc));
         x[4 * e + 1] = (float)((cells[e][1] - uc[0]) * isc);
         x[4 * e + 2] = (float)((cells[e][2] - uc[1]) * isc);
-        x[4 * e + 3] = (float)log(cells[e][3] / Tc);
+        x[4 * e + 3] = __logf((float)(cells[e][3] * iTc));
     }
     const int64_t nf = P.nface;
     double su[2], sT;
@@ -171,7 +172,7 @@ PD void face_features(const Params &P, const State<R> &S, int64_t f, float *x, f
     if (sT > 0.0) {
         x[36] = (float)((su[0] - uc[0]) * isc);
         x[37] = (float)((su[1] - uc[1]) * isc);
-        x[38] = (float)log(sT / Tc);
+        x[38] = __logf((float)(sT * iTc));
         x[39] = 1.0f;
     } else {
         x[36] = x[37] = x[38] = x[39] = 0.0f;
@@ -571,11 +572,6 @@ inline int64_t slot_cap(int64_t n)
     return 64 * ((waves + NSLOT - 1) / NSLOT);
 }
 
-__global__ void zero_ints_kernel(int *p, int n)
-{
-    for (int i = threadIdx.x; i < n; i += blockDim.x) p[i] = 0;
-}
-
 // faces that took at least `hard` iterations in the previous step (or did not converge)
 template <typename R>
 __global__ void mlp_select_kernel(Params P, State<R> S, int hard, int *list, int *count, int cap)
@@ -599,59 +595,99 @@ __global__ void mlp_select_kernel(Params P, State<R> S, int hard, int *list, int
     if (take && pos < cap) list[(int64_t)slot * cap + pos] = (int)f;
 }
 
-// features + network + seed write for the listed faces; one wave per 16 faces
-// block b works on sub-list b mod NSLOT, with the other blocks of that sub-list
+// features + network + seed write for the listed faces; one wave per 64 faces. The
+// faces of the NSLOT sub-lists, concatenated, are dealt out 16 per block in turn (the hard
+// faces cluster in the sub-lists of the waves that cover a shock).
 template <int D, typename R>
 __global__ __launch_bounds__(64) void mlp_seed_kernel(Params P, State<R> S, const __bf16 *wbf,
                                                       const float *master, const int *lists,
                                                       const int *counts, int cap)
 {
-    __shared__ float xs[16][MLP_IN + 1];
-    __shared__ float rs[16][4];
+    __shared__ float xs[64][MLP_IN + 1];
+    __shared__ float rs[64][4];
+    __shared__ int pre[NSLOT + 1];
+    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
+    {
+        // pre[s] = listed faces in the sub-lists before s; lane l sums sub-lists 4l..4l+3
+        static_assert(NSLOT == 256, "4 sub-lists per lane of a 64-lane block");
+        int v[4], x = 0;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            v[q] = min(counts[4 * l + q], cap);
+            x += v[q];
+        }
+#pragma unroll
+        for (int d = 1; d < 64; d <<= 1) {
+            const int y = __shfl_up(x, d, 64);
+            if (l >= d) x += y;
+        }
+        int run = x - (v[0] + v[1] + v[2] + v[3]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            pre[4 * l + q] = run;
+            run += v[q];
+        }
+        if (l == 63) pre[NSLOT] = x;
+        __syncthreads();
+    }
+    const int n = pre[NSLOT];
+    if ((int)blockIdx.x * 64 >= n) return;
     MlpRegs W;
     mlp_load_regs(wbf, master, W);
-    const int l = threadIdx.x & 63, g = l >> 4, c = l & 15;
-    const int slot = blockIdx.x % NSLOT, sub = blockIdx.x / NSLOT, nsub = gridDim.x / NSLOT;
-    const int n = min(counts[slot], cap);
-    const int *list = lists + (int64_t)slot * cap;
+    // list index of the k-th listed face: in the last sub-list s with pre[s] <= k
+    auto entry = [&](int k) {
+        int lo = 0, hi = NSLOT - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= k)
+                lo = mid;
+            else
+                hi = mid - 1;
+        }
+        return (int64_t)lo * cap + (k - pre[lo]);
+    };
     const int64_t nf = P.nface;
-    for (int t0 = sub * 16; t0 < n; t0 += nsub * 16) {
-        if (l < 16) {
-            if (t0 + l < n) {
-                float x[MLP_IN], ref[4];
-                face_features<D, R>(P, S, list[t0 + l], x, ref);
-                for (int q = 0; q < MLP_IN; ++q) xs[l][q] = x[q];
-                for (int q = 0; q < 4; ++q) rs[l][q] = ref[q];
-            } else {
-                for (int q = 0; q < MLP_IN; ++q) xs[l][q] = 0.0f;
-                rs[l][0] = rs[l][1] = 0.0f;
-                rs[l][2] = rs[l][3] = 1.0f;
-            }
+    for (int t0 = (int)blockIdx.x * 64; t0 < n; t0 += (int)gridDim.x * 64) {
+        // every lane gathers the features of one face, then 4 tiles of 16 faces go through
+        // the network
+        if (t0 + l < n) {
+            float x[MLP_IN], ref[4];
+            face_features<D, R>(P, S, lists[entry(t0 + l)], x, ref);
+            for (int q = 0; q < MLP_IN; ++q) xs[l][q] = x[q];
+            for (int q = 0; q < 4; ++q) rs[l][q] = ref[q];
+        } else {
+            for (int q = 0; q < MLP_IN; ++q) xs[l][q] = 0.0f;
+            rs[l][0] = rs[l][1] = 0.0f;
+            rs[l][2] = rs[l][3] = 1.0f;
         }
         __syncthreads();
-        bf16x8 xb[2];
+#pragma unroll 1
+        for (int tile = 0; tile < 4; ++tile) {
+            const int fc = 16 * tile + c; // face of this lane's column in the tile
+            bf16x8 xb[2];
 #pragma unroll
-        for (int kb = 0; kb < 2; ++kb)
+            for (int kb = 0; kb < 2; ++kb)
 #pragma unroll
-            for (int j = 0; j < 8; ++j) xb[kb][j] = (__bf16)xs[c][32 * kb + 8 * g + j];
-        f4 y = mlp_tile_forward(W, xb, nullptr, nullptr);
-        if (g == 0 && t0 + c < n) {
-            const int64_t f = list[t0 + c];
-            const int axis = (D == 2 && f >= P.nfx) ? 1 : 0;
-            const float *r = rs[c];
-            const float has = xs[c][39];
-            const float y0 = y[0] + has * xs[c][36], y1 = y[1] + has * xs[c][37];
-            const float y2 = y[2] + has * xs[c][38];
-            const double un = r[0] + (double)r[2] * y0;
-            const double ut = r[1] + (double)r[2] * y1;
-            const double T = (double)r[3] * exp((double)fminf(fmaxf(y2, -20.0f), 20.0f));
-            if (D == 1) {
-                S.F[f] = (R)un;
-                S.F[nf + f] = (R)T;
-            } else {
-                S.F[(axis ? 1 : 0) * nf + f] = (R)un;
-                S.F[(axis ? 0 : 1) * nf + f] = (R)ut;
-                S.F[2 * nf + f] = (R)T;
+                for (int j = 0; j < 8; ++j) xb[kb][j] = (__bf16)xs[fc][32 * kb + 8 * g + j];
+            f4 y = mlp_tile_forward(W, xb, nullptr, nullptr);
+            if (g == 0 && t0 + fc < n) {
+                const int64_t f = lists[entry(t0 + fc)];
+                const int axis = (D == 2 && f >= P.nfx) ? 1 : 0;
+                const float *r = rs[fc];
+                const float has = xs[fc][39];
+                const float y0 = y[0] + has * xs[fc][36], y1 = y[1] + has * xs[fc][37];
+                const float y2 = y[2] + has * xs[fc][38];
+                const double un = r[0] + (double)r[2] * y0;
+                const double ut = r[1] + (double)r[2] * y1;
+                const double T = (double)r[3] * exp((double)fminf(fmaxf(y2, -20.0f), 20.0f));
+                if (D == 1) {
+                    S.F[f] = (R)un;
+                    S.F[nf + f] = (R)T;
+                } else {
+                    S.F[(axis ? 1 : 0) * nf + f] = (R)un;
+                    S.F[(axis ? 0 : 1) * nf + f] = (R)ut;
+                    S.F[2 * nf + f] = (R)T;
+                }
             }
         }
         __syncthreads();
@@ -669,8 +705,7 @@ inline void mlp_free(MlpDevice &M)
 template <int D, typename R>
 hipError_t mlp_seed_launch(const MlpDevice &M, const Params &P, const State<R> &S, hipStream_t st)
 {
-    // cleared by a kernel, not a memset node, so that the sequence can be captured in a graph
-    zero_ints_kernel<<<1, 256, 0, st>>>(M.count, NSLOT);
+    // M.count is cleared by the step's dt_kernel (State::seed_count)
     const int cap = (int)slot_cap(P.nface);
     mlp_select_kernel<R><<<(unsigned)((P.nface + 255) / 256), 256, 0, st>>>(P, S, M.hard_iters, M.list, M.count, cap);
     mlp_seed_kernel<D, R><<<NSLOT * 4, 64, 0, st>>>(P, S, M.wbf, M.master, M.list, M.count, cap);
