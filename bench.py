@@ -38,6 +38,10 @@ FLOPS_FACE_FINAL = {1: 60, 2: 330}
 # FP64 / FP32 vector peaks of MI355X (no packed FP32 instructions are used: FP32 issues at
 # the FP64 rate, so both peaks are the 78.6 TFLOP/s non-packed figure)
 PEAK_VALU_TFLOPS = 78.6
+PEAK_HBM_GBPS = 8000.0
+# Algorithmic bytes of one 2D cell update (read U, coefficients and the cell's share of its
+# 4 face states, write U and coefficients), mixed / FP64
+CELL_BYTES_2D = {"mixed": 312, "fp64": 560}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "double_mach_1920x480_face_traffic.md")
@@ -65,10 +69,24 @@ def measured_traffic():
     return rec
 
 
-def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True, tiles=None, mlp=None):
+def cell_update_hbm(st, kt, steps, precision):
+    fused = kt["tail"] > 0.01  # the tail launch (else only event overhead sits there)
+    ms = kt["cell"] + (kt["tail"] if fused else 0.0)
+    alg = CELL_BYTES_2D[precision] * st["cell_updates"] / steps
+    gbps = alg / (ms * 1e-3) / 1e9 if ms > 0 else None
+    return {"bound": "hbm", "kernels": "tail_cell_kernel_2d + cell_marked_kernel_2d"
+            if fused else "cell_kernel<2>", "ms": ms, "algorithmic_bytes": alg,
+            "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
+            "frac": gbps / PEAK_HBM_GBPS if gbps else None}
+
+
+def run_form(cfg, fields, precision, warmup, steps, seed="prev", autotune=True, tiles=None, mlp=None,
+             iter_split=None):
     from paper_2203_05477_amd import pond
 
     ctx = pond.Context(cfg, fields, precision=precision, seed=seed)
+    if iter_split is not None:
+        ctx.set_iter_split(iter_split)
     if mlp is not None:
         ctx.load_mlp(mlp, hard_iters=2)
     if warmup:
@@ -208,6 +226,9 @@ def main():
     ap.add_argument("--workload", default="double_mach",
                     choices=["double_mach", "shocked_interface", "jet", "tubes"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
+    ap.add_argument("--iter-split", type=int, default=None,
+                    help="face iterations per face in the face kernel before the tail kernel takes "
+                         "over (0: no tail kernel, the cell update is one kernel)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="only run a plain 1 GiB device-to-device copy 5 times (the known-size "
                          "kernel that scales the HBM byte counters)")
@@ -246,7 +267,8 @@ def main():
 
     tiles = tuple(int(v) for v in args.tiles.split("x")) if args.tiles else None
     ctx32, st32, el32, kt32 = run_form(cfg32, fields, "mixed", args.warmup, args.steps,
-                                       autotune=not args.no_autotune, tiles=tiles)
+                                       autotune=not args.no_autotune, tiles=tiles,
+                                       iter_split=args.iter_split)
     # learned seed + FP32: a network trained on the GPU on face frames the solver itself
     # produced (first 300 steps of the same problem on a 4x coarser grid), then the same
     # timed run with the network seeding the faces that needed two or more iterations
@@ -277,7 +299,8 @@ def main():
     rec = {}
     if not args.no_fp64:
         ctx64, st64, el64, kt64 = run_form(cfg64, fields, "fp64", args.warmup, args.steps,
-                                           autotune=not args.no_autotune, tiles=tiles)
+                                           autotune=not args.no_autotune, tiles=tiles,
+                                           iter_split=args.iter_split)
         U32, U64 = ctx32.conserved(), ctx64.conserved()
         l1 = [float(np.abs(U32[k] - U64[k]).sum() / np.abs(U64[k]).sum()) for k in range(4)]
         if learned is not None:
@@ -289,6 +312,7 @@ def main():
             "mean_iters": st64["iters_total"] / max(st64["faces"], 1),
             "kernel_ms": {"dt": kt64["dt"], "face": kt64["face"], "tail_with_cells": kt64["tail"],
                           "cell": kt64["cell"]},
+            "cell_update_hbm": cell_update_hbm(st64, kt64, args.steps, "fp64"),
             "tiles": list(ctx64.tiles()),
         }
         rec["mixed_rel_l1_vs_fp64"] = {"rho": l1[0], "rho_u": l1[1], "rho_v": l1[2], "rho_E": l1[3]}
@@ -337,6 +361,11 @@ def main():
         "kernel_ms": {"dt": kt32["dt"], "face": face_main_ms, "tail_with_cells": kt32["tail"],
                       "cell": kt32["cell"]},
         "tail_faces_per_step": st32["tail_faces"] / args.steps,
+        # the cell update (reframe + flux + collision) against HBM: algorithmic bytes of the
+        # cells updated per step over the launches that update them; with a tail kernel the
+        # first of those launches also finishes the tail's faces (run --iter-split 0 for the
+        # cell update kernel alone)
+        "cell_update_hbm": cell_update_hbm(st32, kt32, args.steps, "mixed"),
         "tiles": list(ctx32.tiles()),
         "t_end": st32["t_max"],
     }
