@@ -1,0 +1,34 @@
+"""bench.py's command line on a machine without a GPU: more than one GPU is refused with a
+message, and the HBM traffic figure is read from the committed counter summary only while
+the kernel sources still hash to the value recorded there."""
+import hashlib
+import json
+import os
+import re
+import subprocess
+import sys
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_more_than_one_gpu_is_refused():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120)
+    assert r.returncode == 2
+    assert "one GPU" in r.stderr or "single MI355X" in r.stderr
+
+
+def test_traffic_figure_follows_the_source_hash():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    txt = open(bench.TRAFFIC_PROFILE).read()
+    rec = json.loads(re.search(r"traffic-json: (\{.*\})", txt).group(1))
+    src = b"".join(open(os.path.join(ROOT, "paper_2203_05477_amd", "csrc", f), "rb").read()
+                   for f in ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip"))
+    same = hashlib.sha256(src).hexdigest() == rec["sources_sha256"]
+    got = bench.measured_traffic()
+    if same:
+        assert got is not None and got["bytes_per_launch"] == rec["bytes_per_launch"] > 0
+    else:
+        assert got is None
