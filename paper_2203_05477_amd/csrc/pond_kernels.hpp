@@ -141,6 +141,51 @@ PD void stat_max(unsigned long long *stats, int k, unsigned long long v)
     if (wave_leader() && v) atomicMax(&stats[k * NSLOT + wave_slot()], v);
 }
 
+// 32-bit forms, for counters whose wave total fits 32 bits
+PD void stat_add32(unsigned long long *stats, int k, unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    if (wave_leader() && v) atomicAdd(&stats[k * NSLOT + wave_slot()], (unsigned long long)v);
+}
+
+PD void stat_max32(unsigned long long *stats, int k, unsigned v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    if (wave_leader() && v) atomicMax(&stats[k * NSLOT + wave_slot()], (unsigned long long)v);
+}
+
+// up to four small counters (k < 0: unused) in one wave reduction: 16-bit fields of one
+// 64-bit sum, which cannot carry into each other while every lane's value is below 1024;
+// otherwise (never in practice) one reduction per counter
+PD void stat_add4(unsigned long long *stats, int k0, unsigned a0, int k1, unsigned a1, int k2,
+                  unsigned a2, int k3, unsigned a3)
+{
+    if (__any(a0 >= 1024u || a1 >= 1024u || a2 >= 1024u || a3 >= 1024u)) {
+        if (k0 >= 0) stat_add(stats, k0, a0);
+        if (k1 >= 0) stat_add(stats, k1, a1);
+        if (k2 >= 0) stat_add(stats, k2, a2);
+        if (k3 >= 0) stat_add(stats, k3, a3);
+        return;
+    }
+    unsigned long long v = (unsigned long long)a0 | ((unsigned long long)a1 << 16) |
+                           ((unsigned long long)a2 << 32) | ((unsigned long long)a3 << 48);
+    v = wave_sum(v);
+    if (wave_leader() && v) {
+        const unsigned sl = wave_slot();
+        const int ks[4] = {k0, k1, k2, k3};
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const unsigned long long x = (v >> (16 * q)) & 0xffffull;
+            if (ks[q] >= 0 && x) atomicAdd(&stats[ks[q] * NSLOT + sl], x);
+        }
+    }
+}
+
 // rho, u, T from conserved variables (ideal gas, R = 1): rho E = C_v rho T + rho |u|^2 / 2
 template <int D>
 PD void prim(const double *U, int64_t n, int64_t c, double &rho, double u[2], double &T, double Cv)
@@ -1060,12 +1105,10 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
             nfc = 1;
         }
     }
-    stat_add(S.stats, ST_FACES, nfc);
-    stat_add(S.stats, ST_ITERS, cnt.iters);
-    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
-    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
-    stat_add(S.stats, ST_DEPOUT, cnt.depout);
-    stat_max(S.stats, ST_ITMAX, cnt.itmax);
+    stat_add4(S.stats, ST_FACES, (unsigned)nfc, ST_NONCONV, (unsigned)cnt.nonconv, ST_FALLBACK,
+              (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
+    stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+    stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
@@ -1106,12 +1149,10 @@ __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
         face_2d<R, 1, LIM>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
         ++nfaces;
     }
-    stat_add(S.stats, ST_FACES, nfaces);
-    stat_add(S.stats, ST_ITERS, cnt.iters);
-    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
-    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
-    stat_add(S.stats, ST_DEPOUT, cnt.depout);
-    stat_max(S.stats, ST_ITMAX, cnt.itmax);
+    stat_add4(S.stats, ST_FACES, (unsigned)nfaces, ST_NONCONV, (unsigned)cnt.nonconv, ST_FALLBACK,
+              (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
+    stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+    stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
@@ -1474,13 +1515,11 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int ax
         else
             tail_face<R, 1, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
     }
-    stat_add(S.stats, ST_ITERS, cnt.iters);
-    stat_add(S.stats, ST_NONCONV, cnt.nonconv);
-    stat_add(S.stats, ST_FALLBACK, cnt.fallback);
-    stat_add(S.stats, ST_DEPOUT, cnt.depout);
-    stat_max(S.stats, ST_ITMAX, cnt.itmax);
-    stat_add(S.stats, ST_TAIL_FACES, cnt.tail_faces);
-    stat_add(S.stats, ST_TAIL_ITERS, cnt.tail_iters);
+    stat_add4(S.stats, ST_TAIL_FACES, (unsigned)cnt.tail_faces, ST_NONCONV, (unsigned)cnt.nonconv,
+              ST_FALLBACK, (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
+    stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+    stat_add32(S.stats, ST_TAIL_ITERS, (unsigned)cnt.tail_iters);
+    stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
@@ -1581,8 +1620,8 @@ PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int
     bool all_conv = false;
     if (work) cell_update<D, R>(P, S, c, k, dt, slot, bits, all_conv);
     vmax_update<R>(P, S, slot ^ 1, k, work, bits);
-    stat_add(S.stats, ST_CELLS, work ? 1 : 0);
-    stat_add(S.stats, ST_CONV_CELLS, (work && all_conv) ? 1 : 0);
+    stat_add4(S.stats, ST_CELLS, work ? 1u : 0u, ST_CONV_CELLS, (work && all_conv) ? 1u : 0u, -1, 0u,
+              -1, 0u);
 }
 
 template <int D, typename R>
