@@ -511,8 +511,10 @@ PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx,
         R v = s * node<R>(i) + u;
         bool up = v >= R(0);
         R B = up ? PR[i] - PL[i] : T[i] - PR[i];
-        R sl = limit(A[i], B, lim);
-        R off = (up ? R(0.5) : R(-0.5)) - v * hdx;
+        // slope from limit_part, offset scaled by limit_scale (bitwise the same product)
+        const R sc = R(limit_scale(lim));
+        R sl = limit_part(A[i], B, lim);
+        R off = (up ? R(0.5) * sc : R(-0.5) * sc) - v * (hdx * sc);
         out[i] = (up ? PL[i] : PR[i]) + off * sl;
     }
 }
@@ -603,7 +605,7 @@ PD void face_write(const Params &P, const State<R> &S, int64_t f, R *mf, R *mg, 
     if (D == 1) {
         R h[4], hg[4];
         if (has_frame) {
-            R inv = R(1) / sf;
+            R inv = frcp(sf);
             shift_1d(mf, sl * inv, (ul[0] - uf[0]) * inv, 4);
             shift_1d(mg, sl * inv, (ul[0] - uf[0]) * inv, 3);
         }
@@ -795,16 +797,25 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
     bool conv = false, failed = false;
     while (it < P.max_iter) {
         ++it;
-        R s = sqrt(T), inv_s = R(1) / s;
+        R s, inv_s;
+        frame_scale(T, s, inv_s);
         R qf[4], qg[4];
         recon_1d<R, false>(L, NT, idx, u[0], s, inv_s, hdx, LIM, qf);
         recon_1d<R, true>(L, NT, idx, u[0], s, inv_s, hdx, LIM, qg);
         moments_1d(qf, mf, 4);
         moments_1d(qg, mg, 3);
         R rho = mf[0];
-        R du = s * mf[1] / rho;
-        R rhoe = R(0.5) * s * s * (mf[2] - mf[1] * mf[1] / rho) + mg[0];
-        R Tn = rhoe / ((R)P.Cv * rho);
+        // FP32: hardware reciprocal estimates; FP64: correctly rounded divisions
+        R irho = R(0), du, rhoe;
+        if constexpr (sizeof(R) == 4) {
+            irho = frcp(rho);
+            du = s * mf[1] * irho;
+            rhoe = R(0.5) * s * s * (mf[2] - mf[1] * mf[1] * irho) + mg[0];
+        } else {
+            du = s * mf[1] / rho;
+            rhoe = R(0.5) * s * s * (mf[2] - mf[1] * mf[1] / rho) + mg[0];
+        }
+        R Tn = temperature(rhoe, rho, irho, P.Cv);
         if (!(rho > R(0)) || !(Tn > R(0)) || !isfinite(Tn) || !isfinite(du)) {
             if (!restarted) {
                 restarted = true;
@@ -817,8 +828,15 @@ PD void face_1d(const Params &P, const State<R> &S, const R *L, int NT, const in
             break;
         }
         R un = u[0] + du;
-        R delta = fmax(fabs(du) / sqrt(Tn), fabs(Tn - T) / Tn);
-        R delta2 = fmax(fabs(un - upp) / sqrt(Tn), fabs(Tn - Tpp) / Tn);
+        R delta, delta2;
+        if constexpr (sizeof(R) == 4) {
+            const R isq = frsq(Tn), iTn = isq * isq;
+            delta = fmax(fabs(du) * isq, rel(Tn, T, Tn, iTn));
+            delta2 = fmax(fabs(un - upp) * isq, rel(Tn, Tpp, Tn, iTn));
+        } else {
+            delta = fmax(fabs(du) / sqrt(Tn), fabs(Tn - T) / Tn);
+            delta2 = fmax(fabs(un - upp) / sqrt(Tn), fabs(Tn - Tpp) / Tn);
+        }
         upp = u[0];
         Tpp = T;
         ul[0] = u[0];
