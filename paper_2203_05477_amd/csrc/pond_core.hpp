@@ -267,6 +267,141 @@ PD void eval_cols_2d(const R h[10], int cols, R p[16], int order)
     }
 }
 
+// ---------------------------------------------------------------------------------
+// 2D coefficients in scaled form q: the Hermite coefficients h_ab times a! b! (q20 = 2 h20,
+// q30 = 6 h30, q21 = 2 h21, ...), which turns the conversions to and from raw moments
+// into plain additions; the population evaluation takes the factorials into its constants.
+// Index order as for h: 00 10 01 20 11 02 30 21 12 03.
+// ---------------------------------------------------------------------------------
+
+template <typename R>
+PD void q2mu_2d(const R q[10], R mu[10], int n)
+{
+    mu[0] = q[0];
+    mu[1] = q[1];
+    mu[2] = q[2];
+    mu[3] = q[0] + q[3];
+    mu[4] = q[4];
+    mu[5] = q[0] + q[5];
+    if (n > 6) {
+        mu[6] = fma(R(3), q[1], q[6]);
+        mu[7] = q[2] + q[7];
+        mu[8] = q[1] + q[8];
+        mu[9] = fma(R(3), q[2], q[9]);
+    }
+}
+
+template <typename R>
+PD void mu2q_2d(const R mu[10], R q[10], int n)
+{
+    q[0] = mu[0];
+    q[1] = mu[1];
+    q[2] = mu[2];
+    q[3] = mu[3] - mu[0];
+    q[4] = mu[4];
+    q[5] = mu[5] - mu[0];
+    if (n > 6) {
+        q[6] = fma(R(-3), mu[1], mu[6]);
+        q[7] = mu[7] - mu[2];
+        q[8] = mu[8] - mu[1];
+        q[9] = fma(R(-3), mu[2], mu[9]);
+    }
+}
+
+// He_2 / 2 and He_3 / 6 at the two node magnitudes
+template <typename R>
+struct LatQ {
+    static constexpr R e2a = R(0.5 * Lat<double>::he2a), e2b = R(0.5 * Lat<double>::he2b);
+    static constexpr R e3a = R(Lat<double>::he3a / 6.0), e3b = R(Lat<double>::he3b / 6.0);
+};
+
+// reduced populations p_i = f_i / W_i from scaled coefficients (sum factorization over y
+// then x, as eval_2d)
+template <typename R>
+PD void eval_q_2d(const R q[10], R p[16], int order)
+{
+    const bool o3 = order > 2;
+    R q30 = o3 ? q[6] : R(0), q21 = o3 ? q[7] : R(0), q12 = o3 ? q[8] : R(0), q03 = o3 ? q[9] : R(0);
+    R B0[4], B1[4], B2[4], B3[4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const R c = m ? Lat<R>::cb : Lat<R>::ca;
+        const R e2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+        const R e3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+        const int ip = m ? 3 : 2, im = m ? 0 : 1;
+        R E = fma(q[5], e2, q[0]), O = fma(q03, e3, q[2] * c);
+        B0[ip] = E + O;
+        B0[im] = E - O;
+        E = fma(q12, e2, q[1]);
+        O = q[4] * c;
+        B1[ip] = E + O;
+        B1[im] = E - O;
+        E = q[3];
+        O = q21 * c;
+        B2[ip] = E + O;
+        B2[im] = E - O;
+        B3[ip] = q30;
+        B3[im] = q30;
+    }
+#pragma unroll
+    for (int iy = 0; iy < 4; ++iy) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const R c = m ? Lat<R>::cb : Lat<R>::ca;
+            const R e2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+            const R e3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+            const int ip = m ? 3 : 2, im = m ? 0 : 1;
+            R E = fma(B2[iy], e2, B0[iy]), O = fma(B3[iy], e3, B1[iy] * c);
+            p[ip + 4 * iy] = E + O;
+            p[im + 4 * iy] = E - O;
+        }
+    }
+}
+
+// the populations of the node columns in `cols` only, from scaled coefficients (as
+// eval_cols_2d; explicit fma throughout, so a column's value does not depend on which
+// other columns are evaluated)
+template <typename R, int AXIS>
+PD void eval_q_cols_2d(const R q[10], int cols, R p[16], int order)
+{
+    const bool o3 = order > 2;
+    // G[n][t] = q of normal degree n, tangential degree t
+    R g00 = q[0], g10, g01, g20, g11, g02, g30, g21, g12, g03;
+    if (AXIS == 0) {
+        g10 = q[1]; g01 = q[2]; g20 = q[3]; g11 = q[4]; g02 = q[5];
+        g30 = o3 ? q[6] : R(0); g21 = o3 ? q[7] : R(0); g12 = o3 ? q[8] : R(0); g03 = o3 ? q[9] : R(0);
+    } else {
+        g10 = q[2]; g01 = q[1]; g20 = q[5]; g11 = q[4]; g02 = q[3];
+        g30 = o3 ? q[9] : R(0); g21 = o3 ? q[8] : R(0); g12 = o3 ? q[7] : R(0); g03 = o3 ? q[6] : R(0);
+    }
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        R out[4] = {R(0), R(0), R(0), R(0)};
+        if (cols & (1 << n)) {
+            const R cn = node<R>(n);
+            const R e2 = (n == 1 || n == 2) ? LatQ<R>::e2a : LatQ<R>::e2b;
+            const R e3n = (n == 1 || n == 2) ? LatQ<R>::e3a : LatQ<R>::e3b;
+            const R e3 = (n < 2) ? -e3n : e3n; // He3 is odd
+            // A_t (times t!) = sum_n' G[n'][t] He_n'(c_n) / n'!
+            const R A0 = fma(e3, g30, fma(e2, g20, fma(cn, g10, g00)));
+            const R A1 = fma(e2, g21, fma(cn, g11, g01));
+            const R A2 = fma(cn, g12, g02);
+            const R A3 = g03;
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const R ct = m ? Lat<R>::cb : Lat<R>::ca;
+                const R t2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+                const R t3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+                const R E = fma(A2, t2, A0), O = fma(A3, t3, A1 * ct);
+                out[m ? 3 : 2] = E + O;
+                out[m ? 0 : 1] = E - O;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[AXIS ? (t + 4 * n) : (n + 4 * t)] = out[t];
+    }
+}
+
 // raw moments mu = sum_i W_i p_i c^k (1D), up to degree n-1
 template <typename R>
 PD void moments_1d(const R p[4], R mu[4], int n)

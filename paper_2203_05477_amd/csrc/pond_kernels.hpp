@@ -403,9 +403,11 @@ PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double
         out[1 * NT] = (R)u[1];
         out[2 * NT] = (R)sqrt(T);
         out[3 * NT] = (R)rho;
-        for (int k = 0; k < 7; ++k) out[(4 + k) * NT] = (R)(Ap * fh[k]);
+        // coefficients in the scaled form of q2mu_2d (times a! b!)
+        constexpr double fq[7] = {2.0, 1.0, 2.0, 6.0, 2.0, 2.0, 6.0}, gq[5] = {1.0, 1.0, 2.0, 1.0, 2.0};
+        for (int k = 0; k < 7; ++k) out[(4 + k) * NT] = (R)(Ap * fq[k] * fh[k]);
         out[11 * NT] = (R)(Ap * b0 + Bp * geq);
-        for (int k = 0; k < 5; ++k) out[(12 + k) * NT] = (R)(Ap * gh[k]);
+        for (int k = 0; k < 5; ++k) out[(12 + k) * NT] = (R)(Ap * gq[k] * gh[k]);
         out[17 * NT] = (R)T;
     }
     (void)slot;
@@ -439,28 +441,30 @@ PD void cell_pops_1d(const R *L, int NT, int c, R u, R inv_s, R p[4])
     eval_1d(h, p, G ? 2 : 3);
 }
 
+// The 2D records hold the coefficients in the scaled form q (see q2mu_2d); the transform
+// into the face frame and the evaluation work on that form.
 template <typename R, bool G>
 PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
 {
     R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
-    R h[10], mu[10];
+    R q[10], mu[10];
     if (!G) {
-        h[0] = L[3 * NT + c];
-        h[1] = R(0);
-        h[2] = R(0);
+        q[0] = L[3 * NT + c];
+        q[1] = R(0);
+        q[2] = R(0);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
-        h2mu_2d(h, mu, 10);
+        for (int k = 0; k < 7; ++k) q[3 + k] = L[(4 + k) * NT + c];
+        q2mu_2d(q, mu, 10);
         shift_2d(mu, r, dx, dy, 10);
-        mu2h_2d(mu, h, 10);
-        eval_2d(h, p, 3);
+        mu2q_2d(mu, q, 10);
+        eval_q_2d(q, p, 3);
     } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
-        h2mu_2d(h, mu, 6);
+        for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
+        q2mu_2d(q, mu, 6);
         shift_2d(mu, r, dx, dy, 6);
-        mu2h_2d(mu, h, 6);
-        eval_2d(h, p, 2);
+        mu2q_2d(mu, q, 6);
+        eval_q_2d(q, p, 2);
     }
 }
 
@@ -469,24 +473,24 @@ template <typename R, bool G, int AXIS>
 PD void cell_cols_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int cols, R p[16])
 {
     R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
-    R h[10], mu[10];
+    R q[10], mu[10];
     if (!G) {
-        h[0] = L[3 * NT + c];
-        h[1] = R(0);
-        h[2] = R(0);
+        q[0] = L[3 * NT + c];
+        q[1] = R(0);
+        q[2] = R(0);
 #pragma unroll
-        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
-        h2mu_2d(h, mu, 10);
+        for (int k = 0; k < 7; ++k) q[3 + k] = L[(4 + k) * NT + c];
+        q2mu_2d(q, mu, 10);
         shift_2d(mu, r, dx, dy, 10);
-        mu2h_2d(mu, h, 10);
-        eval_cols_2d<R, AXIS>(h, cols, p, 3);
+        mu2q_2d(mu, q, 10);
+        eval_q_cols_2d<R, AXIS>(q, cols, p, 3);
     } else {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
-        h2mu_2d(h, mu, 6);
+        for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
+        q2mu_2d(q, mu, 6);
         shift_2d(mu, r, dx, dy, 6);
-        mu2h_2d(mu, h, 6);
-        eval_cols_2d<R, AXIS>(h, cols, p, 2);
+        mu2q_2d(mu, q, 6);
+        eval_q_cols_2d<R, AXIS>(q, cols, p, 2);
     }
 }
 
@@ -710,16 +714,16 @@ template <typename R, bool G, int AXIS>
 PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_sm, R mu[10])
 {
     R ux = L[c], uy = L[NT + c], s = L[2 * NT + c];
-    R h[10], p[16];
+    R q[10], p[16]; // scaled coefficients of the record (see q2mu_2d)
     if (!G) {
-        h[0] = L[3 * NT + c];
-        h[1] = R(0);
-        h[2] = R(0);
-        for (int k = 0; k < 7; ++k) h[3 + k] = L[(4 + k) * NT + c];
-        eval_2d(h, p, 3);
+        q[0] = L[3 * NT + c];
+        q[1] = R(0);
+        q[2] = R(0);
+        for (int k = 0; k < 7; ++k) q[3 + k] = L[(4 + k) * NT + c];
+        eval_q_2d(q, p, 3);
     } else {
-        for (int k = 0; k < 6; ++k) h[k] = L[(11 + k) * NT + c];
-        eval_2d(h, p, 2);
+        for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
+        eval_q_2d(q, p, 2);
     }
     const R un = AXIS ? uy : ux;
     for (int i = 0; i < 16; ++i) {
@@ -1274,9 +1278,17 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
     const int ix = q & 3, iy = q >> 2;
     const R cx = node<R>(ix), cy = node<R>(iy);
     const R cx2 = cx * cx, cy2 = cy * cy;
-    const R bas[10] = {R(1),          cx,         cy,           cx2 - R(1),   cx * cy,
-                       cy2 - R(1),    cx * (cx2 - R(3)), (cx2 - R(1)) * cy, cx * (cy2 - R(1)),
-                       cy * (cy2 - R(3))};
+    // Hermite basis at the lane's node divided by a! b!, to pair with scaled coefficients
+    const R bas[10] = {R(1),
+                       cx,
+                       cy,
+                       R(0.5) * (cx2 - R(1)),
+                       cx * cy,
+                       R(0.5) * (cy2 - R(1)),
+                       cx * (cx2 - R(3)) * R(1.0 / 6.0),
+                       R(0.5) * (cx2 - R(1)) * cy,
+                       R(0.5) * cx * (cy2 - R(1)),
+                       cy * (cy2 - R(3)) * R(1.0 / 6.0)};
     const R wgt = weight1<R>(ix) * weight1<R>(iy);
     const R cn = node<R>(AXIS ? iy : ix), ct = node<R>(AXIS ? ix : iy);
     // stencil cell transformed by this lane
@@ -1306,9 +1318,9 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
 #pragma unroll
                 for (int k = 6; k < 10; ++k) h[k] = R(0);
             }
-            h2mu_2d(h, mu, 10);
+            q2mu_2d(h, mu, 10); // the records hold scaled coefficients
             shift_2d(mu, r, dx, dy, 10);
-            mu2h_2d(mu, h, 10);
+            mu2q_2d(mu, h, 10);
             R *dst = coef + tc * TAIL_CSTRIDE + (tg ? 10 : 0);
             const int nw = tg ? 6 : 10;
 #pragma unroll
