@@ -159,10 +159,35 @@ bool ensure_tail(pond_ctx *c, int bx, int by)
     return true;
 }
 
+// plane stride of the 2D face kernel's LDS tile: 256 or 512 (compiled in), else the tile's
+// own size
+int face_nts(int bx, int by)
+{
+    const int n = (bx + 3) * (by + 3);
+    return n <= 256 ? 256 : (n <= 512 ? 512 : 0);
+}
+
 size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
 {
     if (c->D == 1) return (size_t)(bx + 3 + 3 * span) * Layout<1>::NL * c->rsize;
-    return (size_t)(bx + 3) * (by + 3) * Layout<2>::NL * c->rsize;
+    const int nts = face_nts(bx, by);
+    return (size_t)(nts ? nts : (bx + 3) * (by + 3)) * Layout<2>::NL * c->rsize;
+}
+
+template <typename R, int LIM>
+void launch_face_2d(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
+{
+    dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
+    switch (face_nts(bx, by)) {
+    case 256:
+        face_kernel_2d<R, LIM, 256><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        break;
+    case 512:
+        face_kernel_2d<R, LIM, 512><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        break;
+    default:
+        face_kernel_2d<R, LIM, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+    }
 }
 
 int compute_span(const pond_ctx *c, int B)
@@ -196,12 +221,11 @@ hipError_t launch_face(pond_ctx *c, int bx, int by, bool with_tail)
         else
             face_kernel_1d<R, 0><<<blocks(c->P.nface, bx), bx, lds, c->stream>>>(c->P, S, span);
     } else {
-        dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
         size_t lds = face_lds_bytes(c, bx, by, 0);
         if (c->P.limiter == POND_LIM_MINMOD)
-            face_kernel_2d<R, 1><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+            launch_face_2d<R, 1>(c, S, bx, by, lds);
         else
-            face_kernel_2d<R, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+            launch_face_2d<R, 0>(c, S, bx, by, lds);
         if (with_tail && c->P.iter_split > 0) {
             // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
             dim3 tgrid(NSLOT * 4, 2);

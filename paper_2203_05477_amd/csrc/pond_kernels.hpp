@@ -1136,20 +1136,22 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
 
 // 2D: thread (i, j) owns x-face (i, j) (if j < ny) and y-face (i, j) (if i < nx).
 // LDS tile: cells i0-2 .. i0+BX, j0-2 .. j0+BY.
-template <typename R, int LIM>
+// NTS: plane stride of the LDS tile (at least (BX+3)(BY+3)), a compile-time constant so
+// that the record loads take their plane offsets as immediates; 0: the tile's own size
+template <typename R, int LIM, int NTS>
 __global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
 {
     extern __shared__ unsigned char smem_raw[];
     R *L = reinterpret_cast<R *>(smem_raw);
     const int BX = blockDim.x, BY = blockDim.y;
     const int TX = BX + 3, TY = BY + 3;
-    const int NT = TX * TY;
+    const int NT = NTS ? NTS : TX * TY;
     const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
     const double t = S.tstart[0];
     const int tid = threadIdx.x + BX * threadIdx.y;
-    for (int e = tid; e < NT; e += BX * BY) {
+    for (int e = tid; e < TX * TY; e += BX * BY) {
         int ci = i0 - 2 + e % TX, cj = j0 - 2 + e / TX;
         // faces reference cells in [-2, nx+1] x [-2, ny+1] only
         if (ci > P.nx + 1 || cj > P.ny + 1) continue;
