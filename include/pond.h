@@ -168,7 +168,9 @@ pond_status pond_time(const pond_ctx *ctx, double *t);
  * be replaced before it is destroyed. */
 pond_status pond_set_stream(pond_ctx *ctx, void *hip_stream);
 
-/* Launch shapes. 1D: face_block threads per block. 2D: face tile bx x by (threads).
+/* Launch shapes. 1D: face_block threads per block (64, 128, 192 or 256; by = 1). 2D: face
+ * tile bx x by threads, a multiple of 64 and at most 256. cell_block: threads per block of
+ * the cell update (64 to 256, a multiple of 64). Other shapes give POND_EINVAL.
  * Any shape gives bitwise-identical results. pond_autotune times the candidates on
  * the current state (which it leaves unchanged) and keeps the fastest. */
 pond_status pond_set_tiles(pond_ctx *ctx, int32_t bx, int32_t by, int32_t cell_block);

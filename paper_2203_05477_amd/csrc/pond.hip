@@ -947,11 +947,12 @@ pond_status pond_set_stream(pond_ctx *c, void *s)
 pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_block)
 {
     if (!c) return POND_EINVAL;
-    if (cell_block < 64 || cell_block > 1024 || cell_block % 64) return POND_EINVAL;
+    // every kernel is compiled for blocks of at most 256 threads
+    if (cell_block < 64 || cell_block > 256 || cell_block % 64) return POND_EINVAL;
     if (c->D == 1) {
-        if (bx < 64 || bx > 1024 || bx % 64 || by != 1) return POND_EINVAL;
+        if (bx < 64 || bx > 256 || bx % 64 || by != 1) return POND_EINVAL;
     } else {
-        if (bx < 1 || by < 1 || bx * by > 1024 || (bx * by) % 64) return POND_EINVAL;
+        if (bx < 1 || by < 1 || bx * by > 256 || (bx * by) % 64) return POND_EINVAL;
     }
     int span = compute_span(c, bx);
     if (face_lds_bytes(c, bx, by, span) > 160 * 1024) return POND_EINVAL;
@@ -1001,7 +1002,7 @@ pond_status pond_autotune(pond_ctx *c)
     // a dt must exist for the face kernel: run the dt kernel's effect on a copy
     std::vector<std::pair<int, int>> cand;
     if (c->D == 1)
-        cand = {{64, 1}, {128, 1}, {256, 1}, {512, 1}};
+        cand = {{64, 1}, {128, 1}, {256, 1}};
     else
         cand.assign(std::begin(kTiles2D), std::end(kTiles2D));
     double best = 1e30;

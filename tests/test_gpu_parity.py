@@ -254,3 +254,23 @@ def test_shocked_interface_small_fp64(orc):
     e = _relerr(g.conserved(), o.conserved())
     _print("shocked_interface", err=e.max())
     assert e.max() <= TOL64
+
+
+def test_launch_shapes_above_256_threads_are_rejected():
+    """Every kernel is compiled for at most 256 threads per block: larger shapes are
+    refused when they are set, not when a launch fails."""
+    from paper_2203_05477_amd import pond
+
+    cfg, f = W.double_mach(64, 16)
+    g = pond.Context(cfg, f, precision="fp64")
+    for bx, by, cb in ((32, 16, 256), (16, 8, 512), (8, 4, 256)):
+        with pytest.raises(pond.PondError):
+            g.set_tiles(bx, by, cb)
+    g.set_tiles(16, 16, 256)
+    g.step(2)
+    cfg, f = W.shock_tube(64)
+    h = pond.Context(cfg, f, precision="fp64")
+    with pytest.raises(pond.PondError):
+        h.set_tiles(512, 1, 256)
+    h.set_tiles(192, 1, 128)
+    h.step(2)
