@@ -1137,9 +1137,11 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
 // 2D: thread (i, j) owns x-face (i, j) (if j < ny) and y-face (i, j) (if i < nx).
 // LDS tile: cells i0-2 .. i0+BX, j0-2 .. j0+BY.
 // NTS: plane stride of the LDS tile (at least (BX+3)(BY+3)), a compile-time constant so
-// that the record loads take their plane offsets as immediates; 0: the tile's own size
+// that the record loads take their plane offsets as immediates; 0: the tile's own size.
+// The FP64 Van Leer kernel is held to 2 waves per SIMD: it then spills a few registers,
+// and still runs 17% faster than with 1 wave (the FP64 minmod kernel does not gain).
 template <typename R, int LIM, int NTS>
-__global__ __launch_bounds__(256) void face_kernel_2d(Params P, State<R> S)
+__global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void face_kernel_2d(Params P, State<R> S)
 {
     extern __shared__ unsigned char smem_raw[];
     R *L = reinterpret_cast<R *>(smem_raw);
