@@ -105,6 +105,17 @@ PD unsigned long long wave_sum(unsigned long long v)
     return v;
 }
 
+// Workgroups are dispatched to the 8 XCDs in turn by linear index (workgroup b runs on XCD
+// b mod 8). xcd_tile(b, n) is a permutation of [0, n) that gives XCD x the x-th contiguous
+// run of n/8 tiles (the first n mod 8 XCDs one more).
+constexpr int NXCD = 8;
+PD int xcd_tile(int b, int n)
+{
+    const int xcd = b % NXCD, local = b / NXCD;
+    const int base = n / NXCD, rem = n % NXCD;
+    return xcd < rem ? xcd * (base + 1) + local : rem * (base + 1) + (xcd - rem) * base + local;
+}
+
 // Counters and maxima are spread over NSLOT copies, one picked by the wave's global index:
 // atomics on one address serialize in its L2 channel (about 10 ns each), so one counter
 // hit once per wave would cost a kernel of 14,400 waves some 150 us. Readers combine the
@@ -1148,7 +1159,10 @@ __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void fac
     const int BX = blockDim.x, BY = blockDim.y;
     const int TX = BX + 3, TY = BY + 3;
     const int NT = NTS ? NTS : TX * TY;
-    const int i0 = blockIdx.x * BX, j0 = blockIdx.y * BY;
+    // the tile of this workgroup: each XCD (own L2) gets a contiguous run of tiles, so that
+    // neighbouring tiles, which read the same halo cells, share an L2
+    const int tile = xcd_tile((int)(blockIdx.x + gridDim.x * blockIdx.y), (int)(gridDim.x * gridDim.y));
+    const int i0 = (tile % (int)gridDim.x) * BX, j0 = (tile / (int)gridDim.x) * BY;
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
     const double t = S.tstart[0];
@@ -1661,7 +1675,10 @@ PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int
 template <int D, typename R>
 __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
 {
-    cell_step<D, R>(P, S, (int64_t)blockIdx.x * blockDim.x + threadIdx.x, true, slot);
+    // contiguous runs of blocks per XCD: the rows above and below, which share y-faces, in
+    // the same L2
+    const int64_t blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    cell_step<D, R>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
 }
 
 // The tail work (blocks [0, 2 * TAIL_BLOCKS): TAIL_BLOCKS per axis) beside the update of
@@ -1669,6 +1686,7 @@ __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slo
 // whose waves fill the issue slots that the tail's dependency chains leave idle. Neither
 // reads a cell that the other writes.
 constexpr int TAIL_BLOCKS = 4 * NSLOT;
+static_assert((2 * TAIL_BLOCKS) % NXCD == 0, "the cell blocks start on XCD 0");
 
 template <typename R, int LIM>
 __global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S, int slot)
@@ -1679,7 +1697,9 @@ __global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S,
                            TAIL_BLOCKS);
         return;
     }
-    const int64_t c = (int64_t)(blockIdx.x - 2 * TAIL_BLOCKS) * 256 + threadIdx.x;
+    // 2 * TAIL_BLOCKS is a multiple of the XCD count: cell block k runs on XCD k mod 8
+    const int64_t blk = xcd_tile((int)blockIdx.x - 2 * TAIL_BLOCKS, (int)gridDim.x - 2 * TAIL_BLOCKS);
+    const int64_t c = blk * 256 + threadIdx.x;
     cell_step<2, R>(P, S, c, c < P.ncell && !S.tblock[c], slot);
 }
 
