@@ -651,9 +651,16 @@ PD void face_write(const Params &P, const State<R> &S, int64_t f, R *mf, R *mg, 
         mu2h_2d(mf, h, 10);
         mu2h_2d(mg, hg, 6);
         R rho = h[0];
-        double eps = has_frame ? dt * (double)rho * (double)Tf / P.mu : 0.0;
-        R c = (R)(1.0 / (1.0 + 0.25 * eps));
-        R e4 = (R)(0.25 * eps);
+        R c, e4;
+        if constexpr (sizeof(R) == 4) {
+            const R eps = has_frame ? (R)(dt / P.mu) * rho * Tf : R(0);
+            e4 = R(0.25) * eps;
+            c = frcp(R(1) + e4);
+        } else {
+            double eps = has_frame ? dt * (double)rho * (double)Tf / P.mu : 0.0;
+            c = (R)(1.0 / (1.0 + 0.25 * eps));
+            e4 = (R)(0.25 * eps);
+        }
         S.F[0 * nf + f] = uf[0];
         S.F[1 * nf + f] = uf[1];
         S.F[2 * nf + f] = Tf;
@@ -666,31 +673,26 @@ PD void face_write(const Params &P, const State<R> &S, int64_t f, R *mf, R *mg, 
     }
 }
 
-// mean frame of two cells' conserved variables (seed of the first step, restart frame)
+// mean frame of two cells' conserved variables (seed of the first step, restart frame):
+// with S = rho_a + rho_b, u = (rho_a u_a + rho_b u_b) / S and, from the mean energy,
+// T = (rho_a T_a + rho_b T_b) / S + rho_a rho_b |u_a - u_b|^2 / (2 C_v S^2) -- the same value
+// as (E/rho - |u|^2/2)/C_v of the mean conserved variables, without its cancellation, so
+// it is evaluated in the record precision
 template <int D, typename R>
 PD void mean_frame(const R *L, int NT, int a, int b, const Params &P, R u[2], R &T)
 {
-    const int su = 0, ss = (D == 1) ? 1 : 2, sT = (D == 1) ? 2 : 17, sr = 3;
-    (void)ss;
-    double ra = L[sr * NT + a], rb = L[sr * NT + b];
-    double ua[2] = {(double)L[su * NT + a], D == 2 ? (double)L[NT + a] : 0.0};
-    double ub[2] = {(double)L[su * NT + b], D == 2 ? (double)L[NT + b] : 0.0};
-    double Ta = L[sT * NT + a], Tb = L[sT * NT + b];
-    double r = 0.5 * (ra + rb), e = 0.0, ke = 0.0, m[2];
-    double ka = 0.0, kb = 0.0;
+    const int sT = (D == 1) ? 2 : 17, sr = 3;
+    const R ra = L[sr * NT + a], rb = L[sr * NT + b];
+    const R Sm = ra + rb, iS = (sizeof(R) == 4) ? frcp(Sm) : R(1) / Sm;
+    const R wa = ra * iS, wb = rb * iS;
+    R du2 = R(0);
     for (int q = 0; q < D; ++q) {
-        m[q] = 0.5 * (ra * ua[q] + rb * ub[q]);
-        ka += ua[q] * ua[q];
-        kb += ub[q] * ub[q];
-    }
-    e = 0.5 * (P.Cv * ra * Ta + 0.5 * ra * ka) + 0.5 * (P.Cv * rb * Tb + 0.5 * rb * kb);
-    const double ir = 1.0 / r;
-    for (int q = 0; q < D; ++q) {
-        u[q] = (R)(m[q] * ir);
-        ke += (m[q] * ir) * (m[q] * ir);
+        const R ua = L[q * NT + a], ub = L[q * NT + b];
+        u[q] = wa * ua + wb * ub;
+        du2 += (ua - ub) * (ua - ub);
     }
     if (D == 1) u[1] = R(0);
-    T = (R)((e * ir - 0.5 * ke) / P.Cv);
+    T = wa * L[sT * NT + a] + wb * L[sT * NT + b] + wa * wb * du2 * (R)(0.5 / P.Cv);
 }
 
 // first-order upwind state from each neighbour's own frame (fallback), as raw moments
