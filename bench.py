@@ -30,10 +30,11 @@ METRIC = "converged Mcell-updates/s at fixed L1 err vs FP64 oracle; learned+FP32
 # face (finalization), as counted in the kernel's arithmetic (FMA = 2): transform of the 8
 # (2D) or 4 (1D) stencil cells into the face frame, population evaluation, limited MUSCL
 # reconstruction, moments and frame update. 2D, per iteration: 8 stencil cells x (frame
-# offsets 5 + f transform 61 + g transform 31); populations of L and R in full (f 86, g 56)
-# and of the 6 side cells in the 2 node columns each feeds (f 52, g 32); 32 limited
-# populations x 16 + 60 shared; moments of f (108) and g (80); frame update 40.
-FLOPS_FACE_ITER = {1: 330, 2: 2364}
+# offsets 5 + f transform 49 + g transform 27, on factorial-scaled coefficients); populations
+# of L and R in full (f 86, g 56) and of the 6 side cells in the 2 node columns each feeds
+# (f 52, g 32); 32 limited populations x 16 + 60 shared; moments of f (108) and g (80);
+# frame update 40.
+FLOPS_FACE_ITER = {1: 330, 2: 2236}
 FLOPS_FACE_FINAL = {1: 60, 2: 330}
 # FP64 / FP32 vector peaks of MI355X (no packed FP32 instructions are used: FP32 issues at
 # the FP64 rate, so both peaks are the 78.6 TFLOP/s non-packed figure)
