@@ -211,6 +211,96 @@ def other_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def riemann_workload(args):
+    """The printed 1D Riemann problems (Lax, strong shock tube, double rarefaction, Le Blanc,
+    1D jet) at the paper's resolutions, each run from t = 0 to its printed final time in
+    the mixed and FP64 forms, with the relative L1 error of every conserved field against
+    the exact Riemann solution. A first, untimed run counts the steps to the final time;
+    the timed run then issues them in one pond_step call on a fresh context (launches
+    replayed from a captured graph, which gives the same results). A case that fails
+    (the double rarefaction opens a true vacuum) is reported with the step it failed in
+    and left out of the totals. These grids hold 600-4,000 cells, so a step is bound by
+    kernel launch latency, not by the GPU's throughput."""
+    import oracle
+    import torch
+
+    sys.path.insert(0, os.path.join(ROOT, "tests"))
+    import exact_riemann as ER
+    from paper_2203_05477_amd import pond
+    from paper_2203_05477_amd import workloads as W
+
+    pond.load()
+    cases, tot = {}, {"mixed": [0, 0.0], "fp64": [0, 0.0]}
+    for name, case in W.RIEMANN_CASES.items():
+        left, right, xi, (a, b), gamma, t_end, nx = case[:7]
+        cases[name] = {"cells": nx, "t_end": t_end}
+        for prec, tol in (("mixed", W.TOL_FP32), ("fp64", W.TOL_FP64)):
+            cfg, fields = W.riemann_case(name, tol=tol)
+            ctx = pond.Context(cfg, fields, precision=prec)
+            n, status = 0, pond.OK
+            while ctx.time()[0] < t_end * (1 - 1e-12) and status == pond.OK:
+                status = ctx.step(1, t_end, check=False)["status"]
+                n += 1
+            ctx.close()
+            r = {"steps": n, "status": status}
+            if status != pond.OK:
+                r["failed_at_step"] = n
+                cases[name][prec] = r
+                continue
+            ctx = pond.Context(cfg, fields, precision=prec)
+            ctx.autotune()
+            ctx.set_graph(True)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = ctx.step(n, t_end, check=False)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            ex = ER.cell_average(left, right, gamma, np.linspace(a, b, nx + 1), xi, ctx.time()[0])
+            U = ctx.conserved()
+            r.update({"status": st["status"], "ms": 1e3 * el, "ms_per_step": 1e3 * el / n,
+                      "converged_cell_updates": st["converged_cell_updates"],
+                      "fallback_faces": st["fallback"],
+                      "rel_l1_vs_exact": {k: float(np.abs(U[q] - ex[q]).sum() / np.abs(ex[q]).sum())
+                                          for q, k in enumerate(("rho", "rho_u", "rho_E"))}})
+            ctx.close()
+            cases[name][prec] = r
+            tot[prec][0] += st["converged_cell_updates"]
+            tot[prec][1] += el
+    cpu = None
+    if not args.no_cpu_baseline:
+        # the oracle on the first 500 steps of each case (all of them would take minutes:
+        # Le Blanc alone needs about 19,500 steps of 4,000 cells)
+        cells, el = 0, 0.0
+        for name in W.RIEMANN_CASES:
+            cfg, fields = W.riemann_case(name, tol=W.TOL_FP64)
+            sim = oracle.Sim(cfg, fields["rho"], fields["ux"], None, fields["p"])
+            t0 = time.perf_counter()
+            k = 0
+            while k < 500 and sim.t < cfg["t_end"] * (1 - 1e-12):
+                sim.step(cfg["t_end"])
+                k += 1
+            el += time.perf_counter() - t0
+            cells += k * cfg["nx"]
+        cpu = {"value": cells / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+               "kind": "oracle",
+               "sample": f"first 500 steps of each of the five cases from t=0 (FP64); {el:.1f} s"}
+    m = tot["mixed"]
+    line = {
+        "metric": METRIC, "value": m[0] / m[1] / 1e6, "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": sum(c["mixed"]["steps"] for c in cases.values() if "ms" in c["mixed"]),
+        "warmup": 0, "ms_per_step": 1e3 * m[1] / max(1, sum(c["mixed"]["steps"] for c in cases.values()
+                                                           if "ms" in c["mixed"])),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "riemann_1d_printed_problems", "lattice": "D1Q4",
+                   "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain",
+                   "cfl": 0.2},
+        "roofline": None, "fp64_plain": {"value": tot["fp64"][0] / tot["fp64"][1] / 1e6},
+        "cases": cases, "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -225,7 +315,7 @@ def main():
     ap.add_argument("--tiles", type=str, default=None,
                     help="face tile BXxBY for both forms instead of the autotuner's choice")
     ap.add_argument("--workload", default="double_mach",
-                    choices=["double_mach", "shocked_interface", "jet", "tubes"],
+                    choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
     ap.add_argument("--iter-split", type=int, default=None,
                     help="face iterations per face in the face kernel before the tail kernel takes "
@@ -253,6 +343,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
+        return
+    if args.workload == "riemann_1d":
+        riemann_workload(args)
         return
     if args.workload != "double_mach":
         other_workload(args)
