@@ -183,6 +183,17 @@ pond_status pond_autotune(pond_ctx *ctx);
  * and the last step of an odd count, are launched one by one. Default off. */
 pond_status pond_set_graph(pond_ctx *ctx, int32_t on);
 
+/* 1D only: on != 0 runs all the steps of each pond_step call in a single launch, one
+ * 1,024-thread (mixed) or 512-thread (FP64) block per tube, longest tubes first; each
+ * block advances its tube step by step (the step of Sec. III.B.4 with the tube's own dt),
+ * so no step pays kernel launch latency. Results, counters and failure handling are
+ * identical to the launched kernels (same arithmetic per face and per cell). For small
+ * grids and batches of independent tubes. Not used with timing enabled or the learned
+ * seed (the launched kernels run then). Allocates a tube-order array of n_inst ints on the
+ * first call with on != 0. POND_EINVAL for a 2D context; POND_ENOMEM / POND_EDEVICE if
+ * the order array cannot be set up. Default off. */
+pond_status pond_set_resident(pond_ctx *ctx, int32_t on);
+
 /* 2D: the face kernel runs each face's frame iteration (Sec. III.B.3) for at most k
  * iterations; faces still iterating then continue, from the same state, in a tail kernel
  * that gives every face 16 lanes instead of one (a wave otherwise runs as long as its

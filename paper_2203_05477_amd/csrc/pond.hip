@@ -61,6 +61,9 @@ struct pond_ctx {
     hipGraphExec_t gexec = nullptr;
     double g_tend = 0.0;
     int g_slot = -1;
+    // 1D: every step of a pond_step call in one launch, one block per tube (longest first)
+    int resident = 0;
+    int *res_order = nullptr;
 };
 
 static void drop_graph(pond_ctx *c)
@@ -272,6 +275,24 @@ hipError_t launch_step(pond_ctx *c, double t_end)
     return hipGetLastError();
 }
 
+// the resident 1D kernel: 1,024 threads per tube in mixed precision (the FP32 face code
+// fits the 128 registers that leaves), 512 in FP64
+template <typename R>
+hipError_t launch_resident(pond_ctx *c, int nsteps, double t_end)
+{
+    State<R> S = state_of<R>(c);
+    constexpr int NT = sizeof(R) == 8 ? 512 : 1024;
+    const size_t lds = (size_t)(NT + 3) * Layout<1>::NL * sizeof(R);
+    if (c->P.limiter == POND_LIM_MINMOD)
+        tube_resident_kernel_1d<R, 1, NT><<<c->P.n_inst, NT, lds, c->stream>>>(c->P, S, t_end, nsteps, c->slot,
+                                                                                 c->res_order);
+    else
+        tube_resident_kernel_1d<R, 0, NT><<<c->P.n_inst, NT, lds, c->stream>>>(c->P, S, t_end, nsteps, c->slot,
+                                                                                 c->res_order);
+    c->slot ^= nsteps & 1;
+    return hipGetLastError();
+}
+
 hipError_t step_once(pond_ctx *c, double t_end)
 {
     if (c->D == 1)
@@ -361,7 +382,7 @@ void free_all(pond_ctx *c)
 {
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
                     c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch,
-                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock};
+                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock, c->res_order};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -571,7 +592,11 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         }
     }
     int s0 = 0;
-    if (c->use_graph && !c->timing && nsteps >= 2) {
+    if (c->resident && !c->timing && nsteps > 0 && c->cfg.seed_mode != POND_SEED_MLP) {
+        HIPCHK(c->precision == POND_FP64 ? launch_resident<double>(c, nsteps, t_end)
+                                         : launch_resident<float>(c, nsteps, t_end));
+        s0 = nsteps;
+    } else if (c->use_graph && !c->timing && nsteps >= 2) {
         if (!c->gexec || c->g_tend != t_end || c->g_slot != c->slot) {
             drop_graph(c);
             hipGraph_t g = nullptr;
@@ -970,6 +995,29 @@ pond_status pond_set_graph(pond_ctx *c, int32_t on)
     if (!c) return POND_EINVAL;
     c->use_graph = on ? 1 : 0;
     if (!on) drop_graph(c);
+    return POND_OK;
+}
+
+pond_status pond_set_resident(pond_ctx *c, int32_t on)
+{
+    if (!c || (on && c->D != 1)) return POND_EINVAL;
+    if (on && !c->res_order) {
+        // longest tubes first, so that the last blocks to start are the short ones
+        const int n = c->P.n_inst;
+        std::vector<int> ord(n);
+        for (int k = 0; k < n; ++k) ord[k] = k;
+        const auto &off = c->h_cell_off;
+        std::stable_sort(ord.begin(), ord.end(),
+                         [&](int a, int b) { return off[a + 1] - off[a] > off[b + 1] - off[b]; });
+        int *d = nullptr;
+        if (hipMalloc(&d, sizeof(int) * n) != hipSuccess) return POND_ENOMEM;
+        if (!hip_ok(hipMemcpy(d, ord.data(), sizeof(int) * n, hipMemcpyHostToDevice))) {
+            (void)hipFree(d);
+            return POND_EDEVICE;
+        }
+        c->res_order = d;
+    }
+    c->resident = on ? 1 : 0;
     return POND_OK;
 }
 

@@ -241,21 +241,21 @@ PD void vmax_update(const Params &P, const State<R> &S, int parity, int k, bool 
 // dt kernel: one 64-thread block per instance
 // ---------------------------------------------------------------------------------
 
+// dt of instance k from its CFL-rate copies of parity `slot` (which the other parity's
+// cell updates filled); clears the copies of the other parity. Every lane of one wave.
+// The copies and the instance's failure flag are read with device-scope atomic loads: they
+// were written by atomics, which act in L2, and a resident block (below) reads them again
+// on the CU that may still cache the previous step's values.
 template <int D, typename R>
-__global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_end, int slot)
+PD void instance_dt(const Params &P, const State<R> &S, int k, int lane, double t_end, int slot)
 {
-    const int k = blockIdx.x;
-    const int lane = threadIdx.x;
     unsigned long long m = 0ull;
     for (int c = lane; c < P.vslots; c += 64) {
-        unsigned long long v = S.vmax[vmax_at(P, slot, k, c)];
+        unsigned long long v =
+            __hip_atomic_load(S.vmax + vmax_at(P, slot, k, c), __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         m = v > m ? v : m;
         S.vmax[vmax_at(P, slot ^ 1, k, c)] = 0ull;
     }
-    if (k == 0 && S.tail_count)
-        for (int c = lane; c < 2 * NSLOT; c += 64) S.tail_count[c] = 0;
-    if (k == 0 && S.seed_count)
-        for (int c = lane; c < NSLOT; c += 64) S.seed_count[c] = 0;
 #pragma unroll
     for (int o = 32; o > 0; o >>= 1) {
         unsigned long long w = __shfl_xor(m, o, 64);
@@ -269,12 +269,25 @@ __global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_e
     if (P.dim == 2) rate = fmax(rate, P.bc_speed[1] / P.dy);
     double t = S.t[k];
     double dt = P.cfl / rate;
-    if (!(rate > 0.0) || S.inst_err[k]) dt = 0.0; // a failed instance stays frozen
+    const int failed = __hip_atomic_load(S.inst_err + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if (!(rate > 0.0) || failed) dt = 0.0; // a failed instance stays frozen
     if (t + dt > t_end) dt = t_end - t;
     if (!(dt > 0.0)) dt = 0.0;
     S.tstart[k] = t;
     S.dt[k] = dt;
     S.t[k] = t + dt;
+}
+
+template <int D, typename R>
+__global__ __launch_bounds__(64) void dt_kernel(Params P, State<R> S, double t_end, int slot)
+{
+    const int k = blockIdx.x;
+    const int lane = threadIdx.x;
+    if (k == 0 && S.tail_count)
+        for (int c = lane; c < 2 * NSLOT; c += 64) S.tail_count[c] = 0;
+    if (k == 0 && S.seed_count)
+        for (int c = lane; c < NSLOT; c += 64) S.seed_count[c] = 0;
+    instance_dt<D, R>(P, S, k, lane, t_end, slot);
 }
 
 // ---------------------------------------------------------------------------------
@@ -1681,6 +1694,73 @@ __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slo
     // the same L2
     const int64_t blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     cell_step<D, R>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
+}
+
+// 1D, resident: one block runs every step of a pond_step call for one tube (block b takes
+// tube order[b]), so a step costs no kernel launches and the tube's state stays in the
+// caches. Tubes are independent (each has its own dt), so the blocks never wait for each
+// other. Each step is the standard one: the tube's dt (one wave), its faces in chunks of
+// NT (LDS tile of NT + 3 records, as in face_kernel_1d), then its cells in chunks of NT,
+// with block barriers between the phases; per face and per cell the arithmetic is that of
+// the launched kernels, so the results are the same bits. Every trip count and branch
+// around a barrier depends only on the tube (uniform over the block).
+template <typename R, int LIM, int NT>
+__global__ __launch_bounds__(NT) void tube_resident_kernel_1d(Params P, State<R> S, double t_end, int nsteps,
+                                                               int slot0, const int *order)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *L = reinterpret_cast<R *>(smem_raw);
+    constexpr int NTL = NT + 3;
+    const int k = order ? order[blockIdx.x] : (int)blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t c0 = S.cell_off[k], c1 = S.cell_off[k + 1];
+    const int n = (int)(c1 - c0);
+    const int64_t fa = c0 + k, fz = c1 + k; // the tube's faces fa..fz
+    const int64_t pk = S.pad_off[k];
+    const double dxa = S.dxk ? S.dxk[k] : P.dx;
+    for (int s = 0; s < nsteps; ++s) {
+        const int slot = slot0 ^ (s & 1);
+        if (tid < 64) instance_dt<1, R>(P, S, k, tid, t_end, slot);
+        __syncthreads();
+        const double dt = S.dt[k];
+        if (dt > 0.0) {
+            const double tst = S.tstart[k];
+            for (int64_t f0 = fa; f0 <= fz; f0 += NT) {
+                const int64_t fl = min(f0 + NT - 1, fz);
+                const int64_t vlo = f0 + 3 * (int64_t)k, vhi = fl + 3 * (int64_t)k + 3;
+                for (int64_t v = vlo + tid; v <= vhi; v += NT) {
+                    const int q = (int)(v - pk) - 2;
+                    CellRef c{0, 0, 0, -1, 0};
+                    if (q >= 0 && q < n) {
+                        c.src = c0 + q;
+                    } else {
+                        const int side = (q < 0) ? 0 : 1;
+                        const int sq = side_rule(P, side, q, n, 0.0, xcen(P, q), 0.0, tst, c.mx, c.fside, c.falt);
+                        c.src = (sq < 0) ? -1 : c0 + sq;
+                    }
+                    plus_record<1, R>(P, S, c, dt, L + (v - vlo), NTL, 0);
+                }
+                __syncthreads();
+                const int64_t f = f0 + tid;
+                FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
+                unsigned long long nfc = 0;
+                if (f <= fl) {
+                    const int base = (int)(f + 3 * (int64_t)k - vlo);
+                    const int idx[4] = {base + 1, base + 2, base, base + 3};
+                    face_1d<R, LIM>(P, S, L, NTL, idx, f, dt, dxa, cnt);
+                    nfc = 1;
+                }
+                stat_add4(S.stats, ST_FACES, (unsigned)nfc, ST_NONCONV, (unsigned)cnt.nonconv, ST_FALLBACK,
+                          (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
+                stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+                stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
+                if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+                __syncthreads();
+            }
+            for (int64_t b = c0; b < c1; b += NT) cell_step<1, R>(P, S, b + tid, b + tid < c1, slot);
+        }
+        __syncthreads();
+    }
 }
 
 // The tail work (blocks [0, 2 * TAIL_BLOCKS): TAIL_BLOCKS per axis) beside the update of

@@ -109,6 +109,7 @@ def load(path: str | None = None):
         "pond_autotune": (S, [_P]),
         "pond_set_iter_split": (S, [_P, ctypes.c_int32]),
         "pond_set_graph": (S, [_P, ctypes.c_int32]),
+        "pond_set_resident": (S, [_P, ctypes.c_int32]),
         "pond_save": (S, [_P, ctypes.c_char_p]),
         "pond_load": (S, [_P, ctypes.c_char_p]),
         "pond_enable_timing": (S, [_P, ctypes.c_int32]),
@@ -145,6 +146,7 @@ def exported_symbols():
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
             "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split", "pond_set_graph",
+            "pond_set_resident",
             "pond_save", "pond_load",
             "pond_enable_timing",
             "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
@@ -362,6 +364,11 @@ class Context:
         rc = load().pond_set_graph(self._h, int(bool(on)))
         if rc != OK:
             raise PondError(rc, "pond_set_graph")
+
+    def set_resident(self, on: bool = True):
+        rc = load().pond_set_resident(self._h, int(bool(on)))
+        if rc != OK:
+            raise PondError(rc, "pond_set_resident")
 
     def set_iter_split(self, k: int):
         rc = load().pond_set_iter_split(self._h, int(k))
