@@ -184,7 +184,8 @@ pond_status pond_autotune(pond_ctx *ctx);
 pond_status pond_set_graph(pond_ctx *ctx, int32_t on);
 
 /* 1D only: on != 0 runs all the steps of each pond_step call in a single launch, one
- * 1,024-thread (mixed) or 512-thread (FP64) block per tube, longest tubes first; each
+ * block per tube, longest tubes first (256 threads for a batch of 256 tubes or more,
+ * otherwise 1,024 in mixed precision and 512 in FP64); each
  * block advances its tube step by step (the step of Sec. III.B.4 with the tube's own dt),
  * so no step pays kernel launch latency. Results, counters and failure handling are
  * identical to the launched kernels (same arithmetic per face and per cell). For small
