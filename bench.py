@@ -49,18 +49,18 @@ TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "double_mach_1920x480_face_traf
 KERNEL_SOURCES = ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip")
 
 
-def measured_traffic():
-    """HBM bytes per face-kernel launch from the committed counter summary (FETCH_SIZE and
-    WRITE_SIZE scaled by a known-size copy), or None once the kernel sources have changed
-    since those counters were taken."""
+def measured_traffic(tiles):
+    """HBM bytes per face-kernel launch at the given (BX, BY) tile from the committed counter
+    summary (FETCH_SIZE and WRITE_SIZE scaled by a known-size copy; one record per tile the
+    autotuner picks), or None without a record for that tile or once the kernel sources
+    have changed since those counters were taken."""
     import hashlib
 
     if not os.path.exists(TRAFFIC_PROFILE):
         return None
-    rec = None
-    for line in open(TRAFFIC_PROFILE):
-        if line.startswith("traffic-json:"):
-            rec = json.loads(line.split(":", 1)[1])
+    recs = [json.loads(line.split(":", 1)[1]) for line in open(TRAFFIC_PROFILE)
+            if line.startswith("traffic-json:")]
+    rec = next((r for r in recs if list(r["tiles"]) == list(tiles)), None)
     if rec is None:
         return None
     csrc = os.path.join(ROOT, "paper_2203_05477_amd", "csrc")
@@ -459,7 +459,7 @@ def main():
     main_finals = (st32["faces"] - st32["tail_faces"]) / args.steps
     face_flops = main_iters * FLOPS_FACE_ITER[2] + main_finals * FLOPS_FACE_FINAL[2]
     face_main_ms = kt32["face"]
-    traffic = measured_traffic()
+    traffic = measured_traffic(list(ctx32.tiles())[:2])
     achieved = face_flops / (face_main_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,

@@ -23,12 +23,15 @@ def test_traffic_figure_follows_the_source_hash():
     import bench
 
     txt = open(bench.TRAFFIC_PROFILE).read()
-    rec = json.loads(re.search(r"traffic-json: (\{.*\})", txt).group(1))
+    recs = [json.loads(m) for m in re.findall(r"traffic-json: (\{.*\})", txt)]
+    assert recs
     src = b"".join(open(os.path.join(ROOT, "paper_2203_05477_amd", "csrc", f), "rb").read()
                    for f in ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip"))
-    same = hashlib.sha256(src).hexdigest() == rec["sources_sha256"]
-    got = bench.measured_traffic()
-    if same:
-        assert got is not None and got["bytes_per_launch"] == rec["bytes_per_launch"] > 0
-    else:
-        assert got is None
+    for rec in recs:
+        same = hashlib.sha256(src).hexdigest() == rec["sources_sha256"]
+        got = bench.measured_traffic(rec["tiles"])
+        if same:
+            assert got is not None and got["bytes_per_launch"] == rec["bytes_per_launch"] > 0
+        else:
+            assert got is None
+    assert bench.measured_traffic([7, 3]) is None  # no record for a tile never measured
