@@ -7,7 +7,8 @@ no code with the GPU library and never imports it.
 
 Configurations are the plain dicts produced by the workload generators
 (keys: dim, nx, ny, x0, x1, y0, y1, gamma, cfl, mu, limiter, tol, max_iter, bc,
-bc_state, bc_alt, bc_param); boundary kinds and limiters are given by name.
+bc_state, bc_alt, bc_param, and optionally regularization); boundary kinds, limiters
+and regularizations are given by name.
 """
 from __future__ import annotations
 
@@ -31,6 +32,7 @@ BC_KIND = {
     "moving_shock": 6,
 }
 LIMITER = {"vanleer": 0, "minmod": 1}
+REGULARIZATION = {"grad": 0, "eq": 1}
 
 
 def build(force: bool = True) -> str:
@@ -55,6 +57,7 @@ class _Config(ctypes.Structure):
         ("bc_state", (ctypes.c_double * 4) * 4),
         ("bc_alt", (ctypes.c_double * 4) * 4),
         ("bc_param", (ctypes.c_double * 4) * 4),
+        ("reg", ctypes.c_int),
     ]
 
 
@@ -83,6 +86,7 @@ def _load():
     lib.orc_moments.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, _D]
     lib.orc_grad_project.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, _D]
     lib.orc_grad_coefficients.argtypes = [ctypes.c_int, ctypes.c_int, _D, _D, ctypes.c_double, _D]
+    lib.orc_eq_project.argtypes = [ctypes.c_int, _D, _D, ctypes.c_double, _D]
     lib.orc_limiter.restype = ctypes.c_double
     lib.orc_limiter.argtypes = [ctypes.c_int, ctypes.c_double, ctypes.c_double]
     for name in ("orc_phibar_plus", "orc_face_recover", "orc_update_relax"):
@@ -163,6 +167,18 @@ def grad_coefficients(dim: int, order: int, M, u, T) -> np.ndarray:
     return out
 
 
+def eq_project(dim, M, u, T):
+    """Populations of the alternative regularization of Sec. II.C (moments of order 0..3
+    kept, the other moments at equilibrium in the new frame) with lab moments M (packed
+    as for grad_project, order 3) in frame {u, T}."""
+    lib = _load()
+    M = _f64(M)
+    u = _f64(np.atleast_1d(u))
+    out = np.zeros(4 ** dim)
+    lib.orc_eq_project(dim, _ptr(M), _ptr(u), float(T), _ptr(out))
+    return out
+
+
 def limiter(kind: str, a: float, b: float) -> float:
     return _load().orc_limiter(LIMITER[kind], float(a), float(b))
 
@@ -196,6 +212,7 @@ def _make_config(cfg: dict) -> _Config:
     c.limiter = LIMITER[cfg.get("limiter", "vanleer")]
     c.tol = float(cfg["tol"])
     c.max_iter = int(cfg["max_iter"])
+    c.reg = REGULARIZATION[cfg.get("regularization", "grad")]
     bc = cfg["bc"]
     for k in range(4):
         c.bc[k] = BC_KIND[bc[k]]

@@ -212,6 +212,121 @@ static void grad_project(const lattice *L, int order, const tensors *M, const do
     grad_populations(L, order, &a, f);
 }
 
+/* The alternative regularization of Sec. II.C: in the new frame the moments of order
+ * 0..3 keep their values, the remaining Q - q moments take their equilibrium values, and
+ * the populations follow from the Q x Q moment system of the new frame.
+ * Readings (the paper leaves both open):
+ *  - the moment vector is that of the frame-relative velocities c = (v - u')/sqrt(T'),
+ *    the monomials c_x^a c_y^b with 0 <= a, b <= 3 (independent on the product lattice);
+ *    the slow ones are a + b <= 3 (they carry the same information as M_0..M_3), the fast
+ *    ones a + b >= 4. Monomials of the lab velocities would make the result depend on
+ *    the lab velocity of the frame itself (not Galilean invariant), which the frame-relative
+ *    ones do not;
+ *  - the equilibrium of the fast moments depends on M_0 and M_1 only: it is the
+ *    product-form equilibrium of the new frame's lattice with density M_0 and velocity
+ *    M_1/M_0, i.e. in frame-relative variables rho g_a(d_x) g_b(d_y) with
+ *    d = (M_1/M_0 - u')/sqrt(T') and the unit-variance Gaussian moments
+ *    g_0 = 1, g_1 = d, g_2 = d^2 + 1, g_3 = d^3 + 3 d.
+ * D1Q4 has Q = q: no fast moments, the Grad projection is the same transformation. */
+static double ipow(double x, int n)
+{
+    double r = 1.0;
+    for (int k = 0; k < n; ++k) r *= x;
+    return r;
+}
+
+static double binom(int n, int k)
+{
+    double r = 1.0;
+    for (int j = 1; j <= k; ++j) r = r * (n - k + j) / j;
+    return r;
+}
+
+/* lab moment with a x-components and b y-components, a + b <= 3 */
+static double lab_moment(const tensors *M, int a, int b)
+{
+    int idx[3], n = 0;
+    for (int k = 0; k < a; ++k) idx[n++] = 0;
+    for (int k = 0; k < b; ++k) idx[n++] = 1;
+    if (n == 0) return M->t0;
+    if (n == 1) return M->t1[idx[0]];
+    if (n == 2) return M->t2[idx[0]][idx[1]];
+    return M->t3[idx[0]][idx[1]][idx[2]];
+}
+
+/* solve A x = b (n x n, row-major in A[n][n+1] with b as the last column) by Gaussian
+ * elimination with partial pivoting */
+static void gauss_solve(int n, double A[MAXQ][MAXQ + 1], double *x)
+{
+    for (int col = 0; col < n; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < n; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (piv != col)
+            for (int k = 0; k <= n; ++k) {
+                double t = A[col][k];
+                A[col][k] = A[piv][k];
+                A[piv][k] = t;
+            }
+        for (int r = col + 1; r < n; ++r) {
+            double m = A[r][col] / A[col][col];
+            for (int k = col; k <= n; ++k) A[r][k] -= m * A[col][k];
+        }
+    }
+    for (int r = n - 1; r >= 0; --r) {
+        double acc = A[r][n];
+        for (int k = r + 1; k < n; ++k) acc -= A[r][k] * x[k];
+        x[r] = acc / A[r][r];
+    }
+}
+
+static void eq_project(const lattice *L, const tensors *M, const double *up, double Tp, double *f)
+{
+    if (L->D == 1) {
+        grad_project(L, 3, M, up, Tp, f);
+        return;
+    }
+    const double s = sqrt(Tp / TL);
+    const double rho = M->t0;
+    const double d[2] = {(M->t1[0] / rho - up[0]) / s, (M->t1[1] / rho - up[1]) / s};
+    double g[2][4];
+    for (int a = 0; a < 2; ++a) {
+        g[a][0] = 1.0;
+        g[a][1] = d[a];
+        g[a][2] = d[a] * d[a] + 1.0;
+        g[a][3] = d[a] * d[a] * d[a] + 3.0 * d[a];
+    }
+    double A[MAXQ][MAXQ + 1];
+    int row = 0;
+    for (int b = 0; b < 4; ++b)
+        for (int a = 0; a < 4; ++a, ++row) {
+            for (int i = 0; i < L->Q; ++i) A[row][i] = ipow(L->c[i][0], a) * ipow(L->c[i][1], b);
+            double rhs = 0.0;
+            if (a + b <= 3) {
+                /* frame-relative moment from the lab ones: expand
+                 * ((v_x - u'_x)/s)^a ((v_y - u'_y)/s)^b binomially */
+                for (int k = 0; k <= a; ++k)
+                    for (int l = 0; l <= b; ++l)
+                        rhs += binom(a, k) * binom(b, l) * ipow(-up[0], a - k) * ipow(-up[1], b - l) *
+                               lab_moment(M, k, l);
+                rhs /= ipow(s, a + b);
+            } else {
+                rhs = rho * g[0][a] * g[1][b];
+            }
+            A[row][L->Q] = rhs;
+        }
+    gauss_solve(L->Q, A, f);
+}
+
+/* the f-population transformation of the configured regularization */
+static void project_f(const lattice *L, int reg, const tensors *M, const double *up, double Tp, double *f)
+{
+    if (reg == ORC_REG_EQ)
+        eq_project(L, M, up, Tp, f);
+    else
+        grad_project(L, 3, M, up, Tp, f);
+}
+
 /* packing helpers for the exported unit functions */
 static void pack(int D, int order, const tensors *M, double *out)
 {
@@ -260,6 +375,15 @@ void orc_grad_project(int dim, int order, const double *M, const double *u, doub
     make_lattice(dim, &L);
     unpack(dim, order, M, &t);
     grad_project(&L, order, &t, u, T, f);
+}
+
+void orc_eq_project(int dim, const double *M, const double *u, double T, double *f)
+{
+    lattice L;
+    tensors t;
+    make_lattice(dim, &L);
+    unpack(dim, 3, M, &t);
+    eq_project(&L, &t, u, T, f);
 }
 
 void orc_grad_coefficients(int dim, int order, const double *M, const double *u, double T, double *a)
@@ -396,7 +520,7 @@ static void reframe_cell(const orc_sim *s, const cellrec *in, cellrec *out)
     macro(s, in->f, in->g, in->u, in->T, &rho, u, &T);
     moments(&s->L, in->f, in->u, in->T, &Mf);
     moments(&s->L, in->g, in->u, in->T, &Mg);
-    grad_project(&s->L, 3, &Mf, u, T, out->f);
+    project_f(&s->L, s->cfg.reg, &Mf, u, T, out->f);
     grad_project(&s->L, 2, &Mg, u, T, out->g);
     for (int a = 0; a < s->D; ++a) out->u[a] = u[a];
     out->T = T;
@@ -619,7 +743,7 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
     for (it = 1; it <= s->cfg.max_iter; ++it) {
         /* transform every stencil cell into the current frame lambda_k */
         for (int k = 0; k < ns; ++k) {
-            grad_project(&s->L, 3, &Mf[k], lu, lT, Pf[k]);
+            project_f(&s->L, s->cfg.reg, &Mf[k], lu, lT, Pf[k]);
             grad_project(&s->L, 2, &Mg[k], lu, lT, Pg[k]);
         }
         velocities(&s->L, lu, lT, v);
@@ -889,7 +1013,7 @@ int orc_step(orc_sim *s, double t_end, orc_stats *st)
                     unpack(D, 3, F->Mf, &Mf);
                     unpack(D, 2, F->Mg, &Mg);
                     double pf[MAXQ], pg[MAXQ];
-                    grad_project(&s->L, 3, &Mf, c->u, c->T, pf);
+                    project_f(&s->L, s->cfg.reg, &Mf, c->u, c->T, pf);
                     grad_project(&s->L, 2, &Mg, c->u, c->T, pg);
                     double nsign = side ? 1.0 : -1.0;
                     for (int q = 0; q < Q; ++q) {

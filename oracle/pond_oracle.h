@@ -29,6 +29,12 @@ enum {
 
 enum { ORC_LIM_VANLEER = 0, ORC_LIM_MINMOD = 1 };
 
+/* regularization of the f-populations in a change of frame (Sec. II.C): third-order Grad
+ * projection (the paper's choice), or the alternative that keeps the moments of order
+ * 0..3 and sets the other Q - q moments to equilibrium by moment inversion (D2Q16 only;
+ * in 1D, D1Q4 has no other moments and both are the same). */
+enum { ORC_REG_GRAD = 0, ORC_REG_EQ = 1 };
+
 typedef struct {
     int dim;              /* 1 or 2                                   */
     int nx, ny;           /* interior cells (ny = 1 in 1D)            */
@@ -43,6 +49,7 @@ typedef struct {
     double bc_state[4][4];/* rho, ux, uy, p                           */
     double bc_alt[4][4];  /* second state (window / pre-shock)        */
     double bc_param[4][4];/* geometry parameters                      */
+    int reg;              /* ORC_REG_*                                */
 } orc_config;
 
 typedef struct {
@@ -56,6 +63,10 @@ typedef struct {
 } orc_stats;
 
 typedef struct orc_sim orc_sim;
+
+/* the ORC_REG_EQ transformation of populations with lab moments M (packed as for
+ * orc_grad_project, order 3) into frame {u, T}: f has Q entries */
+void orc_eq_project(int dim, const double *M, const double *u, double T, double *f);
 
 /* lattice of Table I: D1Q4 (dim 1) or D2Q16 (dim 2). c: Q*dim, W: Q. returns Q */
 int orc_lattice(int dim, double *c, double *W);
