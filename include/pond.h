@@ -63,7 +63,17 @@ enum {
 enum { POND_LIM_VANLEER = 0, POND_LIM_MINMOD = 1 };
 enum { POND_FP64 = 0, POND_MIXED = 1 };    /* MIXED: FP32 populations, FP64 conserved */
 enum { POND_SEED_PREV = 0, POND_SEED_MLP = 1 };
-enum { POND_FLAG_STRICT = 1 };             /* non-converged faces are an error        */
+enum {
+    POND_FLAG_STRICT = 1, /* non-converged faces are an error                              */
+    /* the alternative regularization of Sec. II.C for the f populations (2D; in 1D the
+     * D1Q4 moments are all kept and it changes nothing): in every change of frame the
+     * moments of degree <= 3 are kept and the six other moments of the D2Q16 moment
+     * vector (frame-relative monomials c_x^a c_y^b, a, b <= 3, a + b >= 4) take the values
+     * of the product-form equilibrium with the state's density and velocity and the new
+     * frame's temperature; the populations follow by moment inversion. Default: the
+     * third-order Grad projection, the paper's choice. */
+    POND_FLAG_REG_EQ = 2
+};
 
 /* Problem statement (paper Sec. IV: initial fields on a uniform grid, gamma, CFL,
  * viscosity, boundary conditions). Caller-owned, copied by pond_init. */

@@ -177,20 +177,56 @@ size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
     return (size_t)(nts ? nts : (bx + 3) * (by + 3)) * Layout<2>::NL * c->rsize;
 }
 
-template <typename R, int LIM>
-void launch_face_2d(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
+// 1: the alternative regularization of the f populations (2D only; in 1D it changes nothing)
+int reg_of(const pond_ctx *c) { return (c->D == 2 && (c->cfg.flags & POND_FLAG_REG_EQ)) ? 1 : 0; }
+
+template <typename R, int LIM, int REG>
+void launch_face_2d_reg(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
 {
     dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
     switch (face_nts(bx, by)) {
     case 256:
-        face_kernel_2d<R, LIM, 256><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 256, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         break;
     case 512:
-        face_kernel_2d<R, LIM, 512><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 512, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         break;
     default:
-        face_kernel_2d<R, LIM, 0><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 0, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
     }
+}
+
+template <typename R, int LIM>
+void launch_face_2d(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
+{
+    if (reg_of(c))
+        launch_face_2d_reg<R, LIM, 1>(c, S, bx, by, lds);
+    else
+        launch_face_2d_reg<R, LIM, 0>(c, S, bx, by, lds);
+}
+
+template <typename R, int REG>
+void launch_face_tail_reg(pond_ctx *c, const State<R> &S)
+{
+    // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
+    dim3 tgrid(NSLOT * 4, 2);
+    if (c->P.limiter == POND_LIM_MINMOD)
+        face_tail_kernel_2d<R, 1, REG><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+    else
+        face_tail_kernel_2d<R, 0, REG><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+}
+
+// the tail beside the update of the cells outside its faces' stencils, then those
+template <typename R, int REG>
+void launch_tail_cells_reg(pond_ctx *c, const State<R> &S, hipEvent_t ev_mid)
+{
+    const unsigned nb = 2 * TAIL_BLOCKS + (unsigned)blocks(c->P.ncell, 256);
+    if (c->P.limiter == POND_LIM_MINMOD)
+        tail_cell_kernel_2d<R, 1, REG><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+    else
+        tail_cell_kernel_2d<R, 0, REG><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+    if (ev_mid) (void)hipEventRecord(ev_mid, c->stream);
+    cell_marked_kernel_2d<R, REG><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
 }
 
 int compute_span(const pond_ctx *c, int B)
@@ -230,12 +266,10 @@ hipError_t launch_face(pond_ctx *c, int bx, int by, bool with_tail)
         else
             launch_face_2d<R, 0>(c, S, bx, by, lds);
         if (with_tail && c->P.iter_split > 0) {
-            // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
-            dim3 tgrid(NSLOT * 4, 2);
-            if (c->P.limiter == POND_LIM_MINMOD)
-                face_tail_kernel_2d<R, 1><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+            if (reg_of(c))
+                launch_face_tail_reg<R, 1>(c, S);
             else
-                face_tail_kernel_2d<R, 0><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+                launch_face_tail_reg<R, 0>(c, S);
         }
     }
     return hipGetLastError();
@@ -258,17 +292,16 @@ hipError_t launch_step(pond_ctx *c, double t_end)
     if (e != hipSuccess) return e;
     if (tm) (void)hipEventRecord(c->ev[3], c->stream);
     if (D == 2 && c->P.iter_split > 0) {
-        // the tail beside the update of the cells outside its faces' stencils, then those
-        const unsigned nb = 2 * TAIL_BLOCKS + (unsigned)blocks(c->P.ncell, 256);
-        if (c->P.limiter == POND_LIM_MINMOD)
-            tail_cell_kernel_2d<R, 1><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+        if (reg_of(c))
+            launch_tail_cells_reg<R, 1>(c, S, tm ? c->ev[4] : nullptr);
         else
-            tail_cell_kernel_2d<R, 0><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
-        if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-        cell_marked_kernel_2d<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
+            launch_tail_cells_reg<R, 0>(c, S, tm ? c->ev[4] : nullptr);
     } else {
         if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-        cell_kernel<D, R><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+        if (reg_of(c))
+            cell_kernel<D, R, 1><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+        else
+            cell_kernel<D, R, 0><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
     }
     if (tm) (void)hipEventRecord(c->ev[5], c->stream);
     c->slot ^= 1;
@@ -342,6 +375,7 @@ pond_status validate(const pond_config *cfg, const double *rho, const double *ux
     if (!(cfg->x1 > cfg->x0) || (cfg->dim == 2 && !(cfg->y1 > cfg->y0))) return POND_EINVAL;
     if (cfg->precision != POND_FP64 && cfg->precision != POND_MIXED) return POND_EINVAL;
     if (cfg->limiter != POND_LIM_VANLEER && cfg->limiter != POND_LIM_MINMOD) return POND_EINVAL;
+    if (cfg->flags & ~(POND_FLAG_STRICT | POND_FLAG_REG_EQ)) return POND_EINVAL;
     double Cv = 1.0 / (cfg->gamma - 1.0);
     if (!(Cv - 0.5 * cfg->dim > 0.0)) return POND_EINVAL;
     for (int s = 0; s < 4; ++s) {
@@ -859,10 +893,15 @@ pond_status pond_populations(const pond_ctx *c, double *f, double *g, double *fr
         else
             pops_kernel<1, float><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
     } else {
-        if (c->precision == POND_FP64)
-            pops_kernel<2, double><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        const bool r1 = reg_of(c) != 0;
+        if (c->precision == POND_FP64 && r1)
+            pops_kernel<2, double, 1><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        else if (c->precision == POND_FP64)
+            pops_kernel<2, double, 0><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        else if (r1)
+            pops_kernel<2, float, 1><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
         else
-            pops_kernel<2, float><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
+            pops_kernel<2, float, 0><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
     }
     bool ok = hip_ok(hipGetLastError()) &&
               hip_ok(hipMemcpyAsync(f, df, nb * Q, hipMemcpyDeviceToHost, c->stream)) &&

@@ -402,6 +402,119 @@ PD void eval_q_cols_2d(const R q[10], int cols, R p[16], int order)
     }
 }
 
+// ---------------------------------------------------------------------------------
+// The alternative regularization of Sec. II.C for f (2D): the moments of degree <= 3 are
+// kept and the six others of the D2Q16 moment vector (c_x^a c_y^b, a, b <= 3, a + b >= 4,
+// in the frame-relative velocities of the new frame) take the values of the product-form
+// equilibrium with the state's density and velocity and the frame's temperature. In the
+// scaled form the coefficients ARE the Hermite moments q_ab = sum_i f_i He_a He_b, so with
+// d = (q10, q01)/q00 the equilibrium's are q00 d_x^a d_y^b and, writing Dq = q - q_eq for the
+// kept ones, the condition on the raw moments fixes the other six:
+//   q31 = q_eq31 - 3 Dq11, q13 = q_eq13 - 3 Dq11, q22 = q_eq22 - Dq20 - Dq02,
+//   q32 = q_eq32 - 3 Dq12 - Dq30, q23 = q_eq23 - 3 Dq21 - Dq03, q33 = q_eq33 + 9 Dq11
+// (from c^2 = He2 + 1 and c^3 = He3 + 3 He1 on each axis).
+// Fast order: 31 22 13 32 23 33.
+// ---------------------------------------------------------------------------------
+
+template <typename R>
+PD void eq_fast_2d(const R q[10], R qf[6])
+{
+    const R rho = q[0];
+    const R ir = R(1) / rho;
+    const R dx = q[1] * ir, dy = q[2] * ir;
+    const R rx = rho * dx, ry = rho * dy;
+    const R e20 = rx * dx, e11 = rx * dy, e02 = ry * dy;
+    const R d20 = q[3] - e20, d11 = q[4] - e11, d02 = q[5] - e02;
+    const R d30 = q[6] - e20 * dx, d21 = q[7] - e20 * dy, d12 = q[8] - e02 * dx, d03 = q[9] - e02 * dy;
+    const R e31 = e20 * dx * dy, e22 = e20 * dy * dy, e13 = e02 * dx * dy;
+    qf[0] = fma(R(-3), d11, e31);
+    qf[1] = e22 - d20 - d02;
+    qf[2] = fma(R(-3), d11, e13);
+    qf[3] = fma(R(-3), d12, e31 * dy) - d30;
+    qf[4] = fma(R(-3), d21, e13 * dx) - d03;
+    qf[5] = fma(R(9), d11, e22 * dx * dy);
+}
+
+// reduced populations from the 10 kept and 6 fast scaled coefficients (the full tensor
+// product of degrees <= 3 per axis; sum factorization over y then x, as eval_q_2d)
+template <typename R>
+PD void eval_q16_2d(const R q[10], const R qf[6], R p[16])
+{
+    // rows of x degree a: (a0, a1, a2, a3)
+    const R g[4][4] = {{q[0], q[2], q[5], q[9]},
+                       {q[1], q[4], q[8], qf[2]},
+                       {q[3], q[7], qf[1], qf[4]},
+                       {q[6], qf[0], qf[3], qf[5]}};
+    R B[4][4];
+#pragma unroll
+    for (int m = 0; m < 2; ++m) {
+        const R c = m ? Lat<R>::cb : Lat<R>::ca;
+        const R e2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+        const R e3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+        const int ip = m ? 3 : 2, im = m ? 0 : 1;
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+            const R E = fma(g[a][2], e2, g[a][0]), O = fma(g[a][3], e3, g[a][1] * c);
+            B[a][ip] = E + O;
+            B[a][im] = E - O;
+        }
+    }
+#pragma unroll
+    for (int iy = 0; iy < 4; ++iy) {
+#pragma unroll
+        for (int m = 0; m < 2; ++m) {
+            const R c = m ? Lat<R>::cb : Lat<R>::ca;
+            const R e2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+            const R e3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+            const int ip = m ? 3 : 2, im = m ? 0 : 1;
+            const R E = fma(B[2][iy], e2, B[0][iy]), O = fma(B[3][iy], e3, B[1][iy] * c);
+            p[ip + 4 * iy] = E + O;
+            p[im + 4 * iy] = E - O;
+        }
+    }
+}
+
+// the populations of the node columns in `cols` only, from the 16 scaled coefficients (as
+// eval_q_cols_2d, explicit fma throughout)
+template <typename R, int AXIS>
+PD void eval_q16_cols_2d(const R q[10], const R qf[6], int cols, R p[16])
+{
+    // G[n][t]: normal degree n, tangential degree t
+    const R gx[4][4] = {{q[0], q[2], q[5], q[9]},
+                        {q[1], q[4], q[8], qf[2]},
+                        {q[3], q[7], qf[1], qf[4]},
+                        {q[6], qf[0], qf[3], qf[5]}};
+    R G[4][4];
+#pragma unroll
+    for (int n = 0; n < 4; ++n)
+#pragma unroll
+        for (int t = 0; t < 4; ++t) G[n][t] = AXIS ? gx[t][n] : gx[n][t];
+#pragma unroll
+    for (int n = 0; n < 4; ++n) {
+        R out[4] = {R(0), R(0), R(0), R(0)};
+        if (cols & (1 << n)) {
+            const R cn = node<R>(n);
+            const R e2 = (n == 1 || n == 2) ? LatQ<R>::e2a : LatQ<R>::e2b;
+            const R e3n = (n == 1 || n == 2) ? LatQ<R>::e3a : LatQ<R>::e3b;
+            const R e3 = (n < 2) ? -e3n : e3n; // He3 is odd
+            R A[4];
+#pragma unroll
+            for (int t = 0; t < 4; ++t) A[t] = fma(e3, G[3][t], fma(e2, G[2][t], fma(cn, G[1][t], G[0][t])));
+#pragma unroll
+            for (int m = 0; m < 2; ++m) {
+                const R ct = m ? Lat<R>::cb : Lat<R>::ca;
+                const R t2 = m ? LatQ<R>::e2b : LatQ<R>::e2a;
+                const R t3 = m ? LatQ<R>::e3b : LatQ<R>::e3a;
+                const R E = fma(A[2], t2, A[0]), O = fma(A[3], t3, A[1] * ct);
+                out[m ? 3 : 2] = E + O;
+                out[m ? 0 : 1] = E - O;
+            }
+        }
+#pragma unroll
+        for (int t = 0; t < 4; ++t) p[AXIS ? (t + 4 * n) : (n + 4 * t)] = out[t];
+    }
+}
+
 // raw moments mu = sum_i W_i p_i c^k (1D), up to degree n-1
 template <typename R>
 PD void moments_1d(const R p[4], R mu[4], int n)

@@ -466,8 +466,9 @@ PD void cell_pops_1d(const R *L, int NT, int c, R u, R inv_s, R p[4])
 }
 
 // The 2D records hold the coefficients in the scaled form q (see q2mu_2d); the transform
-// into the face frame and the evaluation work on that form.
-template <typename R, bool G>
+// into the face frame and the evaluation work on that form. REG = 1: the f populations of
+// the alternative regularization (eq_fast_2d), the g populations unchanged.
+template <typename R, bool G, int REG = 0>
 PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
 {
     R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
@@ -481,7 +482,13 @@ PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
         q2mu_2d(q, mu, 10);
         shift_2d(mu, r, dx, dy, 10);
         mu2q_2d(mu, q, 10);
-        eval_q_2d(q, p, 3);
+        if (REG) {
+            R qf[6];
+            eq_fast_2d(q, qf);
+            eval_q16_2d(q, qf, p);
+        } else {
+            eval_q_2d(q, p, 3);
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
@@ -493,7 +500,7 @@ PD void cell_pops_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, R p[16])
 }
 
 // the populations of stencil cell c in the node columns `cols` (wave-uniform) only
-template <typename R, bool G, int AXIS>
+template <typename R, bool G, int AXIS, int REG = 0>
 PD void cell_cols_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int cols, R p[16])
 {
     R r = L[2 * NT + c] * inv_s, dx = (L[c] - ux) * inv_s, dy = (L[NT + c] - uy) * inv_s;
@@ -507,7 +514,13 @@ PD void cell_cols_2d(const R *L, int NT, int c, R ux, R uy, R inv_s, int cols, R
         q2mu_2d(q, mu, 10);
         shift_2d(mu, r, dx, dy, 10);
         mu2q_2d(mu, q, 10);
-        eval_q_cols_2d<R, AXIS>(q, cols, p, 3);
+        if (REG) {
+            R qf[6];
+            eq_fast_2d(q, qf);
+            eval_q16_cols_2d<R, AXIS>(q, qf, cols, p);
+        } else {
+            eval_q_cols_2d<R, AXIS>(q, cols, p, 3);
+        }
     } else {
 #pragma unroll
         for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
@@ -551,7 +564,7 @@ PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx,
 // SUB: every lane of the wave takes the two negative normal node columns from the R side
 // and the two positive ones from the L side (|normal frame velocity| below s*ca, the usual
 // case); the side cells of the stencil are then evaluated in the two columns they feed only.
-template <typename R, bool G, int AXIS, bool SUB>
+template <typename R, bool G, int AXIS, bool SUB, int REG = 0>
 PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
                  int lim, R M[10])
 {
@@ -571,15 +584,15 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
     }
     constexpr int cup = SUB ? 0xC : 0xF, cdn = SUB ? 0x3 : 0xF;
     const R sc = R(limit_scale(lim)); // slopes come from limit_part
-    cell_pops_2d<R, G>(L, NT, idx[0], ux, uy, inv_s, PL);
+    cell_pops_2d<R, G, REG>(L, NT, idx[0], ux, uy, inv_s, PL);
     __builtin_amdgcn_sched_barrier(0);
-    cell_pops_2d<R, G>(L, NT, idx[1], ux, uy, inv_s, PR);
+    cell_pops_2d<R, G, REG>(L, NT, idx[1], ux, uy, inv_s, PR);
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[2], ux, uy, inv_s, cup, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[2], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = upn[nk(i)] ? PL[i] - T[i] : PR[i] - PL[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[3], ux, uy, inv_s, cdn, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[3], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const bool up = upn[nk(i)];
@@ -593,20 +606,20 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
     }
     // tangential slope of the upwind cell
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[4], ux, uy, inv_s, cup, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[4], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) A[i] = PL[i] - T[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[6], ux, uy, inv_s, cdn, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[6], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i)
         if (!upn[nk(i)]) A[i] = PL[i] - T[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[5], ux, uy, inv_s, cup, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[5], ux, uy, inv_s, cup, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) PR[i] = T[i] - PL[i];
     __builtin_amdgcn_sched_barrier(0);
-    cell_cols_2d<R, G, AXIS>(L, NT, idx[7], ux, uy, inv_s, cdn, T);
+    cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[7], ux, uy, inv_s, cdn, T);
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
@@ -736,7 +749,7 @@ PD void own_half_1d(const R *L, int NT, int c, bool right, R um, R inv_sm, R mu[
     shift_1d(mu, s * inv_sm, (u - um) * inv_sm, 4);
 }
 
-template <typename R, bool G, int AXIS>
+template <typename R, bool G, int AXIS, int REG = 0>
 PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_sm, R mu[10])
 {
     R ux = L[c], uy = L[NT + c], s = L[2 * NT + c];
@@ -746,7 +759,13 @@ PD void own_half_2d(const R *L, int NT, int c, bool right, R umx, R umy, R inv_s
         q[1] = R(0);
         q[2] = R(0);
         for (int k = 0; k < 7; ++k) q[3 + k] = L[(4 + k) * NT + c];
-        eval_q_2d(q, p, 3);
+        if (REG) {
+            R qf[6];
+            eq_fast_2d(q, qf);
+            eval_q16_2d(q, qf, p);
+        } else {
+            eval_q_2d(q, p, 3);
+        }
     } else {
         for (int k = 0; k < 6; ++k) q[k] = L[(11 + k) * NT + c];
         eval_q_2d(q, p, 2);
@@ -944,7 +963,7 @@ PD void tail_cell(const Params &P, int64_t f, int q, int &ci, int &cj)
     }
 }
 
-template <typename R, int AXIS, int LIM>
+template <typename R, int AXIS, int LIM, int REG = 0>
 PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const int idx[2], int sn,
                 int stn, int64_t f, double dt, FaceCount &cnt)
 {
@@ -976,10 +995,10 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
             const int sidx[8] = {b0, b0 + sn, b0 - sn, b0 + 2 * sn, b0 - stn, b0 + stn, b0 + sn - stn, b0 + sn + stn};
             const R un = AXIS ? u[1] : u[0];
             if (__all(!(fma(s, node<R>(1), un) >= R(0)) && (fma(s, node<R>(2), un) >= R(0)))) {
-                recon_2d<R, false, AXIS, true>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
+                recon_2d<R, false, AXIS, true, REG>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
                 recon_2d<R, true, AXIS, true>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
             } else {
-                recon_2d<R, false, AXIS, false>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
+                recon_2d<R, false, AXIS, false, REG>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mf);
                 recon_2d<R, true, AXIS, false>(L, NT, sidx, u[0], u[1], s, inv_s, hdn, hdt, LIM, mg);
             }
         }
@@ -1065,8 +1084,8 @@ PD void face_2d(const Params &P, const State<R> &S, const R *L, int NT, const in
     if (failed || !conv) {
         R sm = sqrt(T_m), inv_sm = R(1) / sm;
         R a[10], b[10];
-        own_half_2d<R, false, AXIS>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
-        own_half_2d<R, false, AXIS>(L, NT, idx[1], true, um[0], um[1], inv_sm, b);
+        own_half_2d<R, false, AXIS, REG>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
+        own_half_2d<R, false, AXIS, REG>(L, NT, idx[1], true, um[0], um[1], inv_sm, b);
         for (int k = 0; k < 10; ++k) mf[k] = a[k] + b[k];
         own_half_2d<R, true, AXIS>(L, NT, idx[0], false, um[0], um[1], inv_sm, a);
         own_half_2d<R, true, AXIS>(L, NT, idx[1], true, um[0], um[1], inv_sm, b);
@@ -1166,7 +1185,7 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
 // that the record loads take their plane offsets as immediates; 0: the tile's own size.
 // The FP64 Van Leer kernel is held to 2 waves per SIMD: it then spills a few registers,
 // and still runs 17% faster than with 1 wave (the FP64 minmod kernel does not gain).
-template <typename R, int LIM, int NTS>
+template <typename R, int LIM, int NTS, int REG = 0>
 __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void face_kernel_2d(Params P, State<R> S)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -1196,12 +1215,12 @@ __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void fac
     unsigned long long nfaces = 0;
     if (i <= P.nx && j < P.ny) {
         const int idx[2] = {li(i - 1, j), li(i, j)};
-        face_2d<R, 0, LIM>(P, S, L, NT, idx, 1, TX, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
+        face_2d<R, 0, LIM, REG>(P, S, L, NT, idx, 1, TX, (int64_t)i + (int64_t)(P.nx + 1) * j, dt, cnt);
         ++nfaces;
     }
     if (i < P.nx && j <= P.ny) {
         const int idx[2] = {li(i, j - 1), li(i, j)};
-        face_2d<R, 1, LIM>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
+        face_2d<R, 1, LIM, REG>(P, S, L, NT, idx, TX, 1, P.nfx + (int64_t)i + (int64_t)P.nx * j, dt, cnt);
         ++nfaces;
     }
     stat_add4(S.stats, ST_FACES, (unsigned)nfaces, ST_NONCONV, (unsigned)cnt.nonconv, ST_FALLBACK,
@@ -1224,11 +1243,15 @@ __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void fac
 // over the 16 lanes. Same iteration, same stopping rules and finalization as face_2d.
 
 constexpr int TAIL_REC = 8 * Layout<2>::NL; // 8 stencil records
-// per stencil cell: f 10, g 6 coefficients, one pad (an odd stride keeps the cells that the
-// lanes of a wave read at one time on different LDS banks)
-constexpr int TAIL_CSTRIDE = 17;
-constexpr int TAIL_COEF = 8 * TAIL_CSTRIDE;
-constexpr int TAIL_GROUP = TAIL_REC + TAIL_COEF;
+// per stencil cell: f 10, g 6 coefficients (and with REG = 1 the 6 fast f coefficients
+// after them), one pad (an odd stride keeps the cells that the lanes of a wave read at one
+// time on different LDS banks)
+template <int REG>
+struct TailDims {
+    static constexpr int CSTRIDE = REG ? 23 : 17;
+    static constexpr int COEF = 8 * CSTRIDE;
+    static constexpr int GROUP = TAIL_REC + COEF;
+};
 
 // LDS written by some lanes of a wave and read by others of the same wave
 PD void wave_fence()
@@ -1274,10 +1297,11 @@ PD R group_sum(R v)
 // One face per 16-lane group. Every lane of the wave runs every instruction of the
 // iteration (a group that is done, or has no face, computes and discards), so the cross-lane
 // sums and the LDS exchange never run under a partial execution mask.
-template <typename R, int AXIS, int LIM>
+template <typename R, int AXIS, int LIM, int REG = 0>
 PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e, bool has,
                   int q, double dt, double t, FaceCount &cnt)
 {
+    constexpr int CS = TailDims<REG>::CSTRIDE;
     const int64_t nf = P.tail_n;
     const int64_t f = has ? S.tail_f[e] : 0;
     if (has && q < 8) {
@@ -1322,6 +1346,10 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
                        R(0.5) * (cx2 - R(1)) * cy,
                        R(0.5) * cx * (cy2 - R(1)),
                        cy * (cy2 - R(3)) * R(1.0 / 6.0)};
+    // REG = 1: the basis of the fast coefficients, order 31 22 13 32 23 33
+    const R hx2 = R(0.5) * (cx2 - R(1)), hy2 = R(0.5) * (cy2 - R(1));
+    const R hx3 = cx * (cx2 - R(3)) * R(1.0 / 6.0), hy3 = cy * (cy2 - R(3)) * R(1.0 / 6.0);
+    const R basf[6] = {hx3 * cy, hx2 * hy2, cx * hy3, hx3 * hy2, hx2 * hy3, hx3 * hy3};
     const R wgt = weight1<R>(ix) * weight1<R>(iy);
     const R cn = node<R>(AXIS ? iy : ix), ct = node<R>(AXIS ? ix : iy);
     // stencil cell transformed by this lane
@@ -1354,11 +1382,17 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
             q2mu_2d(h, mu, 10); // the records hold scaled coefficients
             shift_2d(mu, r, dx, dy, 10);
             mu2q_2d(mu, h, 10);
-            R *dst = coef + tc * TAIL_CSTRIDE + (tg ? 10 : 0);
+            R *dst = coef + tc * CS + (tg ? 10 : 0);
             const int nw = tg ? 6 : 10;
 #pragma unroll
             for (int k = 0; k < 10; ++k)
                 if (k < nw) dst[k] = h[k];
+            if (REG && !tg) {
+                R hf[6];
+                eq_fast_2d(h, hf);
+#pragma unroll
+                for (int k = 0; k < 6; ++k) dst[16 + k] = hf[k];
+            }
         }
         wave_fence();
         const R un = AXIS ? u[1] : u[0], ut = AXIS ? u[0] : u[1];
@@ -1369,10 +1403,14 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         R vf[5], vg[5];
 #pragma unroll
         for (int m = 0; m < 5; ++m) {
-            const R *h = coef + cl[m] * TAIL_CSTRIDE;
+            const R *h = coef + cl[m] * CS;
             R a = h[0], b = h[10];
 #pragma unroll
             for (int k = 1; k < 10; ++k) a += h[k] * bas[k];
+            if (REG) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) a += h[16 + k] * basf[k];
+            }
 #pragma unroll
             for (int k = 1; k < 6; ++k) b += h[10 + k] * bas[k];
             vf[m] = a;
@@ -1456,8 +1494,8 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         if (failed || !conv) {
             R sm = sqrt(T_m), inv_sm = R(1) / sm;
             R a[10], b[10];
-            own_half_2d<R, false, AXIS>(rec, 8, 0, false, um[0], um[1], inv_sm, a);
-            own_half_2d<R, false, AXIS>(rec, 8, 1, true, um[0], um[1], inv_sm, b);
+            own_half_2d<R, false, AXIS, REG>(rec, 8, 0, false, um[0], um[1], inv_sm, a);
+            own_half_2d<R, false, AXIS, REG>(rec, 8, 1, true, um[0], um[1], inv_sm, b);
             for (int k = 0; k < 10; ++k) mf[k] = a[k] + b[k];
             own_half_2d<R, true, AXIS>(rec, 8, 0, false, um[0], um[1], inv_sm, a);
             own_half_2d<R, true, AXIS>(rec, 8, 1, true, um[0], um[1], inv_sm, b);
@@ -1533,23 +1571,23 @@ PD int64_t tail_entry(const Params &P, const int *pre, int axis, int64_t k)
 }
 
 // LDS of one tail block
-template <typename R>
+template <typename R, int REG = 0>
 struct TailShared {
-    R rec[16 * TAIL_GROUP];
+    R rec[16 * TailDims<REG>::GROUP];
     int pre[NSLOT + 1];
     int wtot[4];
 };
 
 // block bx of nbx (256 threads) of the tail work of one axis
-template <typename R, int LIM>
-PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int axis, int bx, int nbx)
+template <typename R, int LIM, int REG = 0>
+PD void tail_block(const Params &P, const State<R> &S, TailShared<R, REG> &sh, int axis, int bx, int nbx)
 {
     R *lds = sh.rec;
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
     const double t = S.tstart[0];
     const int q = threadIdx.x & 15, grp = threadIdx.x >> 4;
-    R *rec = lds + grp * TAIL_GROUP, *coef = rec + TAIL_REC;
+    R *rec = lds + grp * TailDims<REG>::GROUP, *coef = rec + TAIL_REC;
     // The faces of the axis's NSLOT sub-lists, concatenated, are dealt out 16 per block in
     // turn, so that no block works through a long sub-list alone (the hard faces cluster in
     // the sub-lists of the face-kernel waves that cover a shock).
@@ -1574,9 +1612,9 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int ax
         int64_t e = 0;
         if (has) e = tail_entry(P, pre, axis, k);
         if (axis == 0)
-            tail_face<R, 0, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 0, LIM, REG>(P, S, rec, coef, e, has, q, dt, t, cnt);
         else
-            tail_face<R, 1, LIM>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 1, LIM, REG>(P, S, rec, coef, e, has, q, dt, t, cnt);
     }
     stat_add4(S.stats, ST_TAIL_FACES, (unsigned)cnt.tail_faces, ST_NONCONV, (unsigned)cnt.nonconv,
               ST_FALLBACK, (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
@@ -1586,11 +1624,11 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R> &sh, int ax
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
-template <typename R, int LIM>
+template <typename R, int LIM, int REG = 0>
 __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
 {
-    __shared__ TailShared<R> sh;
-    tail_block<R, LIM>(P, S, sh, blockIdx.y, blockIdx.x, gridDim.x);
+    __shared__ TailShared<R, REG> sh;
+    tail_block<R, LIM, REG>(P, S, sh, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // clears n ints (grid-stride)
@@ -1666,13 +1704,13 @@ PD void face_flux(const Params &P, const State<R> &S, int64_t f, int axis, doubl
     }
 }
 
-template <int D, typename R>
+template <int D, typename R, int REG = 0>
 PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
                     unsigned long long &bits, bool &all_conv);
 
 // update of cell c (taken = false: no cell for this lane), with the wave-level CFL maximum
 // and counters; every lane of the wave calls it
-template <int D, typename R>
+template <int D, typename R, int REG = 0>
 PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int slot)
 {
     const bool active = taken && c < P.ncell;
@@ -1681,19 +1719,19 @@ PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int
     const bool work = active && dt > 0.0;
     unsigned long long bits = 0ull;
     bool all_conv = false;
-    if (work) cell_update<D, R>(P, S, c, k, dt, slot, bits, all_conv);
+    if (work) cell_update<D, R, REG>(P, S, c, k, dt, slot, bits, all_conv);
     vmax_update<R>(P, S, slot ^ 1, k, work, bits);
     stat_add4(S.stats, ST_CELLS, work ? 1u : 0u, ST_CONV_CELLS, (work && all_conv) ? 1u : 0u, -1, 0u,
               -1, 0u);
 }
 
-template <int D, typename R>
+template <int D, typename R, int REG = 0>
 __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
 {
     // contiguous runs of blocks per XCD: the rows above and below, which share y-faces, in
     // the same L2
     const int64_t blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    cell_step<D, R>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
+    cell_step<D, R, REG>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
 }
 
 // 1D, resident: one block runs every step of a pond_step call for one tube (block b takes
@@ -1770,34 +1808,34 @@ __global__ __launch_bounds__(NT) void tube_resident_kernel_1d(Params P, State<R>
 constexpr int TAIL_BLOCKS = 4 * NSLOT;
 static_assert((2 * TAIL_BLOCKS) % NXCD == 0, "the cell blocks start on XCD 0");
 
-template <typename R, int LIM>
+template <typename R, int LIM, int REG = 0>
 __global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S, int slot)
 {
-    __shared__ TailShared<R> sh;
+    __shared__ TailShared<R, REG> sh;
     if ((int)blockIdx.x < 2 * TAIL_BLOCKS) {
-        tail_block<R, LIM>(P, S, sh, (int)blockIdx.x / TAIL_BLOCKS, (int)blockIdx.x % TAIL_BLOCKS,
+        tail_block<R, LIM, REG>(P, S, sh, (int)blockIdx.x / TAIL_BLOCKS, (int)blockIdx.x % TAIL_BLOCKS,
                            TAIL_BLOCKS);
         return;
     }
     // 2 * TAIL_BLOCKS is a multiple of the XCD count: cell block k runs on XCD k mod 8
     const int64_t blk = xcd_tile((int)blockIdx.x - 2 * TAIL_BLOCKS, (int)gridDim.x - 2 * TAIL_BLOCKS);
     const int64_t c = blk * 256 + threadIdx.x;
-    cell_step<2, R>(P, S, c, c < P.ncell && !S.tblock[c], slot);
+    cell_step<2, R, REG>(P, S, c, c < P.ncell && !S.tblock[c], slot);
 }
 
 // After the tail: the cells in the stencils of its faces (marked by the face kernel), one
 // thread per cell of the grid; each clears its mark for the next step.
-template <typename R>
+template <typename R, int REG = 0>
 __global__ __launch_bounds__(256) void cell_marked_kernel_2d(Params P, State<R> S, int slot)
 {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool marked = c < P.ncell && S.tblock[c] != 0;
     if (!__any(marked)) return;
     if (marked) S.tblock[c] = 0;
-    cell_step<2, R>(P, S, c, marked, slot);
+    cell_step<2, R, REG>(P, S, c, marked, slot);
 }
 
-template <int D, typename R>
+template <int D, typename R, int REG>
 PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
                     unsigned long long &bits_out, bool &all_conv_out)
 {
@@ -1912,11 +1950,25 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
             mg[9] = R(3) * mg[2];
             const R kf = (R)(dt / (axis ? P.dy : P.dx)) * sgn;
             const R ks = kf * su, ku = kf * (axis ? uy : ux);
-            // degree-4 moments of the degree-3 f expansion that the normal flux needs, from
-            // h00 = mu_00, h20 = (mu_20 - mu_00) / 2, h02 = (mu_02 - mu_00) / 2, h11 = mu_11:
-            // mu_22 = h00 + 2 h20 + 2 h02, mu_31 = mu_13 = 3 h11, mu_40 = 3 h00 + 12 h20
-            const R m22 = mu[3] + mu[5] - mu[0];
-            const R m31 = R(3) * mu[4];
+            // degree-4 moments of the face populations that the normal flux needs. Grad: those
+            // of the degree-3 expansion, from h00 = mu_00, h20 = (mu_20 - mu_00) / 2,
+            // h02 = (mu_02 - mu_00) / 2, h11 = mu_11: mu_22 = h00 + 2 h20 + 2 h02,
+            // mu_31 = mu_13 = 3 h11. REG = 1: the product-form equilibrium's with the face
+            // state's density and velocity in the cell frame (d = mu_10/mu_00, mu_01/mu_00):
+            // mu_22 = rho (dx^2 + 1)(dy^2 + 1), mu_31 = rho (dx^3 + 3 dx) dy, mu_13 likewise.
+            // Either way mu_40 = 6 mu_20 - 3 mu_00 on the D1Q4 nodes (roots of He4).
+            R m22, m31, m13;
+            if (REG) {
+                const R ir = R(1) / mu[0];
+                const R ddx = mu[1] * ir, ddy = mu[2] * ir;
+                m22 = mu[0] * fma(ddx, ddx, R(1)) * fma(ddy, ddy, R(1));
+                m31 = mu[0] * ddx * fma(ddx, ddx, R(3)) * ddy;
+                m13 = mu[0] * ddy * fma(ddy, ddy, R(3)) * ddx;
+            } else {
+                m22 = mu[3] + mu[5] - mu[0];
+                m31 = R(3) * mu[4];
+                m13 = m31;
+            }
             if (axis == 0) {
                 const R m40 = R(6) * mu[3] - R(3) * mu[0];
                 // alpha + e_x: 00->10 10->20 01->11 20->30 11->21 02->12 30->40 21->31 12->22 03->13
@@ -1929,7 +1981,7 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
                 mfo[6] -= ks * m40 + ku * mu[6];
                 mfo[7] -= ks * m31 + ku * mu[7];
                 mfo[8] -= ks * m22 + ku * mu[8];
-                mfo[9] -= ks * m31 + ku * mu[9];
+                mfo[9] -= ks * m13 + ku * mu[9];
                 mgo[0] -= ks * mg[1] + ku * mg[0];
                 mgo[1] -= ks * mg[3] + ku * mg[1];
                 mgo[2] -= ks * mg[4] + ku * mg[2];
@@ -1947,7 +1999,7 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
                 mfo[5] -= ks * mu[9] + ku * mu[5];
                 mfo[6] -= ks * m31 + ku * mu[6];
                 mfo[7] -= ks * m22 + ku * mu[7];
-                mfo[8] -= ks * m31 + ku * mu[8];
+                mfo[8] -= ks * m13 + ku * mu[8];
                 mfo[9] -= ks * m04 + ku * mu[9];
                 mgo[0] -= ks * mg[2] + ku * mg[0];
                 mgo[1] -= ks * mg[4] + ku * mg[1];
@@ -2062,7 +2114,7 @@ __global__ void fields_kernel(int64_t n, const double *U, double Cv, double *out
 }
 
 // populations f~ = W_i (...) and g~ of every cell in its co-moving frame
-template <int D, typename R>
+template <int D, typename R, int REG = 0>
 __global__ void pops_kernel(Params P, State<R> S, double *f, double *g, double *frame)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -2090,7 +2142,16 @@ __global__ void pops_kernel(Params P, State<R> S, double *f, double *g, double *
         for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
         for (int q = 6; q < 10; ++q) hg[q] = 0.0;
         double p[16], q2[16];
-        eval_2d(h, p, 3);
+        if (REG) {
+            // the scaled form (Hermite moments h_ab a! b!) and the six fast ones
+            const double q[10] = {h[0], h[1], h[2], 2.0 * h[3], h[4], 2.0 * h[5],
+                                  6.0 * h[6], 2.0 * h[7], 2.0 * h[8], 6.0 * h[9]};
+            double qf[6];
+            eq_fast_2d(q, qf);
+            eval_q16_2d(q, qf, p);
+        } else {
+            eval_2d(h, p, 3);
+        }
         eval_2d(hg, q2, 2);
         for (int i = 0; i < 16; ++i) {
             double W = weight1<double>(i & 3) * weight1<double>(i >> 2);
