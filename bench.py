@@ -35,6 +35,11 @@ METRIC = "converged Mcell-updates/s at fixed L1 err vs FP64 oracle; learned+FP32
 # (f 52, g 32); 32 limited populations x 16 + 60 shared; moments of f (108) and g (80);
 # frame update 40.
 FLOPS_FACE_ITER = {1: 330, 2: 2236}
+# With the alternative regularization (--regularization eq) each iteration also sets the six
+# fast f coefficients of the 8 stencil cells (43 flops each) and evaluates 16 f coefficients
+# instead of 10 (L and R in full: 112 instead of 86; side cells, 2 columns: 76 instead of 52):
+# 2,236 + 344 + 52 + 144 = 2,776.
+FLOPS_FACE_ITER_EQ2 = 2776
 FLOPS_FACE_FINAL = {1: 60, 2: 330}
 # FP64 / FP32 vector peaks of MI355X (no packed FP32 instructions are used: FP32 issues at
 # the FP64 rate, so both peaks are the 78.6 TFLOP/s non-packed figure)
@@ -357,6 +362,10 @@ def main():
     ap.add_argument("--workload", default="double_mach",
                     choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
+    ap.add_argument("--regularization", choices=["grad", "eq"], default="grad",
+                    help="transformation of the f populations between frames: third-order Grad "
+                         "projection (the paper's choice) or the alternative with the fast moments "
+                         "at equilibrium (Sec. II.C)")
     ap.add_argument("--iter-split", type=int, default=None,
                     help="face iterations per face in the face kernel before the tail kernel takes "
                          "over (0: no tail kernel, the cell update is one kernel)")
@@ -397,6 +406,7 @@ def main():
     tol32, tol64 = W.TOL_FP32, W.TOL_FP64
     cfg32, fields = W.double_mach(args.nx, args.ny, tol=tol32)
     cfg64, _ = W.double_mach(args.nx, args.ny, tol=tol64)
+    cfg32["regularization"] = cfg64["regularization"] = args.regularization
     ncell = args.nx * args.ny
 
     tiles = tuple(int(v) for v in args.tiles.split("x")) if args.tiles else None
@@ -412,6 +422,7 @@ def main():
 
         t0 = time.perf_counter()
         cfgh, fh = W.double_mach(args.nx // 4, args.ny // 4, tol=tol32)
+        cfgh["regularization"] = args.regularization
         data = LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2)
         net, losses, nsamp = LS.train([data], epochs=20, batch=4096, lr=2e-3)
         t_train = time.perf_counter() - t0
@@ -457,9 +468,11 @@ def main():
     # the face kernel proper (the tail kernel's share of faces and iterations taken out)
     main_iters = (st32["iters_total"] - st32["tail_iters"]) / args.steps
     main_finals = (st32["faces"] - st32["tail_faces"]) / args.steps
-    face_flops = main_iters * FLOPS_FACE_ITER[2] + main_finals * FLOPS_FACE_FINAL[2]
+    it_flops = FLOPS_FACE_ITER_EQ2 if args.regularization == "eq" else FLOPS_FACE_ITER[2]
+    face_flops = main_iters * it_flops + main_finals * FLOPS_FACE_FINAL[2]
     face_main_ms = kt32["face"]
-    traffic = measured_traffic(list(ctx32.tiles())[:2])
+    # the counter summary covers the Grad kernel only
+    traffic = measured_traffic(list(ctx32.tiles())[:2]) if args.regularization == "grad" else None
     achieved = face_flops / (face_main_ms * 1e-3) / 1e12
     line = {
         "metric": METRIC,
@@ -477,13 +490,14 @@ def main():
         "config": {"workload": f"double_mach_reflection_{args.nx}x{args.ny}", "lattice": "D2Q16",
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain",
                    "tol": tol32, "cfl": cfg32["cfl"], "mu": cfg32["mu"],
+                   "regularization": args.regularization,
                    "steps_from_t0": args.warmup + args.steps},
         "roofline": {"bound": "alu", "achieved": achieved, "peak": PEAK_VALU_TFLOPS,
                      "unit": "TFLOP/s", "frac": achieved / PEAK_VALU_TFLOPS,
                      "traffic": traffic["bytes_per_launch"] if traffic else None,
                      "traffic_unit": "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE)",
                      "traffic_tiles": traffic["tiles"] if traffic else None,
-                     "kernel": "face_kernel_2d<float, 0>", "kernel_ms": face_main_ms,
+                     "kernel": "face_kernel_2d<float, 0>" + (" (regularization eq)" if args.regularization == "eq" else ""), "kernel_ms": face_main_ms,
                      "flop_per_launch": face_flops},
         "cell_updates": st32["cell_updates"],
         "converged_fraction": st32["converged_cell_updates"] / max(st32["cell_updates"], 1),
@@ -509,6 +523,7 @@ def main():
     ctx32.close()
     if not args.no_cpu_baseline:
         cfgc, fc = W.double_mach(args.nx, args.ny, tol=tol64)
+        cfgc["regularization"] = args.regularization
         line["cpu_baseline"] = cpu_baseline(cfgc, fc)
     print(json.dumps(line), flush=True)
 
