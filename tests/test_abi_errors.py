@@ -66,6 +66,21 @@ def test_invalid_input_is_rejected(cfg, f):
     assert _init_status(cfg, f) == EINVAL
 
 
+def test_unknown_flag_bits_are_rejected():
+    """Only POND_FLAG_STRICT and POND_FLAG_REG_EQ are defined: any other bit is an error."""
+    lib = pond.load()
+    cfg, f = W.double_mach(16, 8)
+    c, keep = pond.make_config(cfg)
+    c.flags = 4
+    arrs = [np.ascontiguousarray(np.asarray(f[k], dtype=np.float64)) for k in ("rho", "ux", "uy", "p")]
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert lib.pond_init(ctypes.byref(c), *[P(a) for a in arrs], ctypes.byref(h)) == EINVAL
+    assert not h.value
+    c2, _ = pond.make_config(dict(cfg, regularization="eq"))
+    assert c2.flags == pond.FLAG_REG_EQ
+
+
 def test_batch_rules():
     """A batch needs tubes of at least 4 cells and no periodic ends."""
     cfg, f = W.tube_batch(n_tubes=3, len_lo=10, len_hi=20)
@@ -95,6 +110,7 @@ def test_null_handles_and_strerror():
     assert lib.pond_step(P(), 1, 1.0, None) == EINVAL
     assert lib.pond_set_iter_split(P(), 2) == EINVAL
     assert lib.pond_set_graph(P(), 1) == EINVAL
+    assert lib.pond_set_resident(P(), 1) == EINVAL
     assert lib.pond_set_tiles(P(), 8, 8, 256) == EINVAL
     assert lib.pond_autotune(P()) == EINVAL
     assert lib.pond_kernel_times(P(), None) == EINVAL
