@@ -72,7 +72,14 @@ enum {
      * of the product-form equilibrium with the state's density and velocity and the new
      * frame's temperature; the populations follow by moment inversion. Default: the
      * third-order Grad projection, the paper's choice. */
-    POND_FLAG_REG_EQ = 2
+    POND_FLAG_REG_EQ = 2,
+    /* 1D only: the semi-Lagrangian realization of Sec. III.A instead of the finite-volume
+     * scheme: every cell iterates its frame with its populations advected from the
+     * departure points x - v_i dt (4-point interpolating cubic kernel over the cell centres,
+     * clipped into the range of the two enclosing cells), then relaxes with the BGK
+     * collision of that section. Not conservative (the paper's point in favour of the
+     * finite-volume scheme). Not with the learned seed or the resident launch (EINVAL). */
+    POND_FLAG_SEMI_LAGRANGIAN = 4
 };
 
 /* Problem statement (paper Sec. IV: initial fields on a uniform grid, gamma, CFL,

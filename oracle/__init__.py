@@ -7,8 +7,8 @@ no code with the GPU library and never imports it.
 
 Configurations are the plain dicts produced by the workload generators
 (keys: dim, nx, ny, x0, x1, y0, y1, gamma, cfl, mu, limiter, tol, max_iter, bc,
-bc_state, bc_alt, bc_param, and optionally regularization); boundary kinds, limiters
-and regularizations are given by name.
+bc_state, bc_alt, bc_param, and optionally regularization and scheme); boundary kinds,
+limiters, regularizations and schemes are given by name.
 """
 from __future__ import annotations
 
@@ -33,6 +33,7 @@ BC_KIND = {
 }
 LIMITER = {"vanleer": 0, "minmod": 1}
 REGULARIZATION = {"grad": 0, "eq": 1}
+SCHEME = {"fv": 0, "sl": 1}
 
 
 def build(force: bool = True) -> str:
@@ -58,6 +59,7 @@ class _Config(ctypes.Structure):
         ("bc_alt", (ctypes.c_double * 4) * 4),
         ("bc_param", (ctypes.c_double * 4) * 4),
         ("reg", ctypes.c_int),
+        ("scheme", ctypes.c_int),
     ]
 
 
@@ -213,6 +215,7 @@ def _make_config(cfg: dict) -> _Config:
     c.tol = float(cfg["tol"])
     c.max_iter = int(cfg["max_iter"])
     c.reg = REGULARIZATION[cfg.get("regularization", "grad")]
+    c.scheme = SCHEME[cfg.get("scheme", "fv")]
     bc = cfg["bc"]
     for k in range(4):
         c.bc[k] = BC_KIND[bc[k]]

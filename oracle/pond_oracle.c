@@ -533,6 +533,7 @@ orc_sim *orc_create(const orc_config *cfg, const double *rho, const double *ux, 
     if (!cfg || (cfg->dim != 1 && cfg->dim != 2) || cfg->nx < 2) return NULL;
     if (cfg->dim == 2 && cfg->ny < 2) return NULL;
     if (!(cfg->gamma > 1.0)) return NULL;
+    if (cfg->scheme == ORC_SCHEME_SL && cfg->dim != 1) return NULL; /* 1D only */
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     s->cfg = *cfg;
     s->D = cfg->dim;
@@ -910,22 +911,12 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
 /* one time step (Sec. III.B.4)                                              */
 /* ------------------------------------------------------------------------- */
 
-int orc_step(orc_sim *s, double t_end, orc_stats *st)
+/* time step from CFL = max |v_ia| dt / dx_a (Sec. IV) over the cells (in their own frames)
+ * and the prescribed boundary states, clipped at t_end */
+static double time_step(const orc_sim *s, double t_end)
 {
     const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny;
     const double cmax = s->L.c[Q - 1][0]; /* largest node, sqrt(3 + sqrt 6) */
-    if (s->t >= t_end) return 1;
-
-    /* 1. every cell's populations in its own co-moving frame */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            cellrec tmp;
-            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
-            s->cell[cidx(s, i, j)] = tmp;
-        }
-
-    /* time step from CFL = max |v_ia| dt / dx_a (Sec. IV), clipped at t_end */
     double rate = 0.0;
 #pragma omp parallel for collapse(2) reduction(max : rate) schedule(static)
     for (int j = 0; j < ny; ++j)
@@ -956,6 +947,164 @@ int orc_step(orc_sim *s, double t_end, orc_stats *st)
     }
     double dt = s->cfg.cfl / rate;
     if (s->t + dt > t_end) dt = t_end - s->t;
+    return dt;
+}
+
+/* ------------------------------------------------------------------------- */
+/* the semi-Lagrangian realization (Sec. III.A), 1D                          */
+/* ------------------------------------------------------------------------- */
+
+/* Readings (the paper's interpolation recipe is in a cited thesis, not in the paper):
+ *  - collocation points are the cell centres; a population is interpolated at its
+ *    departure point from the 4 collocation points around it (2 on each side), all of
+ *    them transformed into the current frame by the regularized transformation;
+ *  - the 4-point kernel is the interpolating cubic (Catmull-Rom) spline, and the
+ *    limiter clips the value into the range of the two collocation points that enclose
+ *    the departure point;
+ *  - the frame iteration starts from the cell's own frame of the previous step (the
+ *    paper's seed) and stops as the face iteration does (tolerance, 2-cycle, max_iter);
+ *    a cell whose iteration does not converge keeps its last advected populations;
+ *  - the collision is the BGK map of Sec. III.A in the frame of the last advection, with
+ *    2 beta = 2 dt / (2 tau + dt), tau = mu / p, i.e. the same relaxation time as the
+ *    finite-volume scheme. */
+static void catmull_rom(double t, double w[4])
+{
+    const double t2 = t * t, t3 = t2 * t;
+    w[0] = 0.5 * (-t3 + 2.0 * t2 - t);
+    w[1] = 0.5 * (3.0 * t3 - 5.0 * t2 + 2.0);
+    w[2] = 0.5 * (-3.0 * t3 + 4.0 * t2 + t);
+    w[3] = 0.5 * (t3 - t2);
+}
+
+/* one cell: frame iteration of the advection, then the collision; writes the new
+ * populations (and their frame) into *out */
+static void sl_cell(const orc_sim *s, int j, double dt, cellrec *out, int *iters, int *conv_out,
+                    long long *depout)
+{
+    const int Q = s->Q;
+    tensors Mf[5], Mg[5];
+    for (int k = 0; k < 5; ++k) {
+        const cellrec *c = &s->plus[cidx(s, j - 2 + k, 0)];
+        moments(&s->L, c->f, c->u, c->T, &Mf[k]);
+        moments(&s->L, c->g, c->u, c->T, &Mg[k]);
+    }
+    const cellrec *own = &s->plus[cidx(s, j, 0)];
+    double lu[MAXD] = {own->u[0], 0.0}, lT = own->T;
+    double pu = 0.0, pT = 1.0;
+    double fa[MAXQ], ga[MAXQ], fu = lu[0], fT = lT;
+    int it, conv = 0, have_pp = 0;
+    for (it = 1; it <= s->cfg.max_iter; ++it) {
+        double Pf[5][MAXQ], Pg[5][MAXQ], v[MAXQ][MAXD];
+        for (int k = 0; k < 5; ++k) {
+            project_f(&s->L, s->cfg.reg, &Mf[k], lu, lT, Pf[k]);
+            grad_project(&s->L, 2, &Mg[k], lu, lT, Pg[k]);
+        }
+        velocities(&s->L, lu, lT, v);
+        for (int i = 0; i < Q; ++i) {
+            /* departure point x_j - v_i dt, in cells: d in (-1, 1) while the CFL rule holds */
+            const double d = -v[i][0] * dt / s->dx[0];
+            if (fabs(d) >= 1.0) ++*depout;
+            const int m = (d < 0.0) ? -1 : 0; /* base cell j + m, fraction d - m in [0, 1) */
+            double w[4];
+            catmull_rom(d - m, w);
+            double vf = 0.0, vg = 0.0;
+            for (int q = 0; q < 4; ++q) {
+                vf += w[q] * Pf[m + 1 + q][i];
+                vg += w[q] * Pg[m + 1 + q][i];
+            }
+            const double f1 = Pf[m + 2][i], f2 = Pf[m + 3][i];
+            const double g1 = Pg[m + 2][i], g2 = Pg[m + 3][i];
+            fa[i] = fmin(fmax(vf, fmin(f1, f2)), fmax(f1, f2));
+            ga[i] = fmin(fmax(vg, fmin(g1, g2)), fmax(g1, g2));
+        }
+        fu = lu[0];
+        fT = lT;
+        double rho, nu[MAXD] = {0, 0}, nT;
+        macro(s, fa, ga, lu, lT, &rho, nu, &nT);
+        if (!(rho > 0.0) || !(nT > 0.0) || !isfinite(nT)) break; /* the cell fails */
+        double delta = fmax(fabs(nu[0] - lu[0]) / sqrt(nT), fabs(nT - lT) / nT);
+        double delta2 = fmax(fabs(nu[0] - pu) / sqrt(nT), fabs(nT - pT) / nT);
+        pu = lu[0];
+        pT = lT;
+        lu[0] = nu[0];
+        lT = nT;
+        if (delta <= s->cfg.tol) {
+            conv = 1;
+            break;
+        }
+        if (have_pp && delta2 <= 1e-2 * delta) break; /* 2-cycle */
+        have_pp = 1;
+    }
+    if (it > s->cfg.max_iter) it = s->cfg.max_iter;
+    *iters = it;
+    *conv_out = conv;
+    /* collision in the frame of the last advection (Sec. III.A) */
+    double rho = 0.0;
+    for (int i = 0; i < Q; ++i) rho += fa[i];
+    const double eps = dt * rho * fT / s->cfg.mu;
+    const double b2 = 2.0 * eps / (2.0 + eps); /* 2 beta */
+    const double geq = (s->Cv - 0.5 * s->D) * rho * fT;
+    for (int i = 0; i < Q; ++i) {
+        out->f[i] = fa[i] + b2 * (rho * s->L.W[i] - fa[i]);
+        out->g[i] = ga[i] + b2 * (geq * s->L.W[i] - ga[i]);
+    }
+    out->u[0] = fu;
+    out->u[1] = 0.0;
+    out->T = fT;
+    out->rho = rho;
+}
+
+static int sl_step(orc_sim *s, double t_end, orc_stats *st)
+{
+    const int nx = s->nx;
+    for (int i = 0; i < nx; ++i) {
+        cellrec tmp;
+        reframe_cell(s, &s->cell[cidx(s, i, 0)], &tmp);
+        s->cell[cidx(s, i, 0)] = tmp;
+    }
+    const double dt = time_step(s, t_end);
+    for (int i = 0; i < nx; ++i) s->plus[cidx(s, i, 0)] = s->cell[cidx(s, i, 0)];
+    fill_ghosts(s);
+    long long itot = 0, nonc = 0, depout = 0;
+    int imax = 0;
+#pragma omp parallel for reduction(+ : itot, nonc, depout) reduction(max : imax) schedule(dynamic, 16)
+    for (int i = 0; i < nx; ++i) {
+        int it, conv;
+        sl_cell(s, i, dt, &s->cell[cidx(s, i, 0)], &it, &conv, &depout);
+        itot += it;
+        if (it > imax) imax = it;
+        if (!conv) ++nonc;
+    }
+    s->t += dt;
+    s->nstep += 1;
+    if (st) {
+        st->faces = nx;
+        st->iters_total = itot;
+        st->iters_max = imax;
+        st->nonconverged = nonc;
+        st->departure_out = depout;
+        st->nonphysical = 0;
+        st->dt = dt;
+    }
+    return nonc ? 2 : 0;
+}
+
+int orc_step(orc_sim *s, double t_end, orc_stats *st)
+{
+    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny;
+    if (s->t >= t_end) return 1;
+    if (s->cfg.scheme == ORC_SCHEME_SL) return sl_step(s, t_end, st);
+
+    /* 1. every cell's populations in its own co-moving frame */
+#pragma omp parallel for collapse(2) schedule(static)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            cellrec tmp;
+            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
+            s->cell[cidx(s, i, j)] = tmp;
+        }
+
+    double dt = time_step(s, t_end);
 
     /* 2. phi-bar-plus of every cell (Sec. III.B.3), eps = dt/tau = dt p / mu */
 #pragma omp parallel for collapse(2) schedule(static)

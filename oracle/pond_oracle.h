@@ -35,6 +35,10 @@ enum { ORC_LIM_VANLEER = 0, ORC_LIM_MINMOD = 1 };
  * in 1D, D1Q4 has no other moments and both are the same). */
 enum { ORC_REG_GRAD = 0, ORC_REG_EQ = 1 };
 
+/* discretization: the finite-volume scheme (Sec. III.B, the paper's main one) or the
+ * semi-Lagrangian realization (Sec. III.A; 1D only here) */
+enum { ORC_SCHEME_FV = 0, ORC_SCHEME_SL = 1 };
+
 typedef struct {
     int dim;              /* 1 or 2                                   */
     int nx, ny;           /* interior cells (ny = 1 in 1D)            */
@@ -50,6 +54,7 @@ typedef struct {
     double bc_alt[4][4];  /* second state (window / pre-shock)        */
     double bc_param[4][4];/* geometry parameters                      */
     int reg;              /* ORC_REG_*                                */
+    int scheme;           /* ORC_SCHEME_*                             */
 } orc_config;
 
 typedef struct {

@@ -63,6 +63,11 @@ struct pond_ctx {
     int g_slot = -1;
     // 1D: every step of a pond_step call in one launch, one block per tube (longest first)
     int resident = 0;
+    // semi-Lagrangian scheme: staging of the new state, and the largest number of tube
+    // boundaries inside a block of 256 cells
+    double *U2 = nullptr;
+    void *H2 = nullptr;
+    int sl_span = 0;
     int *res_order = nullptr;
 };
 
@@ -112,6 +117,8 @@ State<R> state_of(pond_ctx *c)
     S.stats = c->stats;
     S.err = c->err;
     S.inst_err = c->inst_err;
+    S.U2 = c->U2;
+    S.H2 = reinterpret_cast<R *>(c->H2);
     S.tail_f = c->tail_f;
     S.tail_s = reinterpret_cast<R *>(c->tail_s);
     S.tail_meta = c->tail_meta;
@@ -247,6 +254,25 @@ int compute_span(const pond_ctx *c, int B)
     return span;
 }
 
+// largest number of tube boundaries inside one block of B cells
+int compute_cell_span(const pond_ctx *c, int B)
+{
+    if (c->cfg.dim != 1 || c->P.n_inst == 1) return 0;
+    const int64_t n = c->P.ncell;
+    const auto &off = c->h_cell_off;
+    int span = 0, k = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += B) {
+        const int64_t cl = std::min(c0 + B, n) - 1;
+        while (k + 1 < c->P.n_inst && off[k + 1] <= c0) ++k;
+        int k1 = k;
+        while (k1 + 1 < c->P.n_inst && off[k1 + 1] <= cl) ++k1;
+        span = std::max(span, k1 - k);
+    }
+    return span;
+}
+
+bool semi_lagrangian(const pond_ctx *c) { return (c->cfg.flags & POND_FLAG_SEMI_LAGRANGIAN) != 0; }
+
 // the face kernel, and in 2D (with_tail) the tail kernel after it
 template <int D, typename R>
 hipError_t launch_face(pond_ctx *c, int bx, int by, bool with_tail)
@@ -288,6 +314,17 @@ hipError_t launch_step(pond_ctx *c, double t_end)
         if (e != hipSuccess) return e;
     }
     if (tm) (void)hipEventRecord(c->ev[2], c->stream);
+    if (D == 1 && semi_lagrangian(c)) {
+        // semi-Lagrangian step: every cell into the staging buffers, then committed
+        const size_t lds = (size_t)(256 + 4 + 4 * c->sl_span) * Layout<1>::NL * sizeof(R);
+        sl_kernel_1d<R><<<blocks(c->P.ncell, 256), 256, lds, c->stream>>>(c->P, S, c->sl_span, c->slot);
+        if (tm) (void)hipEventRecord(c->ev[3], c->stream);
+        if (tm) (void)hipEventRecord(c->ev[4], c->stream);
+        sl_commit_kernel<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S);
+        if (tm) (void)hipEventRecord(c->ev[5], c->stream);
+        c->slot ^= 1;
+        return hipGetLastError();
+    }
     hipError_t e = launch_face<D, R>(c, c->bx, c->by, false);
     if (e != hipSuccess) return e;
     if (tm) (void)hipEventRecord(c->ev[3], c->stream);
@@ -375,7 +412,9 @@ pond_status validate(const pond_config *cfg, const double *rho, const double *ux
     if (!(cfg->x1 > cfg->x0) || (cfg->dim == 2 && !(cfg->y1 > cfg->y0))) return POND_EINVAL;
     if (cfg->precision != POND_FP64 && cfg->precision != POND_MIXED) return POND_EINVAL;
     if (cfg->limiter != POND_LIM_VANLEER && cfg->limiter != POND_LIM_MINMOD) return POND_EINVAL;
-    if (cfg->flags & ~(POND_FLAG_STRICT | POND_FLAG_REG_EQ)) return POND_EINVAL;
+    if (cfg->flags & ~(POND_FLAG_STRICT | POND_FLAG_REG_EQ | POND_FLAG_SEMI_LAGRANGIAN)) return POND_EINVAL;
+    if ((cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) && (cfg->dim != 1 || cfg->seed_mode != POND_SEED_PREV))
+        return POND_EINVAL;
     double Cv = 1.0 / (cfg->gamma - 1.0);
     if (!(Cv - 0.5 * cfg->dim > 0.0)) return POND_EINVAL;
     for (int s = 0; s < 4; ++s) {
@@ -430,7 +469,8 @@ void free_all(pond_ctx *c)
 {
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
                     c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch,
-                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock, c->res_order};
+                    c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock, c->res_order,
+                    c->U2, c->H2};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -548,6 +588,10 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     alloc((void **)&c->err, sizeof(int));
     alloc((void **)&c->inst_err, sizeof(int) * P.n_inst);
     alloc((void **)&c->scratch, sizeof(double) * 4 * std::max(n, nf));
+    if (cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) {
+        alloc((void **)&c->U2, sizeof(double) * (c->D + 2) * n);
+        alloc(&c->H2, c->rsize * c->nh * n);
+    }
     if (P.n_inst > 1) {
         alloc((void **)&c->cell_inst, sizeof(int) * n);
         alloc((void **)&c->face_inst, sizeof(int) * nf);
@@ -613,6 +657,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         return POND_EDEVICE;
     }
     c->tube_span = compute_span(c, c->bx);
+    c->sl_span = compute_cell_span(c, 256);
     if (c->D == 1)
         c->precision == POND_FP64 ? init_launch<1, double>(c, c->scratch) : init_launch<1, float>(c, c->scratch);
     else
@@ -640,7 +685,7 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         }
     }
     int s0 = 0;
-    if (c->resident && !c->timing && nsteps > 0 && c->cfg.seed_mode != POND_SEED_MLP) {
+    if (c->resident && !c->timing && nsteps > 0 && c->cfg.seed_mode != POND_SEED_MLP && !semi_lagrangian(c)) {
         HIPCHK(c->precision == POND_FP64 ? launch_resident<double>(c, nsteps, t_end)
                                          : launch_resident<float>(c, nsteps, t_end));
         s0 = nsteps;
@@ -1053,7 +1098,7 @@ pond_status pond_set_graph(pond_ctx *c, int32_t on)
 
 pond_status pond_set_resident(pond_ctx *c, int32_t on)
 {
-    if (!c || (on && c->D != 1)) return POND_EINVAL;
+    if (!c || (on && (c->D != 1 || semi_lagrangian(c)))) return POND_EINVAL;
     if (on && !c->res_order) {
         // longest tubes first, so that the last blocks to start are the short ones
         const int n = c->P.n_inst;

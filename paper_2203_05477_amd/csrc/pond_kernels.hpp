@@ -65,6 +65,8 @@ struct State {
     unsigned long long *stats; // ST_N counters
     int *err;
     int *inst_err;             // per instance: nonzero once a step produced an invalid cell
+    double *U2;                // semi-Lagrangian scheme: staging of the new state
+    R *H2;
     // faces handed from the face kernel to the tail kernel (2D): face index, iteration
     // state (u_x, u_y, T, and the frame two iterations back: 6 planes of tail_n R), and
     // it | have_pp << 16 | restarted << 17. Entry (axis * NSLOT + slot) * tail_cap + pos:
@@ -1799,6 +1801,207 @@ __global__ __launch_bounds__(NT) void tube_resident_kernel_1d(Params P, State<R>
         }
         __syncthreads();
     }
+}
+
+// ---------------------------------------------------------------------------------
+// the semi-Lagrangian realization (Sec. III.A), 1D: one thread per cell
+// ---------------------------------------------------------------------------------
+
+// interpolating cubic (Catmull-Rom) weights of the 4 collocation points around a point at
+// fraction t in [0, 1) between the middle two
+template <typename R>
+PD void catmull_rom(R t, R w[4])
+{
+    const R t2 = t * t, t3 = t2 * t;
+    w[0] = R(0.5) * (t2 + t2 - t3 - t);
+    w[1] = R(0.5) * (R(3) * t3 - R(5) * t2 + R(2));
+    w[2] = R(0.5) * (R(4) * t2 - R(3) * t3 + t);
+    w[3] = R(0.5) * (t3 - t2);
+}
+
+// Cell c (padded slot c + 4 k + 2 of tube k) advects its populations from the departure
+// points x - v_i dt, interpolated from the 4 collocation points (cell centres) around each
+// with the Catmull-Rom kernel and clipped into the range of the two that enclose it, all
+// transformed into the current frame; the frame is iterated as at the faces (seed: the
+// cell's own frame; tolerance, 2-cycle and max_iter stops), then the BGK collision of
+// Sec. III.A (2 beta = 2 dt / (2 tau + dt)) acts in the frame of the last advection. The
+// new state (conserved variables from the moments, coefficients in the new co-moving
+// frame) goes to the staging buffers U2/H2: neighbours still read the old one. The LDS
+// tile holds the old state of the block's cells and two ghosts at each tube end (records
+// at eps = 0, i.e. the carried populations themselves).
+template <typename R>
+__global__ __launch_bounds__(256) void sl_kernel_1d(Params P, State<R> S, int span, int slot)
+{
+    extern __shared__ unsigned char smem_raw[];
+    R *L = reinterpret_cast<R *>(smem_raw);
+    const int B = blockDim.x;
+    const int NT = B + 4 + 4 * span;
+    const int64_t c0 = (int64_t)blockIdx.x * B;
+    const int64_t c = c0 + threadIdx.x;
+    const int64_t clast = min(c0 + B, P.ncell) - 1;
+    const int k0 = S.cell_inst ? S.cell_inst[c0] : 0;
+    const int k1 = S.cell_inst ? S.cell_inst[clast] : 0;
+    const int64_t vlo = c0 + 4 * (int64_t)k0, vhi = clast + 4 * (int64_t)k1 + 4;
+    for (int64_t v = vlo + threadIdx.x; v <= vhi; v += B) {
+        int k = k0;
+        while (k < k1 && v >= S.pad_off[k + 1]) ++k;
+        const int64_t cb = S.cell_off[k];
+        const int n = (int)(S.cell_off[k + 1] - cb);
+        const int q = (int)(v - S.pad_off[k]) - 2;
+        CellRef cr{0, 0, 0, -1, 0};
+        if (q >= 0 && q < n) {
+            cr.src = cb + q;
+        } else {
+            const int side = (q < 0) ? 0 : 1;
+            const int sq = side_rule(P, side, q, n, 0.0, xcen(P, q), 0.0, S.tstart[k], cr.mx, cr.fside, cr.falt);
+            cr.src = (sq < 0) ? -1 : cb + sq;
+        }
+        plus_record<1, R>(P, S, cr, 0.0, L + (v - vlo), NT, 0);
+    }
+    __syncthreads();
+    const bool active = c < P.ncell;
+    const int k = (active && S.cell_inst) ? S.cell_inst[c] : 0;
+    const double dt = active ? S.dt[k] : 0.0;
+    const bool work = active && dt > 0.0;
+    FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
+    unsigned long long bits = 0ull;
+    bool conv = false;
+    if (work) {
+        const double dxc = S.dxk ? S.dxk[k] : P.dx;
+        const int base = (int)(c + 4 * (int64_t)k - vlo); // stencil slots base .. base + 4
+        R lu = L[base + 2], lT = L[2 * NT + base + 2];
+        R pu = R(0), pT = R(1), fu = lu, fT = lT;
+        R pa[4] = {R(0), R(0), R(0), R(0)}, ga[4] = {R(0), R(0), R(0), R(0)};
+        bool have_pp = false;
+        int it;
+        for (it = 1; it <= P.max_iter; ++it) {
+            R s, inv_s;
+            frame_scale(lT, s, inv_s);
+            R Pf[5][4], Pg[5][4];
+#pragma unroll
+            for (int m = 0; m < 5; ++m) {
+                cell_pops_1d<R, false>(L, NT, base + m, lu, inv_s, Pf[m]);
+                cell_pops_1d<R, true>(L, NT, base + m, lu, inv_s, Pg[m]);
+            }
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const R vi = fma(s, node<R>(i), lu);
+                const R d = -vi * (R)(dt / dxc); // departure point, in cells
+                if (fabs(d) >= R(1)) cnt.depout += 1;
+                const int mb = (d < R(0)) ? 0 : 1; // stencil slot of the point before the base cell
+                R w[4];
+                catmull_rom(d - R(mb - 1), w);
+                R vf = R(0), vg = R(0);
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    vf = fma(w[q], Pf[mb + q][i], vf);
+                    vg = fma(w[q], Pg[mb + q][i], vg);
+                }
+                const R f1 = Pf[mb + 1][i], f2 = Pf[mb + 2][i], g1 = Pg[mb + 1][i], g2 = Pg[mb + 2][i];
+                pa[i] = fmin(fmax(vf, fmin(f1, f2)), fmax(f1, f2));
+                ga[i] = fmin(fmax(vg, fmin(g1, g2)), fmax(g1, g2));
+            }
+            fu = lu;
+            fT = lT;
+            R mf[4], mg[4];
+            moments_1d(pa, mf, 4);
+            moments_1d(ga, mg, 3);
+            const R rho = mf[0];
+            const R nu = fma(s, mf[1] / rho, lu);
+            // rho E in frame (lu, s): sum (v^2/2) f + sum g, v = lu + s c; T = (E/rho - u^2/2)/C_v
+            const R e = R(0.5) * (s * s * mf[2] + R(2) * s * lu * mf[1] + lu * lu * mf[0]) + mg[0];
+            const R nT = (e / rho - R(0.5) * nu * nu) / (R)P.Cv;
+            if (!(rho > R(0)) || !(nT > R(0)) || !isfinite(nT)) break;
+            const R ns = sqrt(nT);
+            const R delta = fmax(fabs(nu - lu) / ns, fabs(nT - lT) / nT);
+            const R delta2 = fmax(fabs(nu - pu) / ns, fabs(nT - pT) / nT);
+            pu = lu;
+            pT = lT;
+            lu = nu;
+            lT = nT;
+            if (delta <= (R)P.tol) {
+                conv = true;
+                break;
+            }
+            if (have_pp && delta2 <= R(1e-2) * delta) break;
+            have_pp = true;
+        }
+        if (it > P.max_iter) it = P.max_iter;
+        cnt.iters = (unsigned long long)it;
+        cnt.itmax = (unsigned long long)it;
+        cnt.nonconv = conv ? 0ull : 1ull;
+        // collision in frame (fu, fT): p <- p + 2 beta (p_eq - p), p_eq = rho (f), g_eq (g)
+        R sf, inv_sf;
+        frame_scale(fT, sf, inv_sf);
+        R mf[4], mg[4];
+        moments_1d(pa, mf, 4);
+        moments_1d(ga, mg, 3);
+        const double rho = (double)mf[0];
+        const double eps = dt * rho * (double)fT / P.mu;
+        const R b2 = (R)(2.0 * eps / (2.0 + eps));
+        const R geq = (R)((P.Cv - 0.5) * rho * (double)fT);
+        // moments of the equilibria in their own frame: rho (1, 0, 1, 0), g_eq (1, 0, 1)
+        mf[1] = mf[1] - b2 * mf[1];
+        mf[2] = fma(b2, (R)rho - mf[2], mf[2]);
+        mf[3] = mf[3] - b2 * mf[3];
+        mg[0] = fma(b2, geq - mg[0], mg[0]);
+        mg[1] = mg[1] - b2 * mg[1];
+        mg[2] = fma(b2, geq - mg[2], mg[2]);
+        // conserved variables of the new state and its coefficients in the new co-moving frame
+        const double su = (double)sf, uu = (double)fu;
+        double Un[3];
+        Un[0] = (double)mf[0];
+        Un[1] = uu * Un[0] + su * (double)mf[1];
+        Un[2] = 0.5 * (su * su * (double)mf[2] + 2.0 * su * uu * (double)mf[1] + uu * uu * Un[0]) + (double)mg[0];
+        const int64_t n = P.ncell;
+        const double irn = 1.0 / Un[0];
+        const double un = Un[1] * irn;
+        const double Tn = (Un[2] * irn - 0.5 * un * un) / P.Cv;
+        const bool ok = (Un[0] > 0.0) && (Tn > 0.0) && isfinite(Tn);
+        if (!ok) {
+            atomicOr(S.err, ERR_NONPHYS);
+            atomicOr(S.inst_err + k, 1);
+        }
+        const double sn = sqrt(fabs(Tn)), isn = 1.0 / sn;
+        const R r = (R)(su * isn), dxs = (R)((uu - un) * isn);
+        R hh[4];
+        shift_1d(mf, r, dxs, 4);
+        mf[0] = (R)Un[0];
+        mu2h_1d(mf, hh);
+        S.H2[c] = hh[2];
+        S.H2[n + c] = hh[3];
+        shift_1d(mg, r, dxs, 3);
+        mg[3] = R(0);
+        mu2h_1d(mg, hh);
+        S.H2[2 * n + c] = hh[1];
+        S.H2[3 * n + c] = hh[2];
+        for (int q = 0; q < 3; ++q) S.U2[q * n + c] = Un[q];
+        const double rate = ok ? (fabs(un) + sn * CMAX) / dxc : 0.0;
+        bits = (unsigned long long)__double_as_longlong(rate);
+    } else if (active) {
+        // a frozen or finished tube keeps its state
+        const int64_t n = P.ncell;
+        for (int q = 0; q < 4; ++q) S.H2[q * n + c] = S.H[q * n + c];
+        for (int q = 0; q < 3; ++q) S.U2[q * n + c] = S.U[q * n + c];
+    }
+    vmax_update<R>(P, S, slot ^ 1, k, work, bits);
+    stat_add4(S.stats, ST_FACES, work ? 1u : 0u, ST_NONCONV, (unsigned)cnt.nonconv, ST_CELLS, work ? 1u : 0u,
+              ST_CONV_CELLS, (work && conv) ? 1u : 0u);
+    stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+    stat_add32(S.stats, ST_DEPOUT, (unsigned)cnt.depout);
+    stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
+    if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// the staged state becomes the current one
+template <typename R>
+__global__ void sl_commit_kernel(Params P, State<R> S)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.ncell;
+    if (c >= n) return;
+    for (int q = 0; q < 4; ++q) S.H[q * n + c] = S.H2[q * n + c];
+    for (int q = 0; q < 3; ++q) S.U[q * n + c] = S.U2[q * n + c];
 }
 
 // The tail work (blocks [0, 2 * TAIL_BLOCKS): TAIL_BLOCKS per axis) beside the update of

@@ -22,6 +22,7 @@ PRECISION = {"fp64": 0, "mixed": 1}
 SEED = {"prev": 0, "mlp": 1}
 FLAG_STRICT = 1
 FLAG_REG_EQ = 2
+FLAG_SEMI_LAGRANGIAN = 4
 
 
 class PondError(RuntimeError):
@@ -197,7 +198,8 @@ def make_config(cfg: dict, precision="fp64", seed="prev", strict=False) -> tuple
     c.max_iter = int(cfg["max_iter"])
     c.precision = PRECISION[precision]
     c.seed_mode = SEED[seed]
-    c.flags = (FLAG_STRICT if strict else 0) | (FLAG_REG_EQ if cfg.get("regularization", "grad") == "eq" else 0)
+    c.flags = ((FLAG_STRICT if strict else 0) | (FLAG_REG_EQ if cfg.get("regularization", "grad") == "eq" else 0)
+               | (FLAG_SEMI_LAGRANGIAN if cfg.get("scheme", "fv") == "sl" else 0))
     z = [[0.0] * 4] * 4
     for k in range(4):
         c.bc[k] = BC[cfg["bc"][k]]
