@@ -154,6 +154,7 @@ def other_workload(args):
     out = {}
     for prec, tol in (("mixed", W.TOL_FP32), ("fp64", W.TOL_FP64)):
         cfg, fields = make(tol)
+        cfg["scheme"] = args.scheme
         ctx = pond.Context(cfg, fields, precision=prec)
         if args.warmup:
             ctx.step(args.warmup, check=False)
@@ -173,7 +174,7 @@ def other_workload(args):
                      "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
                                    "cell": kt["cell"]}, "tiles": list(ctx.tiles())}
         ctx.close()
-        if name == "tubes":
+        if name == "tubes" and args.scheme == "fv":
             # the same steps with the resident kernel (one block per tube, every step in one
             # launch; the same bits), without per-kernel timing
             ctx = pond.Context(cfg, fields, precision=prec)
@@ -192,10 +193,11 @@ def other_workload(args):
     if not args.no_cpu_baseline:
         if name == "tubes":
             cfg, fields = make(W.TOL_FP64)
+            cfg["scheme"] = args.scheme
             t0 = time.perf_counter()
             cells, k = 0, 0
             while time.perf_counter() - t0 < 15.0 and k < len(cfg["lengths"]):
-                c = W.tube_config(cfg, k)
+                c = dict(W.tube_config(cfg, k), scheme=args.scheme)
                 ff = W.tube_fields(cfg, fields, k)
                 sim = oracle.Sim(c, ff["rho"], ff["ux"], None, ff["p"])
                 for _ in range(16):
@@ -227,7 +229,7 @@ def other_workload(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": {"shocked_interface": "shocked_interface_2048x512", "jet": "jet_2048x2048",
-                                "tubes": "tube_batch_4096"}[name],
+                                "tubes": "tube_batch_4096"}[name], "scheme": args.scheme,
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
         "roofline": None, "mixed": m, "fp64_plain": out["fp64"], "cpu_baseline": cpu,
     }
@@ -271,6 +273,7 @@ def riemann_workload(args):
         cases[name] = {"cells": nx, "t_end": t_end}
         for prec, tol in (("mixed", W.TOL_FP32), ("fp64", W.TOL_FP64)):
             cfg, fields = W.riemann_case(name, tol=tol)
+            cfg["scheme"] = args.scheme
             ctx = pond.Context(cfg, fields, precision=prec)
             n, status = 0, pond.OK
             while ctx.time()[0] < t_end * (1 - 1e-12) and status == pond.OK:
@@ -283,7 +286,7 @@ def riemann_workload(args):
                 cases[name][prec] = r
                 continue
             trial = {}
-            for mode in ("graph", "resident"):
+            for mode in ("graph", "resident") if args.scheme == "fv" else ("graph",):
                 ctx = pond.Context(cfg, fields, precision=prec)
                 launch_mode(ctx, mode)
                 torch.cuda.synchronize()
@@ -318,6 +321,7 @@ def riemann_workload(args):
         cells, el = 0, 0.0
         for name in W.RIEMANN_CASES:
             cfg, fields = W.riemann_case(name, tol=W.TOL_FP64)
+            cfg["scheme"] = args.scheme
             sim = oracle.Sim(cfg, fields["rho"], fields["ux"], None, fields["p"])
             t0 = time.perf_counter()
             k = 0
@@ -337,7 +341,7 @@ def riemann_workload(args):
                                                            if "ms" in c["mixed"])),
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
-        "config": {"workload": "riemann_1d_printed_problems", "lattice": "D1Q4",
+        "config": {"workload": "riemann_1d_printed_problems", "lattice": "D1Q4", "scheme": args.scheme,
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain",
                    "cfl": 0.2},
         "roofline": None, "fp64_plain": {"value": tot["fp64"][0] / tot["fp64"][1] / 1e6},
@@ -362,6 +366,9 @@ def main():
     ap.add_argument("--workload", default="double_mach",
                     choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
+    ap.add_argument("--scheme", choices=["fv", "sl"], default="fv",
+                    help="1D workloads (tubes, riemann_1d): the finite-volume scheme or the "
+                         "semi-Lagrangian realization (Sec. III.A)")
     ap.add_argument("--regularization", choices=["grad", "eq"], default="grad",
                     help="transformation of the f populations between frames: third-order Grad "
                          "projection (the paper's choice) or the alternative with the fast moments "
@@ -393,6 +400,10 @@ def main():
         torch.cuda.synchronize()
         print(json.dumps({"copy_bytes_read": 4 * n, "copy_bytes_written": 4 * n, "copies": 5}))
         return
+    if args.scheme == "sl" and args.workload not in ("tubes", "riemann_1d"):
+        print("the semi-Lagrangian scheme is built in 1D only (--workload tubes or riemann_1d)",
+              file=sys.stderr)
+        sys.exit(2)
     if args.workload == "riemann_1d":
         riemann_workload(args)
         return
