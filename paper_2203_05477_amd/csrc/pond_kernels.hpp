@@ -2297,6 +2297,10 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
     vmax_update<R>(P, S, 0, k, c < n, bits);
     if (c < n && S.tblock) S.tblock[c] = 0;
     if (c < P.nface) {
+        // no seed yet (T < 0); the velocity planes are cleared so that a read-out of the face
+        // frames is defined before any face step (the semi-Lagrangian scheme has none)
+        S.F[c] = R(0);
+        if (D == 2) S.F[P.nface + c] = R(0);
         S.F[(D == 1 ? 1 : 2) * P.nface + c] = R(-1);
         S.fiter[c] = 0; // read by the learned seed's selection before the first step
     }

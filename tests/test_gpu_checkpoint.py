@@ -9,7 +9,7 @@ from paper_2203_05477_amd import workloads as W
 pytestmark = pytest.mark.gpu
 
 
-@pytest.mark.parametrize("case", ["dmr_mixed", "dmr_fp64", "tubes_fp64"])
+@pytest.mark.parametrize("case", ["dmr_mixed", "dmr_fp64", "tubes_fp64", "dmr_eq_fp64", "tubes_sl_fp64"])
 def test_resume_is_bitwise(tmp_path, case):
     from paper_2203_05477_amd import pond
 
@@ -17,6 +17,10 @@ def test_resume_is_bitwise(tmp_path, case):
         cfg, f = W.double_mach(96, 24, tol=1e-5 if case.endswith("mixed") else 1e-10)
     else:
         cfg, f = W.tube_batch(n_tubes=40, len_lo=20, len_hi=200, tol=1e-10)
+    if "_eq_" in case:
+        cfg["regularization"] = "eq"
+    if "_sl_" in case:
+        cfg["scheme"] = "sl"
     prec = "mixed" if case.endswith("mixed") else "fp64"
     a = pond.Context(cfg, f, precision=prec)
     a.step(11, check=False)

@@ -11,14 +11,15 @@ pytestmark = pytest.mark.gpu
 
 
 def _same(a, b):
-    return all(np.array_equal(x, y) for x, y in zip(a, b))
+    # a tube that failed holds the same invalid values on both sides
+    return all(np.array_equal(x, y, equal_nan=True) for x, y in zip(a, b))
 
 
 def _state(g):
     return g.conserved(), g.face_frames(), g.time()
 
 
-@pytest.mark.parametrize("case", ["dmr_fp64", "dmr_mixed", "tubes_mixed"])
+@pytest.mark.parametrize("case", ["dmr_fp64", "dmr_mixed", "tubes_mixed", "dmr_eq_mixed", "tubes_sl_fp64"])
 def test_graph_replay_matches_eager(case):
     from paper_2203_05477_amd import pond
 
@@ -27,6 +28,10 @@ def test_graph_replay_matches_eager(case):
     else:
         cfg, f = W.tube_batch(n_tubes=64, len_lo=50, len_hi=300, tol=1e-5, rho_decades=1.0,
                               p_decades=1.0, mach=1.0)
+    if "_eq_" in case:
+        cfg["regularization"] = "eq"
+    if "_sl_" in case:
+        cfg["scheme"] = "sl"
     prec = "fp64" if case.endswith("fp64") else "mixed"
     eager = pond.Context(cfg, f, precision=prec)
     graph = pond.Context(cfg, f, precision=prec)
@@ -39,8 +44,8 @@ def test_graph_replay_matches_eager(case):
         assert se["iters_total"] == sg["iters_total"] and se["cell_updates"] == sg["cell_updates"]
     # a t_end inside the next steps: the graph is captured again with the clipped last step
     t = eager.time().max()
-    eager.step(10, t_end=t * 1.02)
-    graph.step(10, t_end=t * 1.02)
+    eager.step(10, t_end=t * 1.02, check=False)
+    graph.step(10, t_end=t * 1.02, check=False)
     assert _same(_state(eager), _state(graph))
 
 
