@@ -112,6 +112,7 @@ typedef struct {
     int64_t cell_updates;           /* cells advanced, summed over steps               */
     int64_t converged_cell_updates; /* of which every face met tol within max_iter     */
     int64_t faces;                  /* face iterations started, summed over steps      */
+                                    /* (semi-Lagrangian scheme: cell iterations)        */
     int64_t iters_total;            /* frame iterations, summed over faces and steps   */
     int32_t iters_max;              /* largest iteration count of one face             */
     int64_t nonconverged;           /* faces that hit max_iter                         */
@@ -225,9 +226,11 @@ pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
 
 /* Average device time in ms per step of each launch over the last pond_step call,
  * measured with HIP events on the context's stream, into a caller array of 5:
- * out[0] dt/time kernel, out[1] face kernel, out[2] cell update kernel (1D, and 2D
- * without a tail kernel; 0 otherwise), out[3] seed (MLP) kernels, out[4] 2D with a tail
- * kernel: the launch that finishes the deferred faces and updates every cell (0 otherwise).
+ * out[0] dt/time kernel, out[1] face kernel (semi-Lagrangian scheme: its step kernel),
+ * out[2] cell update kernel (1D, and 2D without a tail kernel; 2D with a tail kernel: the
+ * pass over the marked stencil cells; semi-Lagrangian: the commit of the staged state),
+ * out[3] seed (MLP) kernels, out[4] 2D with a tail kernel: the launch that finishes the
+ * deferred faces and updates the other cells (0 otherwise).
  * Timing is recorded only after pond_enable_timing(ctx, 1). */
 pond_status pond_enable_timing(pond_ctx *ctx, int32_t on);
 pond_status pond_kernel_times(const pond_ctx *ctx, double *out);
