@@ -149,6 +149,8 @@ def other_workload(args):
         make = lambda tol: W.shocked_interface(tol=tol)
     elif name == "jet":
         make = lambda tol: W.jet(tol=tol)
+    elif name == "explosion_box":
+        make = lambda tol: W.explosion_box(tol=tol)
     else:
         make = lambda tol: W.tube_batch(tol=tol)
     out = {}
@@ -229,7 +231,8 @@ def other_workload(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": {"shocked_interface": "shocked_interface_2048x512", "jet": "jet_2048x2048",
-                                "tubes": "tube_batch_4096"}[name], "scheme": args.scheme,
+                                "tubes": "tube_batch_4096", "explosion_box": "explosion_box_256x256"}[name],
+                   "scheme": args.scheme,
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
         "roofline": None, "mixed": m, "fp64_plain": out["fp64"], "cpu_baseline": cpu,
     }
@@ -364,7 +367,8 @@ def main():
     ap.add_argument("--tiles", type=str, default=None,
                     help="face tile BXxBY for both forms instead of the autotuner's choice")
     ap.add_argument("--workload", default="double_mach",
-                    choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d"],
+                    choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d",
+                             "explosion_box"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
     ap.add_argument("--scheme", choices=["fv", "sl"], default="fv",
                     help="1D workloads (tubes, riemann_1d): the finite-volume scheme or the "

@@ -119,6 +119,19 @@ def rankine_hugoniot(rho1, p1, mach, gamma):
     return rho2, p2, du
 
 
+def explosion_box(n=256, cfl=0.2, mu=1e-3, tol=TOL_PARITY, max_iter=32):
+    """Explosion in a closed box (Sec. IV.C): [0,1]^2, n x n cells (the paper's 256),
+    reflecting walls; (rho, u, p) = (5, 0, 5) inside the circle of radius 0.3 around
+    (0.4, 0.4) (cell-centre test), (1, 0, 1) outside; gamma 1.4; run to t = 0.5."""
+    cfg = base_config(2, n, n, cfl=cfl, mu=mu, tol=tol, max_iter=max_iter, bc=("reflect",) * 4)
+    x, y = cell_centres(cfg)
+    inside = (x - 0.4) ** 2 + (y - 0.4) ** 2 < 0.3 ** 2
+    cfg["name"] = "explosion_box"
+    cfg["t_end"] = 0.5
+    v = np.where(inside, 5.0, 1.0)
+    return cfg, {"rho": v.copy(), "ux": np.zeros(v.size), "uy": np.zeros(v.size), "p": v.copy()}
+
+
 def double_mach(nx=1920, ny=480, mach=10.0, gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL_PARITY,
                 max_iter=32):
     """Mach-10 shock meeting a 30 degree wall (Sec. IV.C.4): [0,4]x[0,1]; shock through

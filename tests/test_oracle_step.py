@@ -220,3 +220,25 @@ def test_time_step_includes_the_prescribed_boundary_states(orc):
     s = _sim(orc, cfg, f)
     s.step()
     assert s.last["dt"] == pytest.approx(0.2 / 8 / (0.3 + math.sqrt(0.7) * cmax), rel=1e-14)
+
+
+def test_explosion_box_setup_and_invariants(orc):
+    """Explosion in a box (Sec. IV.C.2): the set-up takes the printed states, and in the
+    closed reflecting box mass and energy are exact while the state keeps its symmetry
+    about the diagonal x = y (the circle is centred on it)."""
+    g = read_golden()
+    cfg, f = W.explosion_box(32)
+    inside = [float(t) for t in g["explosion_box_inside"]]
+    outside = [float(t) for t in g["explosion_box_outside"]]
+    k_in, k_out = int(np.argmax(f["rho"])), int(np.argmin(f["rho"]))
+    assert [f[q][k_in] for q in ("rho", "ux", "uy", "p")] == inside
+    assert [f[q][k_out] for q in ("rho", "ux", "uy", "p")] == outside
+    s = _sim(orc, cfg, f)
+    U0 = s.conserved().sum(axis=1)
+    for _ in range(20):
+        s.step()
+    U1 = s.conserved().sum(axis=1)
+    assert abs(U1[0] - U0[0]) <= 1e-13 * U0[0] and abs(U1[3] - U0[3]) <= 1e-13 * U0[3]
+    r, ux, uy, _ = s.fields()
+    tr = lambda a: a.reshape(32, 32).T.ravel()
+    assert np.abs(tr(r) - r).max() < 1e-12 and np.abs(tr(ux) - uy).max() < 1e-12
