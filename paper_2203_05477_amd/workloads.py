@@ -119,6 +119,19 @@ def rankine_hugoniot(rho1, p1, mach, gamma):
     return rho2, p2, du
 
 
+def blast_waves(nx=1600, mu=1e-4, tol=TOL_PARITY, max_iter=32):
+    """Two interacting blast waves (Sec. IV.B): [0,1], reflecting ends, rho = 1, u = 0 and
+    p = 1000 | 0.01 | 100 split at x = 0.1 and 0.9 (cell-centre test), gamma 1.4, CFL 0.2,
+    to t = 0.038 (the paper's 1,600 points). mu = 1e-4: at 1e-5 the 1000 | 0.01 jump is
+    too far past the Euler limit at the first step (as for the strong shock tube)."""
+    cfg = base_config(1, nx, cfl=0.2, mu=mu, tol=tol, max_iter=max_iter, bc=("reflect",) * 4)
+    x, _ = cell_centres(cfg)
+    cfg["name"] = "blast_waves"
+    cfg["t_end"] = 0.038
+    p = np.where(x < 0.1, 1000.0, np.where(x < 0.9, 0.01, 100.0))
+    return cfg, {"rho": np.ones(nx), "ux": np.zeros(nx), "uy": None, "p": p}
+
+
 def explosion_box(n=256, cfl=0.2, mu=1e-3, tol=TOL_PARITY, max_iter=32):
     """Explosion in a closed box (Sec. IV.C): [0,1]^2, n x n cells (the paper's 256),
     reflecting walls; (rho, u, p) = (5, 0, 5) inside the circle of radius 0.3 around
