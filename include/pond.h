@@ -217,7 +217,7 @@ pond_status pond_set_resident(pond_ctx *ctx, int32_t on);
  * iterations; faces still iterating then continue, from the same state, in a tail kernel
  * that gives every face 16 lanes instead of one (a wave otherwise runs as long as its
  * slowest face). Results are those of the same iteration (rounding order aside).
- * k = 0 runs every face to the end in the face kernel. Default 3 (FP64) or 2 (mixed).
+ * k = 0 runs every face to the end in the face kernel. Default 4 (FP64) or 2 (mixed).
  * The tail sums its moments in another order than the face kernel, so different k
  * give results that differ by rounding (tile shapes do not change results at all);
  * pond_autotune therefore leaves k alone. Ignored in 1D.

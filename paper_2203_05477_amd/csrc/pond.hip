@@ -607,7 +607,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         alloc(&c->tail_s, c->rsize * 6 * P.tail_n);
         alloc((void **)&c->tail_count, sizeof(int) * 2 * NSLOT);
         alloc((void **)&c->tblock, sizeof(int) * n);
-        P.iter_split = (cfg->precision == POND_FP64) ? 3 : 2;
+        P.iter_split = (cfg->precision == POND_FP64) ? 4 : 2;
     }
     if (!ok) {
         free_all(c);
