@@ -207,13 +207,14 @@ def shocked_interface(nx=2048, ny=512, mach=2.0, density_ratio=3.0, amplitude=0.
 
 
 def jet(nx=2048, ny=2048, gamma=5.0 / 3.0, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_iter=32,
-        width=0.1, speed=30.0):
-    """Mach-80 jet (Sec. IV.C.5): [0,1]x[-0.5,0.5]; ambient (0.5, 0, 0, 0.4127); left
-    boundary fixed jet (5, speed = 30, 0, 0.4127) for |y| <= width/2, fixed ambient
-    elsewhere; other sides outflow; gamma 5/3."""
+        width=0.1, speed=30.0, x1=1.0):
+    """Mach-80 jet (Sec. IV.C.5): [0,x1]x[-0.5,0.5] (the paper's domain has x1 = 2 on
+    [1000,500] cells; x1 = 1 keeps square cells on a square grid); ambient (0.5, 0, 0,
+    0.4127); left boundary fixed jet (5, speed = 30, 0, 0.4127) for |y| <= width/2, fixed
+    ambient elsewhere; other sides outflow; gamma 5/3."""
     amb = [0.5, 0.0, 0.0, 0.4127]
     jet_state = [5.0, float(speed), 0.0, 0.4127]
-    cfg = base_config(2, nx, ny, 0.0, 1.0, -0.5, 0.5, gamma=gamma, cfl=cfl, mu=mu, tol=tol,
+    cfg = base_config(2, nx, ny, 0.0, x1, -0.5, 0.5, gamma=gamma, cfl=cfl, mu=mu, tol=tol,
                       max_iter=max_iter, bc=("fixed_window", "outflow", "outflow", "outflow"))
     cfg["bc_state"][0] = list(amb)
     cfg["bc_alt"][0] = list(jet_state)

@@ -82,14 +82,17 @@ def test_conservation_with_exact_boundary_fluxes(orc, name):
     assert np.all(np.abs(U1 - pred) <= 1e-11 * scale), (U1 - pred) / scale
 
 
-def test_double_rarefaction_opens_a_vacuum_the_step_cannot_hold(orc):
-    """The printed double rarefaction (p = 0.1 on both sides, u = -2 | 2) opens a true
-    vacuum: 2 (c_L + c_R)/(gamma - 1) < u_R - u_L. The two centre cells then drain in a few
-    steps while the centre face carries nothing; the step keeps the mirror symmetry exactly
-    (rho even, u odd) but the internal energy next to the centre turns negative within ten
-    steps with the Van Leer limiter and within a hundred with minmod, at every resolution.
-    This is the documented failure of the case: nothing in the method keeps the internal
-    energy positive."""
+def test_double_rarefaction_symmetric_up_to_known_departure(orc):
+    """KNOWN DEPARTURE from Sec. IV.B: the paper reports the printed double rarefaction
+    (p = 0.1 on both sides, u = -2 | 2) in good agreement with the exact solution at
+    t = 0.1 on 800 cells; under the readings of this build the step cannot hold it (every
+    reading tried is listed in the design notes with its failing step). This test pins how
+    the case departs, not what the paper shows: the exact solution opens a true vacuum
+    (2 (c_L + c_R)/(gamma - 1) < u_R - u_L); the step keeps the mirror symmetry exactly
+    (rho even, u odd) while the two centre cells drain, and the internal energy next to the
+    centre turns negative within ten steps with the Van Leer limiter and within a hundred
+    with minmod. The paper's outcome is asserted, as an expected failure, by
+    test_double_rarefaction_reaches_the_printed_time."""
     left, right, _, _, g = W.RIEMANN_CASES["double_rarefaction"][:5]
     cl, cr = (np.sqrt(g * s[2] / s[0]) for s in (left, right))
     assert 2.0 * (cl + cr) / (g - 1.0) < right[1] - left[1]
@@ -111,6 +114,26 @@ def test_double_rarefaction_opens_a_vacuum_the_step_cannot_hold(orc):
             print("double rarefaction", nx, lim, "T <= 0 at step", failed, "cell", k)
             assert failed is not None and (lim == "minmod" or failed <= 10)
             assert abs(k + 0.5 - nx / 2) <= 4
+
+
+@pytest.mark.xfail(strict=True, reason="known departure from Sec. IV.B: the double rarefaction "
+                   "loses positivity next to the centre under every reading tried")
+def test_double_rarefaction_reaches_the_printed_time(orc):
+    """The paper's outcome (Sec. IV.B): the run reaches t = 0.1 on 200 cells with positive
+    density and temperature everywhere, and its density is within 10% (relative L1) of the
+    exact solution. Expected to fail under this build's readings."""
+    from exact_riemann import sample
+
+    cfg, f = W.riemann_case("double_rarefaction", nx=200, tol=1e-10)
+    s = orc.Sim(cfg, f["rho"], f["ux"], None, f["p"])
+    while s.t < cfg["t_end"] * (1 - 1e-12):
+        s.step(cfg["t_end"])
+        r, _, _, T = s.fields()
+        assert r.min() > 0 and T.min() > 0, f"T <= 0 at step {s.steps}"
+    left, right, xi, _, g = W.RIEMANN_CASES["double_rarefaction"][:5]
+    x = (np.arange(cfg["nx"]) + 0.5) / cfg["nx"]
+    rex = sample(left, right, g, (x - xi) / s.t)[0]
+    assert np.abs(r - rex).sum() <= 0.1 * np.abs(rex).sum()
 
 
 def test_blast_waves_closed_tube_invariants(orc):
