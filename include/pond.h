@@ -32,7 +32,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 2
+#define POND_ABI_VERSION 3
 
 typedef enum {
     POND_OK = 0,
@@ -123,6 +123,19 @@ typedef struct {
     int32_t failed_instances;       /* instances frozen after producing an invalid cell */
     int64_t tail_faces;             /* 2D: faces finished by the tail kernel           */
     int64_t tail_iters;             /* 2D: iterations run by the tail kernel           */
+    /* the state after the call (Sec. II.B definitions: rho, T = (E - u^2/2)/C_v from the
+     * conserved variables), from one extra pass over cells and faces: */
+    double rho_min;                 /* smallest cell density                           */
+    double T_min;                   /* smallest cell temperature                       */
+    double totals[4];               /* sum over all cells of the conserved variables   */
+                                    /* times the cell volume: mass, momentum (dim       */
+                                    /* values), energy; unused entries 0                */
+    int32_t first_failed_instance;  /* lowest instance that failed in this call, or -1 */
+    int64_t first_failed_cell;      /* lowest cell index (x fastest, tubes concatenated) */
+                                    /* holding rho <= 0, T <= 0 or a non-finite value,  */
+                                    /* or -1                                            */
+    int64_t first_nonconv_face;     /* lowest face index whose iteration in the last   */
+                                    /* step did not converge (see pond_face_iters), -1 */
 } pond_stats;
 
 typedef struct pond_ctx pond_ctx;
@@ -134,59 +147,71 @@ typedef struct pond_ctx pond_ctx;
 pond_status pond_init(const pond_config *cfg, const double *rho, const double *ux,
                       const double *uy, const double *p, pond_ctx **out);
 
-/* Advance every instance by up to nsteps steps, each with dt = cfl / max rate of its
- * cells (Sec. IV), the last one clipped so that no instance passes t_end (pass
- * INFINITY for a fixed step count). st (may be NULL) receives the counters of this
- * call. Returns POND_OK, or the first error found (POND_ENONPHYS after a step that
- * produced an invalid cell; POND_ECFL; POND_ENOCONV only with POND_FLAG_STRICT).
+/* Advance every instance by up to nsteps steps of Sec. III.B.4, each with dt = cfl / max
+ * rate of its cells (Sec. IV), the last one clipped so that no instance passes t_end (pass
+ * INFINITY for a fixed step count). st (may be NULL) receives the counters of this call and
+ * the summary of the state after it (one extra pass over cells and faces, skipped when st
+ * is NULL). Returns POND_OK, or the first error found in this call (POND_ENONPHYS if one of
+ * its steps produced an invalid cell; POND_ECFL and POND_ENOCONV only with
+ * POND_FLAG_STRICT); an instance that failed in an earlier call stays frozen and is
+ * counted in st->failed_instances, but does not make later calls fail.
  * The call is asynchronous on the context's stream except for the counter read-back. */
 pond_status pond_step(pond_ctx *ctx, int32_t nsteps, double t_end, pond_stats *st);
 
-/* Cell fields rho, ux, uy, T (host arrays of nx*ny; uy may be NULL) computed from the
- * conserved variables. Synchronizes the stream. */
+/* Cell fields rho, ux, uy, T computed from the conserved variables (Sec. II.B: u = rho u /
+ * rho, T = (E - u^2/2) / C_v); host arrays of nx*ny; uy may be NULL. Synchronizes the
+ * stream. */
 pond_status pond_moments(const pond_ctx *ctx, double *rho, double *ux, double *uy, double *T);
 
-/* Same fields written to a caller-owned device buffer of 4*nx*ny doubles (planes rho,
- * ux, uy, T) on the context's stream; does not synchronize. */
+/* Same fields (Sec. II.B) written to a caller-owned device buffer of 4*nx*ny doubles
+ * (planes rho, ux, uy, T) on the context's stream; does not synchronize. */
 pond_status pond_moments_device(const pond_ctx *ctx, double *dev_out);
 
-/* Conserved variables (rho, rho u_x[, rho u_y], rho E): (dim+2) planes of nx*ny. */
+/* Conserved variables (rho, rho u_x[, rho u_y], rho E) of Sec. II.B, the moments the
+ * finite-volume update of Sec. III.B.2 conserves: (dim+2) planes of nx*ny. */
 pond_status pond_conserved(const pond_ctx *ctx, double *U);
 
-/* Populations f~, g~ (Q planes of nx*ny each, Q = 4^dim) and their frames ((dim+1)
+/* Populations f~, g~ (the carried variables of Sec. III.B.1, in the Grad form of
+ * Sec. II.C; Q planes of nx*ny each, Q = 4^dim) and their frames ((dim+1)
  * planes: u..., T) as the next step starts from them: in each cell's co-moving frame. */
 pond_status pond_populations(const pond_ctx *ctx, double *f, double *g, double *frame);
 
-/* Number of faces: 1D: nx + n_inst; 2D: (nx+1)*ny x-faces followed by nx*(ny+1) y-faces
- * (x-face (i,j) lies between cells (i-1,j) and (i,j); y-face (i,j) between (i,j-1), (i,j)). */
+/* Number of faces x_b (the cell interfaces of Sec. III.B.3): 1D: nx + n_inst; 2D: (nx+1)*ny
+ * x-faces followed by nx*(ny+1) y-faces (x-face (i,j) lies between cells (i-1,j) and (i,j);
+ * y-face (i,j) between (i,j-1), (i,j)). */
 int64_t pond_nfaces(const pond_ctx *ctx);
 
-/* Face frames of the last step ((dim+1) values per face: u..., T) = the seeds of the
- * next step's predictor. Host array of pond_nfaces*(dim+1). Before the first step
- * every T is -1 (no seed yet). */
+/* Face frames lambda_b of the last step (Sec. III.B.3; (dim+1) values per face: u..., T)
+ * = the seeds of the next step's predictor. Host array of pond_nfaces*(dim+1). Before the
+ * first step every T is -1 (no seed yet). */
 pond_status pond_face_frames(const pond_ctx *ctx, double *out);
-/* Replace the seeds (same layout). T <= 0 marks a face as unseeded. */
+/* Replace the seeds, the predictor frames lambda_0 of Sec. III.B.3 (same layout). T <= 0
+ * marks a face as unseeded. */
 pond_status pond_set_face_frames(pond_ctx *ctx, const double *in);
-/* Lab-frame moments of the face populations phi(x_b, t+dt/2) of the last step:
+/* Lab-frame moments of the face populations phi(x_b, t+dt/2) of the last step (Sec.
+ * III.B.3, after the recovery from phi-bar with the face equilibrium):
  * f: 1+d+d^2+d^3 values (M0, M1, M2, M3 row-major), g: 1+d+d^2 values, per face. */
 pond_status pond_face_moments(const pond_ctx *ctx, double *Mf, double *Mg);
-/* Iteration count per face of the last step (negative: not converged). */
+/* Iteration count of the predictor-corrector loop of Sec. III.B.3 per face of the last
+ * step (negative: not converged; the face then took the first-order fallback state). */
 pond_status pond_face_iters(const pond_ctx *ctx, int32_t *out);
 
-/* Per instance: nonzero once one of its steps produced a cell with rho <= 0, T <= 0 or a
+/* Per instance (the step of Sec. III.B.4 has no failure handling; this is the library's):
+ * nonzero once one of its steps produced a cell with rho <= 0, T <= 0 or a
  * non-finite value. Such an instance is frozen (its later steps have dt = 0) while the
  * other instances go on; pond_step reports POND_ENONPHYS for the call in which it failed. */
 pond_status pond_failed_instances(const pond_ctx *ctx, int32_t *flags);
 
-/* Time of each instance (host array of n_inst). */
+/* Time of each instance, the sum of its time steps (Sec. IV; host array of n_inst). */
 pond_status pond_time(const pond_ctx *ctx, double *t);
 
-/* Make the context issue its work on a caller's HIP stream (hipStream_t passed as
+/* Launch control (changes where the work of Sec. III.B.4 runs, not what it computes).
+ * Make the context issue its work on a caller's HIP stream (hipStream_t passed as
  * void*; NULL = the context's own stream). The stream must outlive the context or
  * be replaced before it is destroyed. */
 pond_status pond_set_stream(pond_ctx *ctx, void *hip_stream);
 
-/* Launch shapes. 1D: face_block threads per block (64, 128, 192 or 256; by = 1). 2D: face
+/* Launch control (results of Sec. III.B.4 unchanged). Launch shapes. 1D: face_block threads per block (64, 128, 192 or 256; by = 1). 2D: face
  * tile bx x by threads, a multiple of 64 and at most 256. cell_block: threads per block of
  * the cell update (64 to 256, a multiple of 64). Other shapes give POND_EINVAL.
  * Any shape gives bitwise-identical results. pond_autotune times the candidates on
@@ -195,13 +220,14 @@ pond_status pond_set_tiles(pond_ctx *ctx, int32_t bx, int32_t by, int32_t cell_b
 pond_status pond_get_tiles(const pond_ctx *ctx, int32_t *bx, int32_t *by, int32_t *cell_block);
 pond_status pond_autotune(pond_ctx *ctx);
 
-/* on != 0: pond_step replays two steps captured once as a HIP graph (kernel launches
+/* Launch control (results of Sec. III.B.4 unchanged). on != 0: pond_step replays two steps captured once as a HIP graph (kernel launches
  * only; captured again when t_end, the step parity or any launch parameter changes)
  * instead of launching every kernel; results are identical. Steps with timing enabled,
  * and the last step of an odd count, are launched one by one. Default off. */
 pond_status pond_set_graph(pond_ctx *ctx, int32_t on);
 
-/* 1D only: on != 0 runs all the steps of each pond_step call in a single launch, one
+/* Launch control (results of Sec. III.B.4 unchanged). 1D only: on != 0 runs all the steps
+ * of each pond_step call in a single launch, one
  * block per tube, longest tubes first (256 threads for a batch of 256 tubes or more,
  * otherwise 1,024 in mixed precision and 512 in FP64); each
  * block advances its tube step by step (the step of Sec. III.B.4 with the tube's own dt),
@@ -224,7 +250,8 @@ pond_status pond_set_resident(pond_ctx *ctx, int32_t on);
  * POND_EINVAL for k < 0. */
 pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
 
-/* Average device time in ms per step of each launch over the last pond_step call,
+/* Measurement (no effect on results). Average device time in ms per step of each launch
+ * over the last pond_step call,
  * measured with HIP events on the context's stream, into a caller array of 5:
  * out[0] dt/time kernel, out[1] face kernel (semi-Lagrangian scheme: its step kernel),
  * out[2] cell update kernel (1D, and 2D without a tail kernel; 2D with a tail kernel: the
@@ -289,7 +316,8 @@ pond_status pond_mlp_targets(pond_ctx *ctx, const float *dev_X, const float *dev
 /* Attach a copy of the network to a context whose seed_mode is POND_SEED_MLP. */
 pond_status pond_load_mlp(pond_ctx *ctx, const pond_mlp *m, int32_t hard_iters);
 
-/* Checkpoint (a warm start of a long run): pond_save writes the carried state -- conserved
+/* Checkpoint of the state carried between steps of Sec. III.B.4 (a warm start of a long
+ * run): pond_save writes the carried state -- conserved
  * variables, non-equilibrium coefficients, face states and seeds, iteration flags, clocks
  * and time steps, the CFL maxima, failed-instance flags, step parity and count, and the
  * tail hand-over point -- to a binary file at `path` (overwritten). pond_load reads such a
@@ -301,6 +329,8 @@ pond_status pond_load_mlp(pond_ctx *ctx, const pond_mlp *m, int32_t hard_iters);
 pond_status pond_save(pond_ctx *ctx, const char *path);
 pond_status pond_load(pond_ctx *ctx, const char *path);
 
+/* Housekeeping: release a context (NULL is ignored); the text of a status; the ABI version
+ * this library implements (POND_ABI_VERSION of the header it was built with). */
 void pond_free(pond_ctx *ctx);
 const char *pond_strerror(pond_status s);
 int32_t pond_abi_version(void);

@@ -43,6 +43,7 @@ struct pond_ctx {
     void *tail_s = nullptr;
     // host mirrors
     std::vector<int64_t> h_cell_off;
+    std::vector<int> h_failed; // failed-instance flags at the end of the last pond_step call
     int tube_span = 0;
     int slot = 0;
     int64_t steps_done = 0;
@@ -674,7 +675,10 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
 {
     if (!c || nsteps < 0) return POND_EINVAL;
     if (c->cfg.seed_mode == POND_SEED_MLP && !c->mlp.ready) return POND_ESTATE;
+    // counters and error flags describe this call only (frozen instances stay frozen
+    // through inst_err, and their cells are not updated again, so they raise no new flag)
     HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N * NSLOT, c->stream));
+    HIPCHK(hipMemsetAsync(c->err, 0, sizeof(int), c->stream));
     double kt[5] = {0, 0, 0, 0, 0};
     if (c->timing) {
         size_t need = (size_t)6 * std::max(nsteps, 1);
@@ -742,6 +746,19 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
     std::vector<double> ht(c->P.n_inst), hdt(c->P.n_inst);
     HIPCHK(hipMemcpyAsync(ht.data(), c->t, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
     HIPCHK(hipMemcpyAsync(hdt.data(), c->dt, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    std::vector<int> fe(c->P.n_inst);
+    HIPCHK(hipMemcpyAsync(fe.data(), c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost, c->stream));
+    std::vector<double> sum;
+    if (st) {
+        // summary of the state after the call: one record per block of summary_kernel
+        sum.resize((size_t)SUM_BLOCKS * SUM_NV);
+        if (c->D == 1)
+            summary_kernel<1><<<SUM_BLOCKS, 256, 0, c->stream>>>(c->P, c->U, c->fiter, c->dxk, c->cell_inst, c->scratch);
+        else
+            summary_kernel<2><<<SUM_BLOCKS, 256, 0, c->stream>>>(c->P, c->U, c->fiter, c->dxk, c->cell_inst, c->scratch);
+        HIPCHK(hipGetLastError());
+        HIPCHK(hipMemcpyAsync(sum.data(), c->scratch, sizeof(double) * sum.size(), hipMemcpyDeviceToHost, c->stream));
+    }
     HIPCHK(hipStreamSynchronize(c->stream));
     c->steps_done += nsteps;
     unsigned long long hs[ST_N];
@@ -770,10 +787,29 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
         st->t_max = *std::max_element(ht.begin(), ht.end());
         st->dt_min = *std::min_element(hdt.begin(), hdt.end());
         st->dt_max = *std::max_element(hdt.begin(), hdt.end());
-        std::vector<int> fe(c->P.n_inst);
-        HIPCHK(hipMemcpy(fe.data(), c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost));
         st->failed_instances = (int32_t)std::count_if(fe.begin(), fe.end(), [](int v) { return v != 0; });
+        st->first_failed_instance = -1;
+        for (int k = 0; k < c->P.n_inst; ++k)
+            if (fe[k] && !(k < (int)c->h_failed.size() && c->h_failed[k])) {
+                st->first_failed_instance = k;
+                break;
+            }
+        double rmin = INFINITY, tmin = INFINITY, bad = INFINITY, nonc = INFINITY, tot[4] = {0, 0, 0, 0};
+        for (int b = 0; b < SUM_BLOCKS; ++b) {
+            const double *r = &sum[(size_t)b * SUM_NV];
+            rmin = std::fmin(rmin, r[0]);
+            tmin = std::fmin(tmin, r[1]);
+            for (int q = 0; q < 4; ++q) tot[q] += r[2 + q];
+            bad = std::fmin(bad, r[6]);
+            nonc = std::fmin(nonc, r[7]);
+        }
+        st->rho_min = rmin;
+        st->T_min = tmin;
+        for (int q = 0; q < 4; ++q) st->totals[q] = tot[q];
+        st->first_failed_cell = std::isfinite(bad) ? (int64_t)bad : -1;
+        st->first_nonconv_face = std::isfinite(nonc) ? (int64_t)nonc : -1;
     }
+    c->h_failed = fe;
     if (herr & ERR_NONPHYS) return POND_ENONPHYS;
     if ((c->cfg.flags & POND_FLAG_STRICT) && hs[ST_NONCONV]) return POND_ENOCONV;
     if ((c->cfg.flags & POND_FLAG_STRICT) && (herr & ERR_DEPART)) return POND_ECFL;
@@ -904,6 +940,8 @@ pond_status pond_load(pond_ctx *c, const char *path)
     for (size_t k = 0; k < blobs.size(); ++k)
         HIPCHK(hipMemcpyAsync(blobs[k].dev, data[k].data(), blobs[k].bytes, hipMemcpyHostToDevice, c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
+    c->h_failed.assign(c->P.n_inst, 0);
+    HIPCHK(hipMemcpy(c->h_failed.data(), c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost));
     c->slot = h.slot;
     c->P.iter_split = h.iter_split;
     c->steps_done = h.steps_done;
@@ -1143,8 +1181,14 @@ pond_status pond_autotune(pond_ctx *c)
     // face state, which is saved first and restored afterwards (the next step's seeds).
     const size_t fbytes = c->rsize * c->nfp * c->P.nface;
     void *save = nullptr;
-    HIPCHK(hipMalloc(&save, fbytes));
+    const size_t ibytes = sizeof(int) * c->P.nface;
+    HIPCHK(hipMalloc(&save, fbytes + ibytes + sizeof(int)));
+    int *save_iter = reinterpret_cast<int *>(static_cast<char *>(save) + fbytes);
     HIPCHK(hipMemcpyAsync(save, c->F, fbytes, hipMemcpyDeviceToDevice, c->stream));
+    // the iteration counts (read by the learned seed's face selection) and the error flags
+    // are restored as well
+    HIPCHK(hipMemcpyAsync(save_iter, c->fiter, ibytes, hipMemcpyDeviceToDevice, c->stream));
+    HIPCHK(hipMemcpyAsync(save_iter + c->P.nface, c->err, sizeof(int), hipMemcpyDeviceToDevice, c->stream));
     // a dt must exist for the face kernel: run the dt kernel's effect on a copy
     std::vector<std::pair<int, int>> cand;
     if (c->D == 1)
@@ -1198,8 +1242,9 @@ pond_status pond_autotune(pond_ctx *c)
     (void)hipMemcpyAsync(c->t, sdt + c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->tstart, sdt + 2 * c->P.n_inst, sizeof(double) * c->P.n_inst, hipMemcpyDeviceToDevice, c->stream);
     (void)hipMemcpyAsync(c->F, save, fbytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->fiter, save_iter, ibytes, hipMemcpyDeviceToDevice, c->stream);
+    (void)hipMemcpyAsync(c->err, save_iter + c->P.nface, sizeof(int), hipMemcpyDeviceToDevice, c->stream);
     HIPCHK(hipMemsetAsync(c->stats, 0, sizeof(unsigned long long) * ST_N * NSLOT, c->stream));
-    HIPCHK(hipMemsetAsync(c->err, 0, sizeof(int), c->stream));
     HIPCHK(hipStreamSynchronize(c->stream));
     (void)hipFree(sdt);
     (void)hipFree(save);

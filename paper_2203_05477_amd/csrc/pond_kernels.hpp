@@ -2307,6 +2307,56 @@ __global__ void init_kernel(Params P, State<R> S, const double *prim4, int nh)
 }
 
 // rho, ux, uy, T planes from U
+// End-of-call summary of the state for pond_stats: each of SUM_BLOCKS blocks walks a
+// strided share of the cells and faces and writes one record of SUM_NV doubles: smallest
+// density, smallest temperature, the conserved totals (U times the cell volume; dim + 2
+// values, the rest 0), the lowest index of a cell with rho <= 0, T <= 0 or a non-finite
+// value, and the lowest index of a face whose last iteration did not converge (indices as
+// exact doubles, -1 for none). Reductions inside a block run in a fixed tree order and the
+// host combines the records in block order, so the totals are reproducible bit for bit.
+constexpr int SUM_BLOCKS = 256;
+constexpr int SUM_NV = 8;
+
+template <int D>
+__global__ __launch_bounds__(256) void summary_kernel(Params P, const double *U, const int *fiter,
+                                                      const double *dxk, const int *cell_inst, double *out)
+{
+    __shared__ double red[SUM_NV][256];
+    const int tid = threadIdx.x;
+    const int64_t n = P.ncell, stride = (int64_t)SUM_BLOCKS * 256;
+    double rmin = INFINITY, tmin = INFINITY, tot[4] = {0.0, 0.0, 0.0, 0.0};
+    double bad = INFINITY, nonc = INFINITY;
+    const double vol2 = P.dx * P.dy;
+    for (int64_t c = (int64_t)blockIdx.x * 256 + tid; c < n; c += stride) {
+        double rho, u[2], T;
+        prim<D>(U, n, c, rho, u, T, P.Cv);
+        rmin = fmin(rmin, rho);
+        tmin = fmin(tmin, T);
+        const double vol = D == 2 ? vol2 : (dxk ? dxk[cell_inst[c]] : P.dx);
+        for (int q = 0; q < D + 2; ++q) tot[q] += U[q * n + c] * vol;
+        if (!(rho > 0.0 && T > 0.0 && isfinite(rho) && isfinite(T)) && bad == INFINITY) bad = (double)c;
+    }
+    for (int64_t f = (int64_t)blockIdx.x * 256 + tid; f < P.nface; f += stride)
+        if (((fiter[f] >> 16) & 1) && nonc == INFINITY) nonc = (double)f;
+    red[0][tid] = rmin;
+    red[1][tid] = tmin;
+    for (int q = 0; q < 4; ++q) red[2 + q][tid] = tot[q];
+    red[6][tid] = bad;
+    red[7][tid] = nonc;
+    __syncthreads();
+    for (int h = 128; h > 0; h >>= 1) {
+        if (tid < h) {
+            red[0][tid] = fmin(red[0][tid], red[0][tid + h]);
+            red[1][tid] = fmin(red[1][tid], red[1][tid + h]);
+            for (int q = 0; q < 4; ++q) red[2 + q][tid] += red[2 + q][tid + h];
+            red[6][tid] = fmin(red[6][tid], red[6][tid + h]);
+            red[7][tid] = fmin(red[7][tid], red[7][tid + h]);
+        }
+        __syncthreads();
+    }
+    if (tid < SUM_NV) out[(size_t)blockIdx.x * SUM_NV + tid] = red[tid][0];
+}
+
 template <int D>
 __global__ void fields_kernel(int64_t n, const double *U, double Cv, double *out)
 {

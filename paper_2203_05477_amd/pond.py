@@ -58,10 +58,16 @@ class Stats(ctypes.Structure):
         ("dt_min", ctypes.c_double), ("dt_max", ctypes.c_double),
         ("failed_instances", ctypes.c_int32),
         ("tail_faces", ctypes.c_int64), ("tail_iters", ctypes.c_int64),
+        ("rho_min", ctypes.c_double), ("T_min", ctypes.c_double),
+        ("totals", ctypes.c_double * 4),
+        ("first_failed_instance", ctypes.c_int32),
+        ("first_failed_cell", ctypes.c_int64), ("first_nonconv_face", ctypes.c_int64),
     ]
 
     def as_dict(self):
-        return {k: getattr(self, k) for k, _ in self._fields_}
+        out = {k: getattr(self, k) for k, _ in self._fields_}
+        out["totals"] = list(self.totals)
+        return out
 
 
 class TrainCfg(ctypes.Structure):

@@ -50,6 +50,31 @@ def test_library_loads_and_reports_abi_version():
     from paper_2203_05477_amd import pond
 
     lib = pond.load()
-    assert lib.pond_abi_version() == 2
+    assert lib.pond_abi_version() == 3
     assert lib.pond_strerror(1) == b"invalid argument"
     assert lib.pond_mlp_nparams() == 8515
+
+
+def test_stats_struct_layout_matches_the_header(tmp_path):
+    """The binding's pond_stats and pond_config layouts equal the C compiler's (sizes and
+    field offsets), so the summary fields land where the library writes them."""
+    import ctypes
+
+    from paper_2203_05477_amd import pond
+
+    fields = {"pond_stats": pond.Stats, "pond_config": pond.Config}
+    src = ["#include <stdio.h>", "#include <stddef.h>", f'#include "{HEADER}"', "int main(void){"]
+    for cname, cls in fields.items():
+        src.append(f'printf("{cname} size %zu\\n", sizeof({cname}));')
+        for name, _ in cls._fields_:
+            src.append(f'printf("{cname} {name} %zu\\n", offsetof({cname}, {name}));')
+    src.append("return 0;}")
+    (tmp_path / "layout.c").write_text("\n".join(src))
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-std=c99", "-o", str(exe), str(tmp_path / "layout.c")], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split("\n")
+    got = {tuple(l.split()[:2]): int(l.split()[2]) for l in out if l.strip()}
+    for cname, cls in fields.items():
+        assert got[(cname, "size")] == ctypes.sizeof(cls)
+        for name, _ in cls._fields_:
+            assert got[(cname, name)] == getattr(cls, name).offset, (cname, name)
