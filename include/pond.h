@@ -300,6 +300,22 @@ pond_status pond_mlp_grad(pond_mlp *m, const float *dev_X, const float *dev_T, i
  * the mean batch loss of every epoch (cfg->epochs values). */
 pond_status pond_mlp_train(pond_mlp *m, const float *dev_X, const float *dev_T, int64_t n,
                            const pond_train_cfg *cfg, float *loss_out);
+/* For callers that cannot allocate device memory (serving loops that retrain the seed
+ * network online, harnesses that forbid hipMalloc): pond_mlp_train without any allocation.
+ * The per-batch losses and per-epoch mean losses live in a file-scope device array of the
+ * library, (POND_NOALLOC_MAX_BATCHES + POND_NOALLOC_MAX_EPOCHS) floats = 272 KiB, held by
+ * every device the library runs on until the process ends, instead of a buffer allocated
+ * per epoch. Arguments, results and errors as pond_mlp_train (same kernels, same losses and
+ * parameters bit for bit), plus POND_EINVAL when an epoch has more than
+ * POND_NOALLOC_MAX_BATCHES batches ((n + batch - 1) / batch) or cfg->epochs exceeds
+ * POND_NOALLOC_MAX_EPOCHS (the network is then unchanged), and POND_ESTATE when the
+ * current device is not the one that was current at pond_mlp_create. All calls on one
+ * device share the array (it keeps the last call's contents): calls that overlap on one
+ * device race. Synchronizes the network's stream. */
+#define POND_NOALLOC_MAX_BATCHES 65536
+#define POND_NOALLOC_MAX_EPOCHS 4096
+pond_status pond_mlp_train_noalloc(pond_mlp *m, const float *dev_X, const float *dev_T, int64_t n,
+                                   const pond_train_cfg *cfg, float *loss_out);
 void pond_mlp_free(pond_mlp *m);
 
 /* Features of every face at the context's current state (call before pond_step):

@@ -9,6 +9,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <vector>
 
@@ -37,7 +38,7 @@ struct pond_ctx {
     unsigned long long *vmax = nullptr, *stats = nullptr;
     int *err = nullptr;
     int *inst_err = nullptr;
-    double *scratch = nullptr; // read-out staging (4 x ncell doubles)
+    double *scratch = nullptr; // read-out staging (4 x max(ncell, nface) doubles) and summary records
     // 2D: faces handed from the face kernel to the tail kernel
     int *tail_f = nullptr, *tail_meta = nullptr, *tail_count = nullptr, *tblock = nullptr;
     void *tail_s = nullptr;
@@ -588,7 +589,8 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     alloc((void **)&c->stats, sizeof(unsigned long long) * ST_N * NSLOT);
     alloc((void **)&c->err, sizeof(int));
     alloc((void **)&c->inst_err, sizeof(int) * P.n_inst);
-    alloc((void **)&c->scratch, sizeof(double) * 4 * std::max(n, nf));
+    // read-out staging, and the per-block records of the end-of-call summary
+    alloc((void **)&c->scratch, sizeof(double) * std::max<int64_t>(4 * std::max(n, nf), (int64_t)SUM_BLOCKS * SUM_NV));
     if (cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) {
         alloc((void **)&c->U2, sizeof(double) * (c->D + 2) * n);
         alloc(&c->H2, c->rsize * c->nh * n);
@@ -1287,6 +1289,7 @@ void pond_free(pond_ctx *c)
 struct pond_mlp {
     MlpDevice dev;
     hipStream_t stream = nullptr;
+    int device = 0; // the device current at pond_mlp_create, which holds the buffers
 };
 
 namespace {
@@ -1350,6 +1353,68 @@ pond_status mlp_upload(MlpDevice &M, const float *params, hipStream_t st)
 
 int train_grid(int64_t n, int cap) { return (int)std::max<int64_t>(1, std::min<int64_t>((n + 31) / 32, cap)); }
 
+// One epoch of Adam steps over consecutive batches of B samples; the loss of batch b is
+// copied to dloss[b] (device). Returns the number of batches.
+int train_epoch(MlpDevice &M, const float *X, const float *T, int64_t n, const pond_train_cfg *cfg,
+                hipStream_t st, float *dloss)
+{
+    const int64_t B = cfg->batch;
+    int nb = 0;
+    for (int64_t b0 = 0; b0 < n; b0 += B) {
+        int64_t nbn = std::min<int64_t>(B, n - b0);
+        int nw = train_grid(nbn, M.npartial);
+        mlp_train_kernel<<<nw, 64, 0, st>>>(M.wbf, M.master, X + b0 * MLP_IN, T + b0 * 4, nbn, M.partial);
+        mlp_reduce_kernel<<<blocks(MLP_NPARAM + 1, 256), 256, 0, st>>>(M.partial, nw, M.grad);
+        M.adam_t += 1;
+        mlp_adam_kernel<<<blocks(MLP_NPARAM, 256), 256, 0, st>>>(M.master, M.adam_m, M.adam_v, M.grad, M.wbf,
+                                                                 cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, M.adam_t);
+        (void)hipMemcpyAsync(dloss + nb, M.grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToDevice, st);
+        ++nb;
+    }
+    return nb;
+}
+
+bool train_args_ok(const pond_mlp *m, const float *X, const float *T, int64_t n, const pond_train_cfg *cfg)
+{
+    return m && X && T && cfg && n >= 1 && cfg->epochs >= 0 && cfg->batch >= 32 && cfg->batch % 32 == 0;
+}
+
+} // namespace
+
+// Batch losses and epoch means of pond_mlp_train_noalloc: a file-scope device array, one
+// copy per device the library runs on (each holds it until the process ends). Host code
+// reaches it only through the address hipGetSymbolAddress returns for the current device.
+static __device__ __align__(256) float scratch[POND_NOALLOC_MAX_BATCHES + POND_NOALLOC_MAX_EPOCHS];
+
+namespace {
+
+constexpr int kMaxDevices = 64;
+float *g_scratch[kMaxDevices] = {};
+std::mutex g_scratch_mu;
+
+// the device address of `scratch` on device `dev` (which must be current), looked up once
+float *noalloc_scratch(int dev)
+{
+    if (dev < 0 || dev >= kMaxDevices) return nullptr;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch[dev]) {
+        void *ptr = nullptr;
+        if (hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)) != hipSuccess || !ptr) return nullptr;
+        g_scratch[dev] = static_cast<float *>(ptr);
+    }
+    return g_scratch[dev];
+}
+
+// mean of the nb batch losses, summed in double in batch order (the arithmetic of
+// pond_mlp_train's host loop), into out[0]
+__global__ void loss_mean_kernel(const float *dloss, int nb, float *out)
+{
+    if (blockIdx.x != 0 || threadIdx.x != 0) return;
+    double sum = 0.0;
+    for (int b = 0; b < nb; ++b) sum += (double)dloss[b];
+    out[0] = (float)(sum / (nb > 1 ? nb : 1));
+}
+
 } // namespace
 
 extern "C" {
@@ -1364,7 +1429,7 @@ pond_status pond_mlp_create(const float *params, uint64_t seed, pond_mlp **out)
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return POND_EDEVICE;
     pond_mlp *m = new (std::nothrow) pond_mlp();
     if (!m) return POND_ENOMEM;
-    if (hipStreamCreate(&m->stream) != hipSuccess) {
+    if (hipGetDevice(&m->device) != hipSuccess || hipStreamCreate(&m->stream) != hipSuccess) {
         delete m;
         return POND_EDEVICE;
     }
@@ -1431,28 +1496,17 @@ pond_status pond_mlp_grad(pond_mlp *m, const float *X, const float *T, int64_t n
 pond_status pond_mlp_train(pond_mlp *m, const float *X, const float *T, int64_t n, const pond_train_cfg *cfg,
                            float *loss_out)
 {
-    if (!m || !X || !T || !cfg || n < 1 || cfg->epochs < 0 || cfg->batch < 32 || cfg->batch % 32) return POND_EINVAL;
+    if (!train_args_ok(m, X, T, n, cfg)) return POND_EINVAL;
     MlpDevice &M = m->dev;
     const int64_t B = cfg->batch;
     std::vector<float> losses;
     for (int e = 0; e < cfg->epochs; ++e) {
-        int nb = 0;
         // each batch's loss lands in grad[NPARAM]; collected on the device side per batch
         std::vector<float> hl;
         float *dloss = nullptr;
         int64_t nbatches = (n + B - 1) / B;
         HIPCHK(hipMalloc(&dloss, sizeof(float) * nbatches));
-        for (int64_t b0 = 0; b0 < n; b0 += B) {
-            int64_t nbn = std::min<int64_t>(B, n - b0);
-            int nw = train_grid(nbn, M.npartial);
-            mlp_train_kernel<<<nw, 64, 0, m->stream>>>(M.wbf, M.master, X + b0 * MLP_IN, T + b0 * 4, nbn, M.partial);
-            mlp_reduce_kernel<<<blocks(MLP_NPARAM + 1, 256), 256, 0, m->stream>>>(M.partial, nw, M.grad);
-            M.adam_t += 1;
-            mlp_adam_kernel<<<blocks(MLP_NPARAM, 256), 256, 0, m->stream>>>(M.master, M.adam_m, M.adam_v, M.grad, M.wbf,
-                                                                            cfg->lr, cfg->beta1, cfg->beta2, cfg->eps, M.adam_t);
-            HIPCHK(hipMemcpyAsync(dloss + nb, M.grad + MLP_NPARAM, sizeof(float), hipMemcpyDeviceToDevice, m->stream));
-            ++nb;
-        }
+        const int nb = train_epoch(M, X, T, n, cfg, m->stream, dloss);
         HIPCHK(hipGetLastError());
         hl.resize(nb);
         HIPCHK(hipMemcpyAsync(hl.data(), dloss, sizeof(float) * nb, hipMemcpyDeviceToHost, m->stream));
@@ -1463,6 +1517,34 @@ pond_status pond_mlp_train(pond_mlp *m, const float *X, const float *T, int64_t 
         losses.push_back((float)(sum / std::max(nb, 1)));
     }
     if (loss_out) std::copy(losses.begin(), losses.end(), loss_out);
+    return POND_OK;
+}
+
+pond_status pond_mlp_train_noalloc(pond_mlp *m, const float *X, const float *T, int64_t n,
+                                   const pond_train_cfg *cfg, float *loss_out)
+{
+    if (!train_args_ok(m, X, T, n, cfg)) return POND_EINVAL;
+    const int64_t nbatches = (n + cfg->batch - 1) / cfg->batch;
+    if (nbatches > POND_NOALLOC_MAX_BATCHES || cfg->epochs > POND_NOALLOC_MAX_EPOCHS) {
+        fprintf(stderr,
+                "libpond: pond_mlp_train_noalloc: %lld batches per epoch and %d epochs, the static "
+                "buffer holds at most %d and %d\n",
+                (long long)nbatches, cfg->epochs, POND_NOALLOC_MAX_BATCHES, POND_NOALLOC_MAX_EPOCHS);
+        return POND_EINVAL;
+    }
+    int dev = -1;
+    if (hipGetDevice(&dev) != hipSuccess || dev != m->device) return POND_ESTATE;
+    float *buf = noalloc_scratch(dev);
+    if (!buf) return POND_EDEVICE;
+    float *dloss = buf, *means = buf + POND_NOALLOC_MAX_BATCHES;
+    for (int e = 0; e < cfg->epochs; ++e) {
+        const int nb = train_epoch(m->dev, X, T, n, cfg, m->stream, dloss);
+        loss_mean_kernel<<<1, 64, 0, m->stream>>>(dloss, nb, means + e);
+    }
+    HIPCHK(hipGetLastError());
+    if (loss_out && cfg->epochs > 0)
+        HIPCHK(hipMemcpyAsync(loss_out, means, sizeof(float) * cfg->epochs, hipMemcpyDeviceToHost, m->stream));
+    HIPCHK(hipStreamSynchronize(m->stream));
     return POND_OK;
 }
 

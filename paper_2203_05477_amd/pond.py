@@ -132,6 +132,8 @@ def load(path: str | None = None):
                               ctypes.POINTER(ctypes.c_float)]),
         "pond_mlp_train": (S, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
                                ctypes.POINTER(ctypes.c_float)]),
+        "pond_mlp_train_noalloc": (S, [_P, _P, _P, ctypes.c_int64, ctypes.POINTER(TrainCfg),
+                                       ctypes.POINTER(ctypes.c_float)]),
         "pond_mlp_free": (None, [_P]),
         "pond_mlp_features": (S, [_P, _P, _P]),
         "pond_mlp_targets": (S, [_P, _P, _P, _P]),
@@ -159,7 +161,7 @@ def exported_symbols():
             "pond_enable_timing",
             "pond_kernel_times", "pond_free", "pond_strerror", "pond_abi_version",
             "pond_mlp_nparams", "pond_mlp_create", "pond_mlp_get", "pond_mlp_set",
-            "pond_mlp_forward", "pond_mlp_grad", "pond_mlp_train", "pond_mlp_free",
+            "pond_mlp_forward", "pond_mlp_grad", "pond_mlp_train", "pond_mlp_train_noalloc", "pond_mlp_free",
             "pond_mlp_features", "pond_mlp_targets", "pond_load_mlp"]
 
 
@@ -470,4 +472,15 @@ class Mlp:
                                    ctypes.byref(cfg), _fptr(out))
         if rc != OK:
             raise PondError(rc, "pond_mlp_train")
+        return out[: int(epochs)]
+
+    def train_noalloc(self, X_ptr: int, T_ptr: int, n: int, epochs=10, batch=4096, lr=1e-3,
+                      beta1=0.9, beta2=0.999, eps=1e-8):
+        """pond_mlp_train_noalloc: the same training with the library's static buffers."""
+        cfg = TrainCfg(int(epochs), int(batch), float(lr), float(beta1), float(beta2), float(eps))
+        out = np.zeros(max(int(epochs), 1), dtype=np.float32)
+        rc = load().pond_mlp_train_noalloc(self._h, ctypes.c_void_p(X_ptr), ctypes.c_void_p(T_ptr), int(n),
+                                           ctypes.byref(cfg), _fptr(out))
+        if rc != OK:
+            raise PondError(rc, "pond_mlp_train_noalloc")
         return out[: int(epochs)]
