@@ -341,7 +341,12 @@ pond_status pond_load_mlp(pond_ctx *ctx, const pond_mlp *m, int32_t hard_iters);
  * are replaced); the steps that follow give bitwise the results the saved run would have
  * given. The learned seed's network is not part of the file. POND_EINVAL: null argument,
  * file that cannot be opened, written or read, or that belongs to another configuration
- * (then the context is unchanged); POND_EDEVICE: device copy failed. */
+ * (then the context is unchanged); POND_EDEVICE: device copy failed. A checkpoint written
+ * by a context of the other precision (FP64 / mixed) is accepted: its coefficient and face
+ * planes are converted (rounded to FP32 or widened to FP64), conserved variables, clocks
+ * and flags are taken as they are, and the context keeps its own tail hand-over point; the
+ * steps that follow are those of the loading context's precision from that state (used to
+ * start every form of a measurement window from one state). */
 pond_status pond_save(pond_ctx *ctx, const char *path);
 pond_status pond_load(pond_ctx *ctx, const char *path);
 

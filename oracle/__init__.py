@@ -115,6 +115,7 @@ def _load():
     lib.orc_face_moments.argtypes = [ctypes.c_void_p, _D, _D]
     lib.orc_face_iters.argtypes = [ctypes.c_void_p, ctypes.POINTER(ctypes.c_int)]
     lib.orc_num_threads.restype = ctypes.c_int
+    lib.orc_set_num_threads.argtypes = [ctypes.c_int]
     _lib = lib
     return lib
 
@@ -199,6 +200,11 @@ def update_relax(ft, feq, eps):
 
 def num_threads() -> int:
     return _load().orc_num_threads()
+
+
+def set_num_threads(n: int) -> None:
+    """Threads of the oracle's OpenMP loops from now on."""
+    _load().orc_set_num_threads(int(n))
 
 
 def _make_config(cfg: dict) -> _Config:

@@ -6,7 +6,8 @@ parameter vector W1 (64x64, out x in), b1, W2 (64x64), b2, W3 (3x64), b3, and th
 reverse-mode differentiation (chain rule, layer by layer). No code is shared with the
 GPU library.
 
-`bf16=True` evaluates the network the way a BF16-input / FP32-accumulate pipeline sees it:
+`bf16=True` (or a rounding function) evaluates the network the way a BF16-input /
+FP32-accumulate pipeline sees it:
 weights, inputs and the hidden activations entering the next layer are rounded to BF16
 (round to nearest even) and everything else is exact FP64. The gradient is then the exact
 gradient of that evaluation with the rounding treated as the identity.
@@ -45,7 +46,10 @@ def bf16_round(a):
 def forward(p, X, bf16=False):
     """Outputs (n x 3) and the intermediate values needed by backward."""
     P = unpack(p)
-    rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
+    if callable(bf16):
+        rnd = bf16
+    else:
+        rnd = bf16_round if bf16 else (lambda a: np.asarray(a, dtype=np.float64))
     W1, W2, W3 = rnd(P["W1"]), rnd(P["W2"]), rnd(P["W3"])
     x = rnd(X)
     z1 = x @ W1.T + P["b1"]
@@ -85,3 +89,33 @@ def he_params(seed=0, nin_used=40):
     d["W2"] = rng.normal(0.0, np.sqrt(2.0 / NH), (NH, NH))
     d["W3"] = rng.normal(0.0, np.sqrt(2.0 / NH), (NOUT, NH))
     return pack(d)
+
+
+def loss_and_grad_bf16_pipeline(p, X, T, rnd=bf16_round):
+    """Loss and gradient as a BF16-operand / FP32-accumulate training pipeline computes them,
+    exact (FP64) except at its rounding points: weights, inputs and the hidden activations
+    entering the next layer (as forward(bf16=True)); the output error dY = 2 (y - t)/n
+    rounded to BF16 before the layer-3 weight gradient (the back-propagation dY W3 and the
+    bias gradient use it unrounded); the back-propagated dZ2 and dZ1 rounded to BF16 before
+    every product and sum that uses them. Returns the loss, the gradient and the
+    intermediates (for error bounds). `rnd` is the rounding applied at those points (the
+    identity turns the pipeline into the exact network and gradient)."""
+    n = X.shape[0]
+    y, c = forward(p, X, bf16=rnd)
+    e = y - np.asarray(T, dtype=np.float64)[:, :NOUT]
+    loss = float(np.sum(e * e) / n)
+    dy = 2.0 * e / n
+    dyb = rnd(dy)
+    g = {}
+    g["W3"] = dyb.T @ c["h2"]
+    g["b3"] = dy.sum(axis=0)
+    d2 = (dy @ c["W3"]) * (c["z2"] > 0)
+    D2 = rnd(d2)
+    g["W2"] = D2.T @ c["h1"]
+    g["b2"] = D2.sum(axis=0)
+    d1 = (D2 @ c["W2"]) * (c["z1"] > 0)
+    D1 = rnd(d1)
+    g["W1"] = D1.T @ c["x"]
+    g["b1"] = D1.sum(axis=0)
+    c.update(y=y, e=e, dy=dy, dyb=dyb, d2=d2, D2=D2, d1=d1, D1=D1)
+    return loss, pack(g), c

@@ -588,6 +588,15 @@ int orc_num_threads(void)
 #endif
 }
 
+void orc_set_num_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 /* ------------------------------------------------------------------------- */
 /* boundary ghosts (applied to the phi-bar-plus records)                     */
 /* ------------------------------------------------------------------------- */

@@ -122,6 +122,8 @@ void orc_face_iters(const orc_sim *s, int *out);
 long long orc_nfaces(const orc_sim *s);
 
 int orc_num_threads(void);
+/* threads of the OpenMP loops of later calls (n >= 1) */
+void orc_set_num_threads(int n);
 
 #ifdef __cplusplus
 }

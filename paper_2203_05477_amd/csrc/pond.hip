@@ -926,14 +926,41 @@ pond_status pond_load(pond_ctx *c, const char *path)
     if (!fp) return POND_EINVAL;
     CkptHeader h, mine = ckpt_header(c);
     bool ok = fread(&h, sizeof(h), 1, fp) == 1 && memcmp(h.magic, mine.magic, 8) == 0 &&
-              h.abi == mine.abi && h.dim == mine.dim && h.precision == mine.precision &&
+              h.abi == mine.abi && h.dim == mine.dim &&
+              (h.precision == POND_FP64 || h.precision == POND_MIXED) &&
               h.n_inst == mine.n_inst && h.nh == mine.nh && h.nfp == mine.nfp &&
               h.vslots == mine.vslots && h.ncell == mine.ncell && h.nface == mine.nface;
+    // a checkpoint of the other precision: its coefficient and face planes (blobs 1 and 2)
+    // hold the other element size and are converted on the way in
+    const bool convert = ok && h.precision != mine.precision;
+    const size_t fsize = (h.precision == POND_FP64) ? sizeof(double) : sizeof(float);
     std::vector<std::vector<unsigned char>> data;
+    int kb = 0;
     for (const Blob &b : ckpt_blobs(c)) {
         if (!ok) break;
-        data.emplace_back(b.bytes);
-        ok = fread(data.back().data(), 1, b.bytes, fp) == b.bytes;
+        const bool planes = convert && (kb == 1 || kb == 2);
+        const size_t count = b.bytes / c->rsize;
+        std::vector<unsigned char> raw(planes ? count * fsize : b.bytes);
+        ok = fread(raw.data(), 1, raw.size(), fp) == raw.size();
+        if (ok && planes) {
+            std::vector<unsigned char> conv(b.bytes);
+            for (size_t q = 0; q < count; ++q) {
+                if (fsize == sizeof(double)) {
+                    double v;
+                    memcpy(&v, raw.data() + q * sizeof(double), sizeof(double));
+                    float w = (float)v;
+                    memcpy(conv.data() + q * sizeof(float), &w, sizeof(float));
+                } else {
+                    float v;
+                    memcpy(&v, raw.data() + q * sizeof(float), sizeof(float));
+                    double w = (double)v;
+                    memcpy(conv.data() + q * sizeof(double), &w, sizeof(double));
+                }
+            }
+            raw.swap(conv);
+        }
+        data.push_back(std::move(raw));
+        ++kb;
     }
     fclose(fp);
     if (!ok) return POND_EINVAL; // the context is left as it was
@@ -945,7 +972,7 @@ pond_status pond_load(pond_ctx *c, const char *path)
     c->h_failed.assign(c->P.n_inst, 0);
     HIPCHK(hipMemcpy(c->h_failed.data(), c->inst_err, sizeof(int) * c->P.n_inst, hipMemcpyDeviceToHost));
     c->slot = h.slot;
-    c->P.iter_split = h.iter_split;
+    if (!convert) c->P.iter_split = h.iter_split; // the other precision's hand-over point is not taken
     c->steps_done = h.steps_done;
     return POND_OK;
 }

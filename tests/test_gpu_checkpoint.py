@@ -1,6 +1,6 @@
 """Checkpoint and resume (pond_save / pond_load): a run resumed from a file continues
 bitwise as the run that wrote it; a file of another configuration is refused and leaves
-the context unchanged."""
+the context unchanged; a file of the other precision is converted."""
 import numpy as np
 import pytest
 
@@ -44,11 +44,49 @@ def test_foreign_checkpoint_is_refused(tmp_path):
     a.step(2)
     path = tmp_path / "dmr.ckpt"
     a.save(path)
-    cfg2, f2 = W.double_mach(32, 16)
-    b = pond.Context(cfg2, f2, precision="mixed")  # other precision: other layout
+    cfg2, f2 = W.double_mach(48, 16)
+    b = pond.Context(cfg2, f2, precision="mixed")  # other grid
     U0 = b.conserved()
     with pytest.raises(pond.PondError):
         b.load_state(path)
     assert np.array_equal(b.conserved(), U0)
     with pytest.raises(pond.PondError):
         b.load_state(tmp_path / "missing.ckpt")
+
+
+def test_checkpoint_of_the_other_precision(tmp_path):
+    """An FP64 state loaded into a mixed context (and back): the conserved variables, clocks
+    and face seeds carry over exactly (the seeds rounded to FP32), and the loading context
+    then steps in its own precision. On this coarse grid (96 x 24, the shock front is a few
+    per cent of the cells) the two forms move apart by about 1e-3 relative L1 within 10
+    steps, through the discrete decisions of the iteration at the front; the bar is 1e-2."""
+    from paper_2203_05477_amd import pond
+
+    cfg64, f = W.double_mach(96, 24, tol=1e-10)
+    cfg32, _ = W.double_mach(96, 24, tol=1e-5)
+    a = pond.Context(cfg64, f, precision="fp64")
+    a.step(30)
+    path = tmp_path / "fp64.ckpt"
+    a.save(path)
+    b = pond.Context(cfg32, f, precision="mixed")
+    b.load_state(path)
+    assert np.array_equal(a.conserved(), b.conserved())
+    assert np.array_equal(a.time(), b.time())
+    fa, fb = a.face_frames(), b.face_frames()
+    assert np.array_equal(fa.astype(np.float32).astype(np.float64), fb)
+    a.step(10)
+    b.step(10)
+    Ua, Ub = a.conserved(), b.conserved()
+    l1 = np.abs(Ub - Ua).sum(axis=1) / np.abs(Ua).sum(axis=1)
+    print("mixed from the fp64 state, 10 steps: rel L1", l1, flush=True)
+    assert np.all(l1 < 1e-2)
+    # each form's dt follows its own cells' largest speed: the clocks drift apart slightly
+    assert np.allclose(a.time(), b.time(), rtol=1e-3)
+    # and back: a mixed state into an FP64 context
+    path2 = tmp_path / "mixed.ckpt"
+    b.save(path2)
+    c = pond.Context(cfg64, f, precision="fp64")
+    c.load_state(path2)
+    assert np.array_equal(c.conserved(), b.conserved())
+    assert np.array_equal(c.face_frames(), b.face_frames())
+    c.step(5)

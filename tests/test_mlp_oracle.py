@@ -42,3 +42,27 @@ def test_gradient_descent_reduces_loss():
     l0, g = M.loss_and_grad(p, X, T)
     l1, _ = M.loss_and_grad(p - 1e-3 * g, X, T)
     assert l1 < l0
+
+
+def test_bf16_pipeline_reference():
+    """The BF16-pipeline gradient: with the identity at its rounding points it is the exact
+    network gradient (pinned above by finite differences); with BF16 rounding it stays within
+    a few BF16 units (2^-8 relative) of the exact gradient of the BF16 forward evaluation, and
+    each of its rounding points matters (rounding dZ1 alone changes the layer-1 gradient)."""
+    rng = np.random.default_rng(4)
+    p = M.he_params(3) + 0.01 * rng.standard_normal(M.NPARAM)
+    X = np.zeros((33, 64))
+    X[:, :40] = rng.standard_normal((33, 40))
+    T = rng.standard_normal((33, 4))
+    ident = lambda a: np.asarray(a, dtype=np.float64)  # noqa: E731
+    l0, g0, _ = M.loss_and_grad_bf16_pipeline(p, X, T, rnd=ident)
+    l1, g1 = M.loss_and_grad(p, X, T)
+    assert l0 == l1 and np.array_equal(g0, g1)
+    lb, gb, c = M.loss_and_grad_bf16_pipeline(p, X, T)
+    lf, gf = M.loss_and_grad(p, X, T, bf16=True)
+    assert lb == lf
+    assert 0 < np.linalg.norm(gb - gf) <= 4 * 2 ** -8 * np.linalg.norm(gf)
+    # the layer-1 weight gradient is D1^T x with D1 = bf16(dZ1)
+    gW1 = M.unpack(gb)["W1"]
+    assert np.allclose(gW1, c["D1"].T @ c["x"], rtol=1e-14, atol=0)
+    assert not np.allclose(gW1, c["d1"].T @ c["x"], rtol=1e-6, atol=0)
