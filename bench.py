@@ -441,11 +441,19 @@ def double_mach_workload(args):
         from paper_2203_05477_amd import learned_seed as LS
 
         t0 = time.perf_counter()
+        # face frames the solver produces on the two plain-method workloads: the double
+        # Mach reflection on a 4x coarser grid, and the 400-cell shock tube as a y-uniform
+        # strip (the network's inputs are 2D stencils)
         cfgh, fh = W.double_mach(nx // 4, ny // 4, tol=W.TOL_FP32)
         cfgh["regularization"] = args.regularization
-        data = LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2)
-        net, losses, nsamp = LS.train([data], epochs=20, batch=4096, lr=2e-3)
-        train_info = {"samples": nsamp, "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+        c1, f1 = W.shock_tube(400, tol=W.TOL_FP32)
+        cs, fs = W.strip_2d(c1, f1, ny=4)
+        data = [LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2),
+                LS.harvest(cs, fs, steps=500, precision="mixed", hard_iters=2)]
+        net, losses, nsamp = LS.train(data, epochs=20, batch=4096, lr=2e-3)
+        train_info = {"samples": nsamp, "sources": {"double_mach_480x120_300_steps": int(data[0][0].shape[0]),
+                                                    "shock_tube_400_strip_500_steps": int(data[1][0].shape[0])},
+                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
                       "seconds": time.perf_counter() - t0}
 
     forms = [("mixed", "mixed", W.TOL_FP32, "prev"), ("mixed_tol1e-6", "mixed", 1e-6, "prev")]

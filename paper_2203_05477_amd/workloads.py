@@ -225,6 +225,25 @@ def jet(nx=2048, ny=2048, gamma=5.0 / 3.0, cfl=0.2, mu=1e-3, tol=TOL_FP32, max_i
                  "p": np.full(n, amb[3])}
 
 
+def strip_2d(cfg1, fields1, ny=4):
+    """A 1D workload embedded in 2D: the same cells in x, `ny` identical rows periodic in y
+    (square cells), the x boundary conditions and states kept; a y-uniform 2D flow."""
+    nx = cfg1["nx"]
+    dx = (cfg1["x1"] - cfg1["x0"]) / nx
+    cfg = base_config(2, nx, ny, cfg1["x0"], cfg1["x1"], 0.0, ny * dx, gamma=cfg1["gamma"],
+                      cfl=cfg1["cfl"], mu=cfg1["mu"], tol=cfg1["tol"], max_iter=cfg1["max_iter"],
+                      limiter=cfg1.get("limiter", "vanleer"),
+                      bc=(cfg1["bc"][0], cfg1["bc"][1], "periodic", "periodic"))
+    for k in range(2):
+        cfg["bc_state"][k] = list(cfg1["bc_state"][k])
+        cfg["bc_alt"][k] = list(cfg1["bc_alt"][k])
+        cfg["bc_param"][k] = list(cfg1["bc_param"][k])
+    cfg["name"] = cfg1.get("name", "strip") + "_strip"
+    rep = lambda a: np.tile(np.asarray(a, dtype=np.float64), ny)  # noqa: E731
+    return cfg, {"rho": rep(fields1["rho"]), "ux": rep(fields1["ux"]), "uy": np.zeros(nx * ny),
+                 "p": rep(fields1["p"])}
+
+
 def uniform(dim, nx, ny=1, rho=1.0, u=(0.3, -0.2), p=0.7, bc="periodic", **kw):
     cfg = base_config(dim, nx, ny, bc=(bc,) * 4, **kw)
     n = nx * (ny if dim == 2 else 1)
