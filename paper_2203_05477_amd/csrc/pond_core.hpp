@@ -578,6 +578,52 @@ PD void moments_2d(const R p[16], R mu[10], int n)
     }
 }
 
+// Moments of the reduced populations in two stages, tangential then normal, so that the
+// populations can be produced half a face at a time (two normal node columns): the
+// tangential stage of normal node n gives the weighted tangential power sums of degree
+// 0..3 of that column's 4 populations (tangential node t at p[t]); the normal stage then
+// combines the 4 columns into the moments mu (layout 00 10 01 20 11 02 30 21 12 03 in
+// x-y powers; n = 6 for degree 2). For AXIS = 0 this is moments_2d's own order.
+template <typename R>
+PD void tan_sums(const R p0, const R p1, const R p2, const R p3, R out[4])
+{
+    constexpr R w0a = Lat<R>::wa, w0b = Lat<R>::wb;
+    constexpr R w1a = R(Lat<double>::wa * Lat<double>::ca), w1b = R(Lat<double>::wb * Lat<double>::cb);
+    constexpr R w2a = R(Lat<double>::wa * Lat<double>::ca * Lat<double>::ca);
+    constexpr R w2b = R(Lat<double>::wb * Lat<double>::cb * Lat<double>::cb);
+    constexpr R w3a = R(Lat<double>::wa * Lat<double>::ca * Lat<double>::ca * Lat<double>::ca);
+    constexpr R w3b = R(Lat<double>::wb * Lat<double>::cb * Lat<double>::cb * Lat<double>::cb);
+    const R ea = p2 + p1, oa = p2 - p1;
+    const R eb = p3 + p0, ob = p3 - p0;
+    out[0] = fma(w0b, eb, w0a * ea);
+    out[1] = fma(w1b, ob, w1a * oa);
+    out[2] = fma(w2b, eb, w2a * ea);
+    out[3] = fma(w3b, ob, w3a * oa);
+}
+
+template <typename R, int AXIS>
+PD void normal_sums(const R Rt[4][4], R mu[10], int n)
+{
+    R m[4][4]; // [tangential degree l][normal degree k]
+#pragma unroll
+    for (int l = 0; l < 4; ++l) {
+        R col[4] = {Rt[0][l], Rt[1][l], Rt[2][l], Rt[3][l]};
+        tan_sums(col[0], col[1], col[2], col[3], m[l]);
+    }
+    // (x degree, y degree) -> index
+    auto at = [](int a, int b) {
+        const int d = a + b;
+        return d * (d + 1) / 2 + b;
+    };
+#pragma unroll
+    for (int l = 0; l < 4; ++l)
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            const int a = AXIS ? l : k, b = AXIS ? k : l;
+            if (a + b <= (n > 6 ? 3 : 2)) mu[at(a, b)] = m[l][k];
+        }
+}
+
 // reciprocal without the scaling and fix-up of IEEE division: the hardware estimate in FP32
 // (1 ulp), and in FP64 the estimate refined by two Newton steps (a few ulp); the limiter
 // and the frame update only need this accuracy

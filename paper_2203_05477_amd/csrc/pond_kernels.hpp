@@ -562,12 +562,13 @@ PD void recon_1d(const R *L, int NT, const int idx[4], R u, R s, R inv_s, R hdx,
     }
 }
 
-// 2D, face normal along AXIS. idx: L, R, L-n, R+n, L-t, L+t, R-t, R+t.
+// 2D, face normal along AXIS, all 16 populations at once (FP32 records). idx: L, R, L-n,
+// R+n, L-t, L+t, R-t, R+t.
 // SUB: every lane of the wave takes the two negative normal node columns from the R side
 // and the two positive ones from the L side (|normal frame velocity| below s*ca, the usual
 // case); the side cells of the stencil are then evaluated in the two columns they feed only.
 template <typename R, bool G, int AXIS, bool SUB, int REG = 0>
-PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
+PD void recon_2d_whole(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
                  int lim, R M[10])
 {
     R PL[16], PR[16], T[16], A[16], out[16];
@@ -630,6 +631,117 @@ PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s,
         A[i] = fma(-vt * (hdt * sc), sl, out[i]);
     }
     moments_2d(A, M, G ? 6 : 10);
+}
+
+// 2D, face normal along AXIS, half a face at a time (FP64 records). idx as recon_2d_whole.
+// SUB: every lane of the wave takes the two negative normal node columns from the R side
+// and the two positive ones from the L side (|normal frame velocity| below s*ca, the usual
+// case); the side cells of the stencil are then evaluated in the two columns they feed only.
+// The face is done half at a time (normal node columns 2, 3, then 0, 1): every stencil cell
+// a half needs is transformed into the face frame again for it (L and R twice in the SUB
+// form), which keeps the live set at a few arrays of 8 populations; each half's columns are
+// reduced over the tangential nodes at once, and the normal stage closes the moments.
+template <typename R, bool G, int AXIS, bool SUB, int REG = 0>
+PD void recon_2d_halves(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
+                 int lim, R M[10])
+{
+    const R un = AXIS ? uy : ux, ut = AXIS ? ux : uy;
+    bool upn[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) upn[k] = SUB ? (k >= 2) : (fma(s, node<R>(k), un) >= R(0));
+    auto nk = [](int i) { return AXIS ? (i >> 2) : (i & 3); };
+    auto tk = [](int i) { return AXIS ? (i & 3) : (i >> 2); };
+    auto pi = [](int n, int t) { return AXIS ? (t + 4 * n) : (n + 4 * t); };
+    // the SUB and full forms give bitwise the same values in every lane (the choice between
+    // them depends on the other lanes of the wave): every population goes through the same
+    // operations in both, and products that feed sums are explicit fma
+    const R sc = R(limit_scale(lim)); // slopes come from limit_part
+    R Rt[4][4];
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const int cols = h ? 0x3 : 0xC;
+        R PL[16], PR[16], T[16], A[16], out[16];
+        __builtin_amdgcn_sched_barrier(0);
+        cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[0], ux, uy, inv_s, cols, PL);
+        __builtin_amdgcn_sched_barrier(0);
+        cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[1], ux, uy, inv_s, cols, PR);
+        if (!SUB || h == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[2], ux, uy, inv_s, cols, T);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i)
+            if (cols & (1 << nk(i))) A[i] = upn[nk(i)] ? PL[i] - T[i] : PR[i] - PL[i];
+        if (!SUB || h == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[3], ux, uy, inv_s, cols, T);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (!(cols & (1 << nk(i)))) continue;
+            const bool up = upn[nk(i)];
+            R vn = fma(s, node<R>(nk(i)), un);
+            R B = up ? PR[i] - PL[i] : T[i] - PR[i];
+            R sl = limit_part(A[i], B, lim);
+            R off = fma(-vn, hdn * sc, up ? R(0.5) * sc : R(-0.5) * sc);
+            R pu = up ? PL[i] : PR[i];
+            out[i] = fma(off, sl, pu);
+            PL[i] = pu; // upwind value, kept for the tangential slope
+        }
+        // tangential slope of the upwind cell: backward neighbour L-t or R-t, forward L+t or R+t
+        if (!SUB || h == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[4], ux, uy, inv_s, cols, T);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (cols & (1 << nk(i))) A[i] = PL[i] - T[i];
+        }
+        if (!SUB || h == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[6], ux, uy, inv_s, cols, T);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if ((cols & (1 << nk(i))) && !upn[nk(i)]) A[i] = PL[i] - T[i];
+        }
+        if (!SUB || h == 0) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[5], ux, uy, inv_s, cols, T);
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if (cols & (1 << nk(i))) PR[i] = T[i] - PL[i];
+        }
+        if (!SUB || h == 1) {
+            __builtin_amdgcn_sched_barrier(0);
+            cell_cols_2d<R, G, AXIS, REG>(L, NT, idx[7], ux, uy, inv_s, cols, T);
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            if (!(cols & (1 << nk(i)))) continue;
+            R B = upn[nk(i)] ? PR[i] : T[i] - PL[i];
+            R sl = limit_part(A[i], B, lim);
+            R vt = fma(s, node<R>(tk(i)), ut);
+            out[i] = fma(-vt * (hdt * sc), sl, out[i]);
+        }
+#pragma unroll
+        for (int n = 0; n < 4; ++n)
+            if (cols & (1 << n)) tan_sums(out[pi(n, 0)], out[pi(n, 1)], out[pi(n, 2)], out[pi(n, 3)], Rt[n]);
+    }
+    normal_sums<R, AXIS>(Rt, M, G ? 6 : 10);
+}
+
+// The reconstruction of one face iteration. FP64: half a face at a time, which holds the
+// FP64 face kernel at 247 registers (2 waves per SIMD without spills, where the whole-face
+// form needs about 282 and spills); FP32: the whole face, whose one transform of L and R
+// per iteration is cheaper there (142 against 161 registers, both 3 waves per SIMD, and the
+// halves' second transforms made the FP32 kernel 7% slower).
+template <typename R, bool G, int AXIS, bool SUB, int REG = 0>
+PD void recon_2d(const R *L, int NT, const int idx[8], R ux, R uy, R s, R inv_s, R hdn, R hdt,
+                 int lim, R M[10])
+{
+    if constexpr (sizeof(R) == 8)
+        recon_2d_halves<R, G, AXIS, SUB, REG>(L, NT, idx, ux, uy, s, inv_s, hdn, hdt, lim, M);
+    else
+        recon_2d_whole<R, G, AXIS, SUB, REG>(L, NT, idx, ux, uy, s, inv_s, hdn, hdt, lim, M);
 }
 
 // ---------------------------------------------------------------------------------
