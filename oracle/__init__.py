@@ -60,6 +60,9 @@ class _Config(ctypes.Structure):
         ("bc_param", (ctypes.c_double * 4) * 4),
         ("reg", ctypes.c_int),
         ("scheme", ctypes.c_int),
+        ("nz", ctypes.c_int),
+        ("z0", ctypes.c_double), ("z1", ctypes.c_double),
+        ("bc_z", ctypes.c_int * 2),
     ]
 
 
@@ -97,6 +100,8 @@ def _load():
         fn.argtypes = [ctypes.c_double, ctypes.c_double, ctypes.c_double]
     lib.orc_create.restype = ctypes.c_void_p
     lib.orc_create.argtypes = [ctypes.POINTER(_Config), _D, _D, _D, _D]
+    lib.orc_create3.restype = ctypes.c_void_p
+    lib.orc_create3.argtypes = [ctypes.POINTER(_Config), _D, _D, _D, _D, _D]
     lib.orc_destroy.argtypes = [ctypes.c_void_p]
     lib.orc_step.restype = ctypes.c_int
     lib.orc_step.argtypes = [ctypes.c_void_p, ctypes.c_double, ctypes.POINTER(_Stats)]
@@ -212,6 +217,8 @@ def _make_config(cfg: dict) -> _Config:
     c.dim = int(cfg["dim"])
     c.nx = int(cfg["nx"])
     c.ny = int(cfg.get("ny", 1))
+    c.nz = int(cfg.get("nz", 1))
+    c.z0, c.z1 = float(cfg.get("z0", 0.0)), float(cfg.get("z1", 1.0))
     c.x0, c.x1 = float(cfg.get("x0", 0.0)), float(cfg.get("x1", 1.0))
     c.y0, c.y1 = float(cfg.get("y0", 0.0)), float(cfg.get("y1", 1.0))
     c.gamma = float(cfg["gamma"])
@@ -223,6 +230,8 @@ def _make_config(cfg: dict) -> _Config:
     c.reg = REGULARIZATION[cfg.get("regularization", "grad")]
     c.scheme = SCHEME[cfg.get("scheme", "fv")]
     bc = cfg["bc"]
+    for k in range(2):
+        c.bc_z[k] = BC_KIND[bc[4 + k]] if len(bc) > 4 else BC_KIND["outflow"]
     for k in range(4):
         c.bc[k] = BC_KIND[bc[k]]
         for q in range(4):
@@ -233,26 +242,28 @@ def _make_config(cfg: dict) -> _Config:
 
 
 class Sim:
-    """One oracle simulation (a 1D tube or a 2D grid)."""
+    """One oracle simulation (a 1D tube, a 2D grid or a 3D box)."""
 
-    def __init__(self, cfg: dict, rho, ux, uy, p):
+    def __init__(self, cfg: dict, rho, ux, uy, p, uz=None):
         lib = _load()
         self.cfg = dict(cfg)
         self.dim = int(cfg["dim"])
         self.nx = int(cfg["nx"])
-        self.ny = int(cfg.get("ny", 1)) if self.dim == 2 else 1
-        self.n = self.nx * self.ny
+        self.ny = int(cfg.get("ny", 1)) if self.dim >= 2 else 1
+        self.nz = int(cfg.get("nz", 1)) if self.dim == 3 else 1
+        self.n = self.nx * self.ny * self.nz
         self.Q = 4 ** self.dim
         self._c = _make_config(cfg)
         self._rho = _f64(rho).ravel()
         self._ux = _f64(ux).ravel()
         self._uy = _f64(uy if uy is not None else np.zeros(self.n)).ravel()
+        self._uz = _f64(uz if uz is not None else np.zeros(self.n)).ravel()
         self._p = _f64(p).ravel()
-        for a in (self._rho, self._ux, self._uy, self._p):
+        for a in (self._rho, self._ux, self._uy, self._uz, self._p):
             if a.size != self.n:
                 raise ValueError("initial field size does not match the grid")
-        h = lib.orc_create(ctypes.byref(self._c), _ptr(self._rho), _ptr(self._ux),
-                           _ptr(self._uy), _ptr(self._p))
+        h = lib.orc_create3(ctypes.byref(self._c), _ptr(self._rho), _ptr(self._ux),
+                            _ptr(self._uy), _ptr(self._uz), _ptr(self._p))
         if not h:
             raise ValueError("oracle rejected the configuration or initial state")
         self._h = h
@@ -293,9 +304,10 @@ class Sim:
         return _load().orc_steps(self._h)
 
     def fields(self):
+        """rho, ux, uy (None in 1D), T; in 3D use conserved() for the z momentum."""
         r = np.zeros(self.n); ux = np.zeros(self.n); uy = np.zeros(self.n); T = np.zeros(self.n)
         _load().orc_fields(self._h, _ptr(r), _ptr(ux), _ptr(uy), _ptr(T))
-        return r, ux, (uy if self.dim == 2 else None), T
+        return r, ux, (uy if self.dim >= 2 else None), T
 
     def conserved(self) -> np.ndarray:
         U = np.zeros((self.dim + 2, self.n))

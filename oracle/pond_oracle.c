@@ -55,8 +55,8 @@
 #endif
 
 #define TL 1.0 /* lattice temperature of Table I */
-#define MAXD 2
-#define MAXQ 16
+#define MAXD 3
+#define MAXQ 64
 #define NG 2 /* ghost layers */
 
 /* ------------------------------------------------------------------------- */
@@ -71,7 +71,8 @@ typedef struct {
 
 /* D1Q4 nodes are the roots of the fourth Hermite polynomial, +-sqrt(3 -+ sqrt 6),
  * with Gauss-Hermite weights (3 +- sqrt 6)/12; D2Q16 is their tensor product,
- * W_i = w_ix w_iy. Index i = ix + 4 iy with nodes sorted ascending. */
+ * W_i = w_ix w_iy, and D3Q64 the product of three. Index i = ix + 4 iy + 16 iz with nodes
+ * sorted ascending. */
 static void make_lattice(int D, lattice *L)
 {
     const double r6 = sqrt(6.0);
@@ -80,14 +81,18 @@ static void make_lattice(int D, lattice *L)
                           (3.0 - r6) / 12.0};
     memset(L, 0, sizeof(*L));
     L->D = D;
-    L->Q = (D == 1) ? 4 : 16;
+    L->Q = (D == 1) ? 4 : (D == 2) ? 16 : 64;
     for (int i = 0; i < L->Q; ++i) {
-        int ix = i % 4, iy = i / 4;
+        int ix = i % 4, iy = (i / 4) % 4, iz = i / 16;
         L->c[i][0] = c1[ix];
         L->W[i] = w1[ix];
-        if (D == 2) {
+        if (D >= 2) {
             L->c[i][1] = c1[iy];
             L->W[i] *= w1[iy];
+        }
+        if (D == 3) {
+            L->c[i][2] = c1[iz];
+            L->W[i] *= w1[iz];
         }
     }
 }
@@ -453,24 +458,27 @@ typedef struct {
 struct orc_sim {
     orc_config cfg;
     lattice L;
-    int D, Q, nx, ny, nxg, nyg;
+    int D, Q, nx, ny, nz, nxg, nyg, nzg;
     double dx[MAXD];
     double Cv;
     double t;
     long long nstep;
     cellrec *cell;   /* carried state, interior + ghost storage (ghosts unused) */
     cellrec *plus;   /* phi-bar-plus of every cell, ghosts included             */
-    facerec *face;   /* x-faces then y-faces                                    */
-    long long nfx, nfy;
+    facerec *face;   /* x-faces, then y-faces, then z-faces                     */
+    long long nfx, nfy, nfz;
 };
 
-static inline long long cidx(const orc_sim *s, int i, int j)
+static inline long long cidx3(const orc_sim *s, int i, int j, int k)
 {
-    return (long long)(i + NG) + (long long)s->nxg * (long long)(s->D == 2 ? (j + NG) : 0);
+    return (long long)(i + NG) + (long long)s->nxg * (long long)(s->D >= 2 ? (j + NG) : 0) +
+           (long long)s->nxg * s->nyg * (long long)(s->D == 3 ? (k + NG) : 0);
 }
 
+static inline long long cidx(const orc_sim *s, int i, int j) { return cidx3(s, i, j, 0); }
+
 static double xc(const orc_sim *s, int i) { return s->cfg.x0 + (i + 0.5) * s->dx[0]; }
-static double yc(const orc_sim *s, int j) { return s->D == 2 ? s->cfg.y0 + (j + 0.5) * s->dx[1] : 0.0; }
+static double yc(const orc_sim *s, int j) { return s->D >= 2 ? s->cfg.y0 + (j + 0.5) * s->dx[1] : 0.0; }
 
 /* equilibrium populations of Sec. II.B in the co-moving frame {u, T}:
  * f_eq = rho W_i, g_eq = (C_v - D/2) T rho W_i */
@@ -487,7 +495,7 @@ static void set_equilibrium(const orc_sim *s, cellrec *c, double rho, const doub
 
 static void set_equilibrium_prim(const orc_sim *s, cellrec *c, const double *st /* rho ux uy p */)
 {
-    double u[MAXD] = {st[1], st[2]};
+    double u[MAXD] = {st[1], st[2], 0.0};
     set_equilibrium(s, c, st[0], u, st[3] / st[0]);
 }
 
@@ -527,43 +535,64 @@ static void reframe_cell(const orc_sim *s, const cellrec *in, cellrec *out)
     out->rho = rho;
 }
 
-orc_sim *orc_create(const orc_config *cfg, const double *rho, const double *ux, const double *uy,
-                    const double *p)
+orc_sim *orc_create3(const orc_config *cfg, const double *rho, const double *ux, const double *uy,
+                     const double *uz, const double *p)
 {
-    if (!cfg || (cfg->dim != 1 && cfg->dim != 2) || cfg->nx < 2) return NULL;
-    if (cfg->dim == 2 && cfg->ny < 2) return NULL;
+    if (!cfg || cfg->dim < 1 || cfg->dim > 3 || cfg->nx < 2) return NULL;
+    if (cfg->dim >= 2 && cfg->ny < 2) return NULL;
+    if (cfg->dim == 3 && cfg->nz < 2) return NULL;
     if (!(cfg->gamma > 1.0)) return NULL;
     if (cfg->scheme == ORC_SCHEME_SL && cfg->dim != 1) return NULL; /* 1D only */
+    if (cfg->dim == 3) {
+        /* 3D: Grad projection, finite volumes, and the periodic / outflow / reflecting sides */
+        if (cfg->reg != ORC_REG_GRAD || cfg->scheme != ORC_SCHEME_FV) return NULL;
+        for (int q = 0; q < 6; ++q) {
+            int kind = q < 4 ? cfg->bc[q] : cfg->bc_z[q - 4];
+            if (kind != ORC_BC_PERIODIC && kind != ORC_BC_OUTFLOW && kind != ORC_BC_REFLECT) return NULL;
+        }
+    }
     orc_sim *s = (orc_sim *)calloc(1, sizeof(orc_sim));
     s->cfg = *cfg;
     s->D = cfg->dim;
     make_lattice(s->D, &s->L);
     s->Q = s->L.Q;
     s->nx = cfg->nx;
-    s->ny = (s->D == 2) ? cfg->ny : 1;
+    s->ny = (s->D >= 2) ? cfg->ny : 1;
+    s->nz = (s->D == 3) ? cfg->nz : 1;
     s->nxg = s->nx + 2 * NG;
-    s->nyg = (s->D == 2) ? s->ny + 2 * NG : 1;
+    s->nyg = (s->D >= 2) ? s->ny + 2 * NG : 1;
+    s->nzg = (s->D == 3) ? s->nz + 2 * NG : 1;
     s->dx[0] = (cfg->x1 - cfg->x0) / s->nx;
-    s->dx[1] = (s->D == 2) ? (cfg->y1 - cfg->y0) / s->ny : 1.0;
+    s->dx[1] = (s->D >= 2) ? (cfg->y1 - cfg->y0) / s->ny : 1.0;
+    s->dx[2] = (s->D == 3) ? (cfg->z1 - cfg->z0) / s->nz : 1.0;
     s->Cv = 1.0 / (cfg->gamma - 1.0);
-    long long ncg = (long long)s->nxg * s->nyg;
+    long long ncg = (long long)s->nxg * s->nyg * s->nzg;
     s->cell = (cellrec *)calloc((size_t)ncg, sizeof(cellrec));
     s->plus = (cellrec *)calloc((size_t)ncg, sizeof(cellrec));
-    s->nfx = (long long)(s->nx + 1) * s->ny;
-    s->nfy = (s->D == 2) ? (long long)s->nx * (s->ny + 1) : 0;
-    s->face = (facerec *)calloc((size_t)(s->nfx + s->nfy), sizeof(facerec));
+    s->nfx = (long long)(s->nx + 1) * s->ny * s->nz;
+    s->nfy = (s->D >= 2) ? (long long)s->nx * (s->ny + 1) * s->nz : 0;
+    s->nfz = (s->D == 3) ? (long long)s->nx * s->ny * (s->nz + 1) : 0;
+    s->face = (facerec *)calloc((size_t)(s->nfx + s->nfy + s->nfz), sizeof(facerec));
     /* initial state: local equilibrium in the co-moving frame, so f~ = f = f_eq */
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i) {
-            long long k = (long long)i + (long long)s->nx * j;
-            double st[4] = {rho[k], ux[k], (s->D == 2 && uy) ? uy[k] : 0.0, p[k]};
-            if (!(st[0] > 0.0) || !(st[3] > 0.0)) {
-                orc_destroy(s);
-                return NULL;
+    for (int kz = 0; kz < s->nz; ++kz)
+        for (int j = 0; j < s->ny; ++j)
+            for (int i = 0; i < s->nx; ++i) {
+                long long k = (long long)i + (long long)s->nx * (j + (long long)s->ny * kz);
+                double u[MAXD] = {ux[k], (s->D >= 2 && uy) ? uy[k] : 0.0, (s->D == 3 && uz) ? uz[k] : 0.0};
+                if (!(rho[k] > 0.0) || !(p[k] > 0.0)) {
+                    orc_destroy(s);
+                    return NULL;
+                }
+                set_equilibrium(s, &s->cell[cidx3(s, i, j, kz)], rho[k], u, p[k] / rho[k]);
             }
-            set_equilibrium_prim(s, &s->cell[cidx(s, i, j)], st);
-        }
     return s;
+}
+
+orc_sim *orc_create(const orc_config *cfg, const double *rho, const double *ux, const double *uy,
+                    const double *p)
+{
+    if (cfg && cfg->dim == 3) return NULL; /* 3D needs the z velocity: orc_create3 */
+    return orc_create3(cfg, rho, ux, uy, NULL, p);
 }
 
 void orc_destroy(orc_sim *s)
@@ -577,7 +606,7 @@ void orc_destroy(orc_sim *s)
 
 double orc_time(const orc_sim *s) { return s->t; }
 long long orc_steps(const orc_sim *s) { return s->nstep; }
-long long orc_nfaces(const orc_sim *s) { return s->nfx + s->nfy; }
+long long orc_nfaces(const orc_sim *s) { return s->nfx + s->nfy + s->nfz; }
 
 int orc_num_threads(void)
 {
@@ -607,9 +636,9 @@ static void mirror(const orc_sim *s, const cellrec *in, cellrec *out, int axis)
 {
     *out = *in;
     for (int i = 0; i < s->Q; ++i) {
-        int ix = i % 4, iy = i / 4;
-        int im = (axis == 0) ? (3 - ix) + 4 * iy : ix + 4 * (3 - iy);
-        if (s->D == 1) im = 3 - ix;
+        int dig[3] = {i % 4, (i / 4) % 4, i / 16};
+        dig[axis] = 3 - dig[axis];
+        int im = dig[0] + 4 * dig[1] + 16 * dig[2];
         out->f[im] = in->f[i];
         out->g[im] = in->g[i];
     }
@@ -652,8 +681,57 @@ static void fill_ghost(orc_sim *s, int side, int gi, int gj)
     }
 }
 
+/* 3D ghosts (periodic, outflow, reflecting sides): x-ghosts of the interior (y, z) rows,
+ * then y-ghosts over every x (ghosts included) of the interior z layers, then z-ghosts over
+ * every x and y; side 2a is the lower side of axis a, 2a + 1 the upper */
+static void fill_ghost3(orc_sim *s, int axis, int hi, int gi, int gj, int gk)
+{
+    const int n = axis == 0 ? s->nx : axis == 1 ? s->ny : s->nz;
+    int g[3] = {gi, gj, gk};
+    int layer = hi ? g[axis] - n : -1 - g[axis];
+    int kind = axis < 2 ? s->cfg.bc[2 * axis + hi] : s->cfg.bc_z[hi];
+    int src[3] = {gi, gj, gk};
+    cellrec *dst = &s->plus[cidx3(s, gi, gj, gk)];
+    if (kind == ORC_BC_PERIODIC) {
+        src[axis] = hi ? g[axis] - n : g[axis] + n;
+        *dst = s->plus[cidx3(s, src[0], src[1], src[2])];
+    } else if (kind == ORC_BC_OUTFLOW) {
+        src[axis] = hi ? n - 1 : 0;
+        *dst = s->plus[cidx3(s, src[0], src[1], src[2])];
+    } else { /* reflect */
+        src[axis] = hi ? n - 1 - layer : layer;
+        mirror(s, &s->plus[cidx3(s, src[0], src[1], src[2])], dst, axis);
+    }
+}
+
+static void fill_ghosts3(orc_sim *s)
+{
+    for (int k = 0; k < s->nz; ++k)
+        for (int j = 0; j < s->ny; ++j)
+            for (int l = 0; l < NG; ++l) {
+                fill_ghost3(s, 0, 0, -1 - l, j, k);
+                fill_ghost3(s, 0, 1, s->nx + l, j, k);
+            }
+    for (int k = 0; k < s->nz; ++k)
+        for (int i = -NG; i < s->nx + NG; ++i)
+            for (int l = 0; l < NG; ++l) {
+                fill_ghost3(s, 1, 0, i, -1 - l, k);
+                fill_ghost3(s, 1, 1, i, s->ny + l, k);
+            }
+    for (int j = -NG; j < s->ny + NG; ++j)
+        for (int i = -NG; i < s->nx + NG; ++i)
+            for (int l = 0; l < NG; ++l) {
+                fill_ghost3(s, 2, 0, i, j, -1 - l);
+                fill_ghost3(s, 2, 1, i, j, s->nz + l);
+            }
+}
+
 static void fill_ghosts(orc_sim *s)
 {
+    if (s->D == 3) {
+        fill_ghosts3(s);
+        return;
+    }
     for (int j = 0; j < s->ny; ++j)
         for (int l = 0; l < NG; ++l) {
             fill_ghost(s, 0, -1 - l, j);
@@ -678,41 +756,45 @@ typedef struct {
 } stepacc;
 
 /* one face along `axis` between cells L=(iL,jL) and R = L + e_axis */
-static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, double dt,
+static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, int kL, double dt,
                            long long *depout, long long *nonphys)
 {
     const int D = s->D, Q = s->Q;
-    const int t_axis = 1 - axis;
+    /* the tangential axes (one in 2D, two in 3D), in increasing order */
+    int t_axes[2], nt = 0;
+    for (int a = 0; a < D; ++a)
+        if (a != axis) t_axes[nt++] = a;
     const double h = 0.5 * dt;
-    int ei[MAXD] = {0, 0};
-    ei[axis] = 1;
-    /* stencil: 0 = L - e_a, 1 = L, 2 = R, 3 = R + e_a; (2D) 4 = L - e_t, 5 = L + e_t,
-     * 6 = R - e_t, 7 = R + e_t */
-    int ns = (D == 2) ? 8 : 4;
-    int si[8], sj[8];
-    int iR = iL + ei[0], jR = jL + ei[1];
-    si[0] = iL - ei[0]; sj[0] = jL - ei[1];
-    si[1] = iL;         sj[1] = jL;
-    si[2] = iR;         sj[2] = jR;
-    si[3] = iR + ei[0]; sj[3] = jR + ei[1];
-    if (D == 2) {
-        int et[2] = {ei[1], ei[0]};
-        si[4] = iL - et[0]; sj[4] = jL - et[1];
-        si[5] = iL + et[0]; sj[5] = jL + et[1];
-        si[6] = iR - et[0]; sj[6] = jR - et[1];
-        si[7] = iR + et[0]; sj[7] = jR + et[1];
+    /* stencil: 0 = L - e_a, 1 = L, 2 = R, 3 = R + e_a; per tangential axis t (q-th):
+     * 4 + 4q = L - e_t, 5 + 4q = L + e_t, 6 + 4q = R - e_t, 7 + 4q = R + e_t */
+    const int ns = 4 + 4 * nt;
+    int sc[12][3];
+    const int L0[3] = {iL, jL, kL};
+    for (int k = 0; k < ns; ++k)
+        for (int a = 0; a < 3; ++a) sc[k][a] = L0[a];
+    sc[0][axis] -= 1;
+    sc[2][axis] += 1;
+    sc[3][axis] += 2;
+    for (int q = 0; q < nt; ++q) {
+        const int t = t_axes[q], b = 4 + 4 * q;
+        sc[b][t] -= 1;
+        sc[b + 1][t] += 1;
+        sc[b + 2][axis] += 1;
+        sc[b + 2][t] -= 1;
+        sc[b + 3][axis] += 1;
+        sc[b + 3][t] += 1;
     }
     /* lab moments of every stencil cell's phi-bar-plus: they do not depend on the
      * target frame, so the regularized transformation into any lambda is a Grad
      * projection of these (Sec. II.C) */
-    tensors Mf[8], Mg[8];
+    tensors Mf[12], Mg[12];
     for (int k = 0; k < ns; ++k) {
-        const cellrec *c = &s->plus[cidx(s, si[k], sj[k])];
+        const cellrec *c = &s->plus[cidx3(s, sc[k][0], sc[k][1], sc[k][2])];
         moments(&s->L, c->f, c->u, c->T, &Mf[k]);
         moments(&s->L, c->g, c->u, c->T, &Mg[k]);
     }
-    const cellrec *cL = &s->plus[cidx(s, iL, jL)];
-    const cellrec *cR = &s->plus[cidx(s, iR, jR)];
+    const cellrec *cL = &s->plus[cidx3(s, sc[1][0], sc[1][1], sc[1][2])];
+    const cellrec *cR = &s->plus[cidx3(s, sc[2][0], sc[2][1], sc[2][2])];
 
     /* frame of the mean conserved variables of L and R: the seed of the first step and
      * the restart frame of an iteration that has left the physical states */
@@ -745,7 +827,7 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
     }
     int restarted = !F->seeded;
 
-    double Pf[8][MAXQ], Pg[8][MAXQ], fb[MAXQ], gb[MAXQ], v[MAXQ][MAXD];
+    double Pf[12][MAXQ], Pg[12][MAXQ], fb[MAXQ], gb[MAXQ], v[MAXQ][MAXD];
     tensors Mfb, Mgb;
     int it, conv = 0, failed = 0, have_pp = 0;
     double pu[MAXD] = {0, 0}, pT = 1.0; /* frame two iterations back */
@@ -771,8 +853,9 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
                                     (Pg[cF][i] - Pg[cU][i]) / s->dx[axis]);
             fb[i] = Pf[cU][i] + off_a * sf;
             gb[i] = Pg[cU][i] + off_a * sg;
-            if (D == 2) {
-                int tm = up ? 4 : 6, tp = up ? 5 : 7;
+            for (int q = 0; q < nt; ++q) {
+                const int t_axis = t_axes[q], b = 4 + 4 * q;
+                int tm = up ? b : b + 2, tp = up ? b + 1 : b + 3;
                 double off_t = -v[i][t_axis] * h;
                 if (fabs(v[i][t_axis]) * h > 0.5 * s->dx[t_axis]) ++*depout;
                 double tf = orc_limiter(s->cfg.limiter, (Pf[cU][i] - Pf[tm][i]) / s->dx[t_axis],
@@ -924,21 +1007,22 @@ static void face_iteration(orc_sim *s, facerec *F, int axis, int iL, int jL, dou
  * and the prescribed boundary states, clipped at t_end */
 static double time_step(const orc_sim *s, double t_end)
 {
-    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny;
+    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny, nz = s->nz;
     const double cmax = s->L.c[Q - 1][0]; /* largest node, sqrt(3 + sqrt 6) */
     double rate = 0.0;
-#pragma omp parallel for collapse(2) reduction(max : rate) schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            const cellrec *c = &s->cell[cidx(s, i, j)];
-            for (int a = 0; a < D; ++a) {
-                double r = (fabs(c->u[a]) + sqrt(c->T / TL) * cmax) / s->dx[a];
-                rate = fmax(rate, r);
+#pragma omp parallel for collapse(3) reduction(max : rate) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const cellrec *c = &s->cell[cidx3(s, i, j, k)];
+                for (int a = 0; a < D; ++a) {
+                    double r = (fabs(c->u[a]) + sqrt(c->T / TL) * cmax) / s->dx[a];
+                    rate = fmax(rate, r);
+                }
             }
-        }
     /* the prescribed boundary states stream into the domain through the boundary faces,
-     * so their particle speeds belong to the same maximum */
-    for (int side = 0; side < 2 * D; ++side) {
+     * so their particle speeds belong to the same maximum (3D has no prescribed states) */
+    for (int side = 0; side < 2 * D && side < 4; ++side) {
         int kind = s->cfg.bc[side];
         const double *used[2] = {NULL, NULL};
         if (kind == ORC_BC_FIXED || kind == ORC_BC_SPLIT_FIXED_REFLECT)
@@ -1098,102 +1182,114 @@ static int sl_step(orc_sim *s, double t_end, orc_stats *st)
     return nonc ? 2 : 0;
 }
 
+/* face index of the face on the `hi` side of cell (i, j, k) along `axis` */
+static long long face_of(const orc_sim *s, int axis, int i, int j, int k, int hi)
+{
+    if (axis == 0) return (long long)(i + hi) + (long long)(s->nx + 1) * (j + (long long)s->ny * k);
+    if (axis == 1) return s->nfx + (long long)i + (long long)s->nx * ((j + hi) + (long long)(s->ny + 1) * k);
+    return s->nfx + s->nfy + (long long)i + (long long)s->nx * (j + (long long)s->ny * (k + hi));
+}
+
 int orc_step(orc_sim *s, double t_end, orc_stats *st)
 {
-    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny;
+    const int D = s->D, Q = s->Q, nx = s->nx, ny = s->ny, nz = s->nz;
     if (s->t >= t_end) return 1;
     if (s->cfg.scheme == ORC_SCHEME_SL) return sl_step(s, t_end, st);
 
     /* 1. every cell's populations in its own co-moving frame */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            cellrec tmp;
-            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
-            s->cell[cidx(s, i, j)] = tmp;
-        }
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                cellrec tmp;
+                reframe_cell(s, &s->cell[cidx3(s, i, j, k)], &tmp);
+                s->cell[cidx3(s, i, j, k)] = tmp;
+            }
 
     double dt = time_step(s, t_end);
 
     /* 2. phi-bar-plus of every cell (Sec. III.B.3), eps = dt/tau = dt p / mu */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            const cellrec *c = &s->cell[cidx(s, i, j)];
-            cellrec *o = &s->plus[cidx(s, i, j)];
-            double eps = dt * c->rho * c->T / s->cfg.mu;
-            double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
-            for (int q = 0; q < Q; ++q) {
-                o->f[q] = orc_phibar_plus(c->f[q], c->rho * s->L.W[q], eps);
-                o->g[q] = orc_phibar_plus(c->g[q], geq_coef * s->L.W[q], eps);
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                const cellrec *c = &s->cell[cidx3(s, i, j, k)];
+                cellrec *o = &s->plus[cidx3(s, i, j, k)];
+                double eps = dt * c->rho * c->T / s->cfg.mu;
+                double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
+                for (int q = 0; q < Q; ++q) {
+                    o->f[q] = orc_phibar_plus(c->f[q], c->rho * s->L.W[q], eps);
+                    o->g[q] = orc_phibar_plus(c->g[q], geq_coef * s->L.W[q], eps);
+                }
+                for (int a = 0; a < D; ++a) o->u[a] = c->u[a];
+                o->T = c->T;
+                o->rho = c->rho;
             }
-            for (int a = 0; a < D; ++a) o->u[a] = c->u[a];
-            o->T = c->T;
-            o->rho = c->rho;
-        }
     fill_ghosts(s);
 
     /* 3. faces: predictor-corrector frame iteration and face moments */
     long long depout = 0, nonphys = 0;
-#pragma omp parallel for collapse(2) reduction(+ : depout, nonphys) schedule(dynamic, 16)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i <= nx; ++i) {
-            facerec *F = &s->face[(long long)i + (long long)(nx + 1) * j];
-            face_iteration(s, F, 0, i - 1, j, dt, &depout, &nonphys);
-        }
-    if (D == 2) {
-#pragma omp parallel for collapse(2) reduction(+ : depout, nonphys) schedule(dynamic, 16)
-        for (int j = 0; j <= ny; ++j)
-            for (int i = 0; i < nx; ++i) {
-                facerec *F = &s->face[s->nfx + (long long)i + (long long)nx * j];
-                face_iteration(s, F, 1, i, j - 1, dt, &depout, &nonphys);
-            }
+#pragma omp parallel for collapse(3) reduction(+ : depout, nonphys) schedule(dynamic, 16)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i <= nx; ++i)
+                face_iteration(s, &s->face[face_of(s, 0, i - 1, j, k, 1)], 0, i - 1, j, k, dt, &depout, &nonphys);
+    if (D >= 2) {
+#pragma omp parallel for collapse(3) reduction(+ : depout, nonphys) schedule(dynamic, 16)
+        for (int k = 0; k < nz; ++k)
+            for (int j = 0; j <= ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    face_iteration(s, &s->face[face_of(s, 1, i, j - 1, k, 1)], 1, i, j - 1, k, dt, &depout, &nonphys);
+    }
+    if (D == 3) {
+#pragma omp parallel for collapse(3) reduction(+ : depout, nonphys) schedule(dynamic, 16)
+        for (int k = 0; k <= nz; ++k)
+            for (int j = 0; j < ny; ++j)
+                for (int i = 0; i < nx; ++i)
+                    face_iteration(s, &s->face[face_of(s, 2, i, j, k - 1, 1)], 2, i, j, k - 1, dt, &depout, &nonphys);
     }
 
     /* 4. flux into each cell's frame and the co-moving update (Sec. III.B.2) */
-#pragma omp parallel for collapse(2) schedule(static)
-    for (int j = 0; j < ny; ++j)
-        for (int i = 0; i < nx; ++i) {
-            cellrec *c = &s->cell[cidx(s, i, j)];
-            double v[MAXQ][MAXD];
-            velocities(&s->L, c->u, c->T, v);
-            double Ff[MAXQ], Fg[MAXQ];
-            for (int q = 0; q < Q; ++q) Ff[q] = Fg[q] = 0.0;
-            for (int a = 0; a < D; ++a)
-                for (int side = 0; side < 2; ++side) {
-                    /* side 0: face at x_j - dx/2 with outward normal -e_a; side 1: +e_a */
-                    const facerec *F;
-                    if (a == 0)
-                        F = &s->face[(long long)(i + side) + (long long)(nx + 1) * j];
-                    else
-                        F = &s->face[s->nfx + (long long)i + (long long)nx * (j + side)];
-                    tensors Mf, Mg;
-                    unpack(D, 3, F->Mf, &Mf);
-                    unpack(D, 2, F->Mg, &Mg);
-                    double pf[MAXQ], pg[MAXQ];
-                    project_f(&s->L, s->cfg.reg, &Mf, c->u, c->T, pf);
-                    grad_project(&s->L, 2, &Mg, c->u, c->T, pg);
-                    double nsign = side ? 1.0 : -1.0;
-                    for (int q = 0; q < Q; ++q) {
-                        /* (dt/V_j) A_c (v_i . n_c) phi_i = (dt/dx_a) (+-v_ia) phi_i */
-                        Ff[q] += dt / s->dx[a] * nsign * v[q][a] * pf[q];
-                        Fg[q] += dt / s->dx[a] * nsign * v[q][a] * pg[q];
+#pragma omp parallel for collapse(3) schedule(static)
+    for (int k = 0; k < nz; ++k)
+        for (int j = 0; j < ny; ++j)
+            for (int i = 0; i < nx; ++i) {
+                cellrec *c = &s->cell[cidx3(s, i, j, k)];
+                double v[MAXQ][MAXD];
+                velocities(&s->L, c->u, c->T, v);
+                double Ff[MAXQ], Fg[MAXQ];
+                for (int q = 0; q < Q; ++q) Ff[q] = Fg[q] = 0.0;
+                for (int a = 0; a < D; ++a)
+                    for (int side = 0; side < 2; ++side) {
+                        /* side 0: face at x_j - dx/2 with outward normal -e_a; side 1: +e_a */
+                        const facerec *F = &s->face[face_of(s, a, i, j, k, side)];
+                        tensors Mf, Mg;
+                        unpack(D, 3, F->Mf, &Mf);
+                        unpack(D, 2, F->Mg, &Mg);
+                        double pf[MAXQ], pg[MAXQ];
+                        project_f(&s->L, s->cfg.reg, &Mf, c->u, c->T, pf);
+                        grad_project(&s->L, 2, &Mg, c->u, c->T, pg);
+                        double nsign = side ? 1.0 : -1.0;
+                        for (int q = 0; q < Q; ++q) {
+                            /* (dt/V_j) A_c (v_i . n_c) phi_i = (dt/dx_a) (+-v_ia) phi_i */
+                            Ff[q] += dt / s->dx[a] * nsign * v[q][a] * pf[q];
+                            Fg[q] += dt / s->dx[a] * nsign * v[q][a] * pg[q];
+                        }
                     }
+                double eps = dt * c->rho * c->T / s->cfg.mu;
+                double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
+                for (int q = 0; q < Q; ++q) {
+                    c->f[q] = orc_update_relax(c->f[q], c->rho * s->L.W[q], eps) - Ff[q];
+                    c->g[q] = orc_update_relax(c->g[q], geq_coef * s->L.W[q], eps) - Fg[q];
                 }
-            double eps = dt * c->rho * c->T / s->cfg.mu;
-            double geq_coef = (s->Cv - 0.5 * D) * c->T * c->rho;
-            for (int q = 0; q < Q; ++q) {
-                c->f[q] = orc_update_relax(c->f[q], c->rho * s->L.W[q], eps) - Ff[q];
-                c->g[q] = orc_update_relax(c->g[q], geq_coef * s->L.W[q], eps) - Fg[q];
+                /* the updated populations stay in the frame lambda_j(t_n) */
             }
-            /* the updated populations stay in the frame lambda_j(t_n) */
-        }
 
     /* face frames seed the next step's predictor */
-    long long nf = s->nfx + s->nfy, itot = 0, nonc = 0;
+    long long nf = s->nfx + s->nfy + s->nfz, itot = 0, nonc = 0;
     int imax = 0;
-    for (long long k = 0; k < nf; ++k) {
-        facerec *F = &s->face[k];
+    for (long long q = 0; q < nf; ++q) {
+        facerec *F = &s->face[q];
         for (int a = 0; a < D; ++a) F->su[a] = F->u[a];
         F->sT = F->T;
         F->seeded = 1;
@@ -1220,39 +1316,45 @@ int orc_step(orc_sim *s, double t_end, orc_stats *st)
 /* read-out                                                                  */
 /* ------------------------------------------------------------------------- */
 
+/* cell (i, j, k) of the interior, x fastest: its storage record and its output index */
+#define FOR_CELLS(s)                                                                               \
+    for (int kz_ = 0; kz_ < (s)->nz; ++kz_)                                                        \
+        for (int j_ = 0; j_ < (s)->ny; ++j_)                                                       \
+            for (int i_ = 0; i_ < (s)->nx; ++i_)
+#define CELL_OUT(s) ((long long)i_ + (long long)(s)->nx * (j_ + (long long)(s)->ny * kz_))
+#define CELL_REC(s) (&(s)->cell[cidx3((s), i_, j_, kz_)])
+
 void orc_fields(const orc_sim *s, double *rho, double *ux, double *uy, double *T)
 {
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i) {
-            const cellrec *c = &s->cell[cidx(s, i, j)];
-            long long k = (long long)i + (long long)s->nx * j;
-            double r, u[MAXD] = {0, 0}, t;
-            macro(s, c->f, c->g, c->u, c->T, &r, u, &t);
-            rho[k] = r;
-            ux[k] = u[0];
-            if (uy && s->D == 2) uy[k] = u[1];
-            T[k] = t;
-        }
+    FOR_CELLS(s) {
+        const cellrec *c = CELL_REC(s);
+        long long k = CELL_OUT(s);
+        double r, u[MAXD] = {0, 0, 0}, t;
+        macro(s, c->f, c->g, c->u, c->T, &r, u, &t);
+        rho[k] = r;
+        ux[k] = u[0];
+        if (uy && s->D >= 2) uy[k] = u[1];
+        T[k] = t;
+    }
 }
 
 void orc_conserved(const orc_sim *s, double *U)
 {
-    long long n = (long long)s->nx * s->ny;
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i) {
-            const cellrec *c = &s->cell[cidx(s, i, j)];
-            long long k = (long long)i + (long long)s->nx * j;
-            tensors Mf, Mg;
-            moments(&s->L, c->f, c->u, c->T, &Mf);
-            moments(&s->L, c->g, c->u, c->T, &Mg);
-            double tr = 0.0;
-            U[k] = Mf.t0;
-            for (int a = 0; a < s->D; ++a) {
-                U[(1 + a) * n + k] = Mf.t1[a];
-                tr += Mf.t2[a][a];
-            }
-            U[(1 + s->D) * n + k] = 0.5 * tr + Mg.t0;
+    long long n = (long long)s->nx * s->ny * s->nz;
+    FOR_CELLS(s) {
+        const cellrec *c = CELL_REC(s);
+        long long k = CELL_OUT(s);
+        tensors Mf, Mg;
+        moments(&s->L, c->f, c->u, c->T, &Mf);
+        moments(&s->L, c->g, c->u, c->T, &Mg);
+        double tr = 0.0;
+        U[k] = Mf.t0;
+        for (int a = 0; a < s->D; ++a) {
+            U[(1 + a) * n + k] = Mf.t1[a];
+            tr += Mf.t2[a][a];
         }
+        U[(1 + s->D) * n + k] = 0.5 * tr + Mg.t0;
+    }
 }
 
 static void copy_out(const orc_sim *s, const cellrec *c, long long k, long long n, double *f,
@@ -1270,26 +1372,23 @@ static void copy_out(const orc_sim *s, const cellrec *c, long long k, long long 
 
 void orc_populations(const orc_sim *s, double *f, double *g, double *frame)
 {
-    long long n = (long long)s->nx * s->ny;
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i)
-            copy_out(s, &s->cell[cidx(s, i, j)], (long long)i + (long long)s->nx * j, n, f, g, frame);
+    long long n = (long long)s->nx * s->ny * s->nz;
+    FOR_CELLS(s) copy_out(s, CELL_REC(s), CELL_OUT(s), n, f, g, frame);
 }
 
 void orc_reframed(const orc_sim *s, double *f, double *g, double *frame)
 {
-    long long n = (long long)s->nx * s->ny;
-    for (int j = 0; j < s->ny; ++j)
-        for (int i = 0; i < s->nx; ++i) {
-            cellrec tmp;
-            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
-            copy_out(s, &tmp, (long long)i + (long long)s->nx * j, n, f, g, frame);
-        }
+    long long n = (long long)s->nx * s->ny * s->nz;
+    FOR_CELLS(s) {
+        cellrec tmp;
+        reframe_cell(s, CELL_REC(s), &tmp);
+        copy_out(s, &tmp, CELL_OUT(s), n, f, g, frame);
+    }
 }
 
 void orc_face_frames(const orc_sim *s, double *out)
 {
-    long long nf = s->nfx + s->nfy;
+    long long nf = s->nfx + s->nfy + s->nfz;
     for (long long k = 0; k < nf; ++k) {
         for (int a = 0; a < s->D; ++a) out[k * (s->D + 1) + a] = s->face[k].su[a];
         out[k * (s->D + 1) + s->D] = s->face[k].sT;
@@ -1298,7 +1397,7 @@ void orc_face_frames(const orc_sim *s, double *out)
 
 void orc_set_face_frames(orc_sim *s, const double *in)
 {
-    long long nf = s->nfx + s->nfy;
+    long long nf = s->nfx + s->nfy + s->nfz;
     for (long long k = 0; k < nf; ++k) {
         for (int a = 0; a < s->D; ++a) s->face[k].su[a] = in[k * (s->D + 1) + a];
         s->face[k].sT = in[k * (s->D + 1) + s->D];
@@ -1310,7 +1409,7 @@ void orc_face_moments(const orc_sim *s, double *Mf, double *Mg)
 {
     const int D = s->D;
     const int nf3 = 1 + D + D * D + D * D * D, ng2 = 1 + D + D * D;
-    long long nf = s->nfx + s->nfy;
+    long long nf = s->nfx + s->nfy + s->nfz;
     for (long long k = 0; k < nf; ++k) {
         for (int q = 0; q < nf3; ++q) Mf[k * nf3 + q] = s->face[k].Mf[q];
         for (int q = 0; q < ng2; ++q) Mg[k * ng2 + q] = s->face[k].Mg[q];
@@ -1319,6 +1418,6 @@ void orc_face_moments(const orc_sim *s, double *Mf, double *Mg)
 
 void orc_face_iters(const orc_sim *s, int *out)
 {
-    long long nf = s->nfx + s->nfy;
+    long long nf = s->nfx + s->nfy + s->nfz;
     for (long long k = 0; k < nf; ++k) out[k] = s->face[k].iters;
 }

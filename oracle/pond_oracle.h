@@ -55,6 +55,12 @@ typedef struct {
     double bc_param[4][4];/* geometry parameters                      */
     int reg;              /* ORC_REG_*                                */
     int scheme;           /* ORC_SCHEME_*                             */
+    /* 3D (dim 3, D3Q64): cells along z, the z extent, and the kinds of the two z sides
+     * (bottom, top); 3D takes the periodic, outflow and reflecting kinds only, and the
+     * Grad projection of the finite-volume scheme */
+    int nz;
+    double z0, z1;
+    int bc_z[2];
 } orc_config;
 
 typedef struct {
@@ -73,7 +79,8 @@ typedef struct orc_sim orc_sim;
  * orc_grad_project, order 3) into frame {u, T}: f has Q entries */
 void orc_eq_project(int dim, const double *M, const double *u, double T, double *f);
 
-/* lattice of Table I: D1Q4 (dim 1) or D2Q16 (dim 2). c: Q*dim, W: Q. returns Q */
+/* lattice of Table I: D1Q4 (dim 1) or D2Q16 (dim 2), and its tensor product D3Q64 (dim 3).
+ * c: Q*dim, W: Q. returns Q */
 int orc_lattice(int dim, double *c, double *W);
 
 /* lab-frame moment tensors M_0..M_order of populations f expressed in frame (u, T);
@@ -95,6 +102,9 @@ double orc_update_relax(double ftilde, double feq, double eps);
 
 orc_sim *orc_create(const orc_config *cfg, const double *rho, const double *ux,
                     const double *uy, const double *p);
+/* the same with the z velocity (3D; uz may be NULL in 1D and 2D) */
+orc_sim *orc_create3(const orc_config *cfg, const double *rho, const double *ux,
+                     const double *uy, const double *uz, const double *p);
 void orc_destroy(orc_sim *s);
 
 /* advance one step (dt clipped so that t does not pass t_end); returns 0 on success,

@@ -28,13 +28,71 @@ def base_config(dim, nx, ny=1, x0=0.0, x1=1.0, y0=0.0, y1=1.0, gamma=1.4, cfl=0.
                 bc=("outflow", "outflow", "outflow", "outflow")):
     z = [[0.0] * 4 for _ in range(4)]
     return {
-        "dim": dim, "nx": nx, "ny": ny if dim == 2 else 1,
+        "dim": dim, "nx": nx, "ny": ny if dim >= 2 else 1,
         "x0": x0, "x1": x1, "y0": y0, "y1": y1,
         "gamma": gamma, "cfl": cfl, "mu": mu, "tol": tol, "max_iter": max_iter,
         "limiter": limiter, "bc": list(bc),
         "bc_state": [list(r) for r in z], "bc_alt": [list(r) for r in z],
         "bc_param": [list(r) for r in z],
     }
+
+
+def base_config_3d(nx, ny, nz, x0=0.0, x1=1.0, y0=0.0, y1=1.0, z0=0.0, z1=1.0, bc=("periodic",) * 6,
+                   **kw):
+    """A 3D box (D3Q64): sides west, east, south, north, bottom, top; the periodic, outflow
+    and reflecting kinds."""
+    cfg = base_config(3, nx, ny, x0=x0, x1=x1, y0=y0, y1=y1, bc=tuple(bc[:4]), **kw)
+    cfg["nz"], cfg["z0"], cfg["z1"] = nz, z0, z1
+    cfg["bc"] = list(bc)
+    return cfg
+
+
+def cell_centres_3d(cfg):
+    """X, Y, Z of every cell, index i + nx (j + ny k)."""
+    ax = []
+    for n, a, b in (("nx", "x0", "x1"), ("ny", "y0", "y1"), ("nz", "z0", "z1")):
+        h = (cfg[b] - cfg[a]) / cfg[n]
+        ax.append(cfg[a] + (np.arange(cfg[n]) + 0.5) * h)
+    Z, Y, X = np.meshgrid(ax[2], ax[1], ax[0], indexing="ij")
+    return X.ravel(), Y.ravel(), Z.ravel()
+
+
+def random_smooth_3d(nx, ny, nz, seed=0, amp=0.3, bc="periodic", **kw):
+    """Periodic, smooth random fields in a unit box (a few Fourier modes per field)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    cfg = base_config_3d(nx, ny, nz, bc=(bc,) * 6, **kw)
+    X, Y, Z = cell_centres_3d(cfg)
+
+    def field(base, a):
+        out = np.full(X.shape, base, dtype=np.float64)
+        for _ in range(3):
+            k = rng.integers(0, 3, 3)
+            k[rng.integers(0, 3)] += 1
+            ph = rng.uniform(0, 2 * np.pi)
+            out += a * rng.uniform(-1, 1) * np.sin(2 * np.pi * (k[0] * X + k[1] * Y + k[2] * Z) + ph)
+        return out
+
+    cfg["name"] = "random_smooth_3d"
+    return cfg, {"rho": field(1.0, amp), "ux": field(0.0, amp), "uy": field(0.0, amp),
+                 "uz": field(0.0, amp), "p": field(1.0, amp)}
+
+
+def riemann_3d(left, right, axis=0, n=100, nt=2, xi=0.5, gamma=1.4, cfl=0.5, mu=1e-3,
+               tol=TOL_PARITY, max_iter=32):
+    """A 1D Riemann problem along `axis` (0, 1, 2) of a 3D box: n cells of [0, 1] along it,
+    outflow at its ends; nt cells (periodic) across; left = (rho, u_n, p) below xi."""
+    ns = [nt, nt, nt]
+    ns[axis] = n
+    bc = ["periodic"] * 6
+    bc[2 * axis], bc[2 * axis + 1] = "outflow", "outflow"
+    cfg = base_config_3d(*ns, bc=bc, gamma=gamma, cfl=cfl, mu=mu, tol=tol, max_iter=max_iter)
+    C = cell_centres_3d(cfg)[axis]
+    L = C < xi
+    vel = [np.zeros(C.size) for _ in range(3)]
+    vel[axis] = np.where(L, left[1], right[1]).astype(np.float64)
+    cfg["name"] = "riemann_3d"
+    return cfg, {"rho": np.where(L, left[0], right[0]).astype(np.float64), "ux": vel[0],
+                 "uy": vel[1], "uz": vel[2], "p": np.where(L, left[2], right[2]).astype(np.float64)}
 
 
 def cell_centres(cfg):

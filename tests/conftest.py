@@ -19,6 +19,10 @@ def orc():
     import oracle
 
     oracle._load()
+    if os.environ.get("PYTEST_XDIST_WORKER"):
+        # parallel test workers share the cores: one oracle thread each, or the OpenMP
+        # teams of several workers spin against each other
+        oracle.set_num_threads(1)
     return oracle
 
 

@@ -1,0 +1,222 @@
+"""Pins of the oracle's three-dimensional step: the finite-volume scheme of Sec. III.B on
+the D3Q64 lattice (the tensor product of three D1Q4 rules, Sec. II.A), with the
+third-order Grad projection of Sec. II.C (20 moments, q = 20).
+
+Checked against what fixes it independently of its own arithmetic: a uniform state is a
+fixed point, the update conserves on a periodic box, the step commutes with a cyclic
+exchange of the axes and with a mirror, a state that varies along one axis stays uniform
+across, a Riemann problem along any axis converges to the exact solution, and the face
+state of a linearly varying density has a closed form (which catches a dropped tangential
+term or a slope over the wrong spacing; both mutations were checked to fail it). The
+lattice and projection pins are in the building-block tests."""
+import numpy as np
+import pytest
+
+import exact_riemann as ER
+from paper_2203_05477_amd import workloads as W
+
+
+def _sim(orc, cfg, f):
+    return orc.Sim(cfg, f["rho"], f["ux"], f["uy"], f["p"], uz=f["uz"])
+
+
+def _prims(s):
+    U = s.conserved()
+    r = U[0]
+    u = U[1:4] / r
+    T = (U[4] / r - 0.5 * (u * u).sum(axis=0)) / s.cv
+    return r, u, T
+
+
+def test_uniform_flow_stays_uniform_any_seed(orc):
+    """Uniform (rho, u, T) in a periodic box is a fixed point whatever the face seeds are."""
+    cfg = W.base_config_3d(6, 5, 4, tol=1e-13)
+    n = 6 * 5 * 4
+    f = {"rho": np.full(n, 1.3), "ux": np.full(n, 0.3), "uy": np.full(n, -0.2),
+         "uz": np.full(n, 0.45), "p": np.full(n, 0.7)}
+    s = _sim(orc, cfg, f)
+    s.cv = 1.0 / (cfg["gamma"] - 1.0)
+    s.step()
+    rng = np.random.default_rng(0)
+    fr = s.face_frames()
+    fr[:, :3] += rng.uniform(-0.5, 0.5, (fr.shape[0], 3))
+    fr[:, 3] *= rng.uniform(0.5, 2.0, fr.shape[0])
+    s.set_face_frames(fr)
+    for _ in range(3):
+        s.step()
+    r, u, T = _prims(s)
+    assert np.abs(r - 1.3).max() < 1e-13
+    assert np.abs(u[0] - 0.3).max() < 1e-13
+    assert np.abs(u[1] + 0.2).max() < 1e-13
+    assert np.abs(u[2] - 0.45).max() < 1e-13
+    assert np.abs(T - 0.7 / 1.3).max() < 1e-13
+
+
+def test_periodic_conservation(orc):
+    """On a periodic box the totals of rho, the three momenta and rho E stay constant to
+    round-off (every face flux leaves one cell and enters its neighbour)."""
+    cfg, f = W.random_smooth_3d(8, 6, 5, seed=3, cfl=0.3, tol=1e-12)
+    s = _sim(orc, cfg, f)
+    U0 = s.conserved().sum(axis=1)
+    for _ in range(6):
+        s.step()
+    U = s.conserved()
+    assert np.all(np.abs(U.sum(axis=1) - U0) <= 1e-13 * np.abs(U).sum(axis=1))
+    assert np.abs(U - orc.Sim(cfg, f["rho"], f["ux"], f["uy"], f["p"], uz=f["uz"]).conserved()).max() > 1e-3
+
+
+def _cycle(a, shape):
+    """(x, y, z) -> (y, z, x): the new x axis is the old y axis, etc.; index i + nx (j + ny k)."""
+    nx, ny, nz = shape
+    return np.transpose(a.reshape(nz, ny, nx), (2, 0, 1)).ravel()
+
+
+def test_cyclic_axis_exchange(orc):
+    """Renaming the axes (x, y, z) -> (y, z, x) -- grid sizes, fields, velocity components
+    and side kinds together -- renames the solution the same way (a transposed operand or
+    a wrong tangential axis in any of the three face directions breaks this)."""
+    shape = (7, 6, 5)
+    cfg, f = W.random_smooth_3d(*shape, seed=4, tol=1e-13)
+    cfg["bc"] = ["outflow", "outflow", "periodic", "periodic", "reflect", "reflect"]
+    s = _sim(orc, cfg, f)
+    cfgc = W.base_config_3d(6, 5, 7, tol=1e-13,
+                            bc=("periodic", "periodic", "reflect", "reflect", "outflow", "outflow"))
+    cy = lambda a: _cycle(a, shape)  # noqa: E731
+    fc = {"rho": cy(f["rho"]), "ux": cy(f["uy"]), "uy": cy(f["uz"]), "uz": cy(f["ux"]),
+          "p": cy(f["p"])}
+    sc = _sim(orc, cfgc, fc)
+    for _ in range(4):
+        s.step()
+        sc.step()
+    assert s.t == pytest.approx(sc.t, rel=1e-13)
+    U, Uc = s.conserved(), sc.conserved()
+    for q, qc in ((0, 0), (1, 3), (2, 1), (3, 2), (4, 4)):
+        assert np.abs(cy(U[q]) - Uc[qc]).max() < 1e-12 * np.abs(U[q]).max()
+
+
+def test_mirror_symmetry(orc):
+    """A state symmetric under z -> -z (u_z odd, the rest even) between reflecting walls
+    stays symmetric."""
+    cfg = W.base_config_3d(5, 4, 10, z0=-1.0, z1=1.0, tol=1e-13,
+                           bc=("periodic",) * 4 + ("reflect", "reflect"))
+    X, Y, Z = W.cell_centres_3d(cfg)
+    f = {"rho": 1.0 + 0.5 * np.exp(-8 * Z ** 2) + 0.1 * np.sin(2 * np.pi * X),
+         "ux": 0.2 * np.cos(2 * np.pi * Y) * np.cos(np.pi * Z),
+         "uy": 0.1 * np.sin(2 * np.pi * X),
+         "uz": 0.3 * np.sin(np.pi * Z),
+         "p": 1.0 + 0.2 * np.exp(-8 * Z ** 2)}
+    s = _sim(orc, cfg, f)
+    for _ in range(4):
+        s.step()
+    U = s.conserved()
+    m = lambda a: a.reshape(10, 4, 5)[::-1].ravel()  # noqa: E731
+    for q, sign in ((0, 1), (1, 1), (2, 1), (3, -1), (4, 1)):
+        assert np.abs(U[q] - sign * m(U[q])).max() < 1e-12 * np.abs(U[q]).max()
+
+
+def test_one_dimensional_state_stays_one_dimensional(orc):
+    """A Riemann problem along x in a box periodic across stays uniform across, with no
+    transverse momentum beyond round-off."""
+    cfg, f = W.riemann_3d((1.0, 0.0, 1.0), (0.125, 0.0, 0.1), axis=0, n=40, nt=3, tol=1e-13)
+    s = _sim(orc, cfg, f)
+    for _ in range(6):
+        s.step()
+    U = s.conserved()
+    R = U[0].reshape(3, 3, 40)
+    assert np.abs(R - R[0, 0]).max() < 1e-13
+    assert np.abs(U[2]).max() < 1e-13 and np.abs(U[3]).max() < 1e-13
+
+
+def _riemann_l1(orc, axis, n):
+    left, right = (1.0, 0.0, 1.0), (0.125, 0.0, 0.1)
+    cfg, f = W.riemann_3d(left, right, axis=axis, n=n, nt=2, tol=1e-10)
+    s = _sim(orc, cfg, f)
+    while s.t < 0.2 * (1 - 1e-12):
+        s.step(0.2)
+    U = s.conserved()
+    shape = [2, 2, 2]
+    shape[2 - axis] = n  # array axes are (z, y, x)
+    line = [np.moveaxis(U[q].reshape(shape), 2 - axis, 0)[:, 0, 0] for q in (0, 1 + axis, 4)]
+    ex = ER.cell_average(left, right, 1.4, np.linspace(0, 1, n + 1), 0.5, 0.2)
+    return np.array([np.abs(line[k] - ex[k]).sum() / np.abs(ex[k]).sum() for k in range(3)]), line, s
+
+
+def test_riemann_problem_along_each_axis_converges(orc):
+    """Sod's problem along x, y or z (two periodic cells across) against the exact Riemann
+    solution: the relative L1 error of rho, rho u_n and rho E falls from 50 to 100 to 200
+    cells and is small at 200; the three directions give the same profile to round-off."""
+    errs = [_riemann_l1(orc, 0, n)[0] for n in (50, 100)]
+    e200, line0, s = _riemann_l1(orc, 0, 200)
+    assert np.all(errs[1] < errs[0]) and np.all(e200 < errs[1])
+    assert np.all(e200 < [0.03, 0.08, 0.03])
+    assert s.t == pytest.approx(0.2, abs=1e-14)
+    for axis in (1, 2):
+        e, line, _ = _riemann_l1(orc, axis, 200)
+        for k in range(3):
+            assert np.abs(line[k] - line0[k]).max() < 1e-12 * np.abs(line0[k]).max()
+
+
+@pytest.mark.parametrize("dim", [2, 3])
+def test_face_state_of_a_linear_density_is_closed_form(orc, dim):
+    """Closed form of the face state (Sec. III.B.3) for equilibrium cells of one velocity u
+    and temperature T whose density is linear in space: every population of every stencil
+    cell, expressed in any frame, is linear in space, so the limited reconstruction at the
+    departure point x_b - v_i dt/2 is exact, and the conserved moments of the face state are
+    moments of a Maxwellian weighted by rho(x_b - v dt/2):
+      rho_b  = rho(x_b) - h grad(rho).u
+      m_b,a  = rho(x_b) u_a - h sum_c d_c rho (T delta_ac + u_a u_c)
+      E_b    = rho(x_b) (u^2/2 + C_v T) - h sum_c d_c rho u_c (u^2/2 + (D/2 + 1) T + (C_v - D/2) T)
+    with h = dt/2; the face recovery keeps them (its equilibrium has the same moments). A
+    dropped tangential term of the departure point or a slope over the wrong spacing breaks
+    this on the faces whose stencils lie inside the domain."""
+    D = dim
+    shape = (8, 7, 6)[:D]
+    grad = np.array([0.3, 0.2, -0.25])[:D]
+    u = np.array([0.3, -0.2, 0.4])[:D]
+    T = 0.9
+    if D == 3:
+        cfg = W.base_config_3d(*shape, bc=("outflow",) * 6, tol=1e-13, cfl=0.4)
+        C = W.cell_centres_3d(cfg)
+    else:
+        cfg = W.base_config(2, *shape, tol=1e-13, cfl=0.4)
+        C = W.cell_centres(cfg)
+    rho_of = lambda X: 1.0 + sum(grad[a] * X[a] for a in range(D))  # noqa: E731
+    rho = rho_of(C)
+    n = rho.size
+    vel = [np.full(n, u[a]) for a in range(D)] + [np.zeros(n)] * (3 - D)
+    s = orc.Sim(cfg, rho, vel[0], vel[1], rho * T, uz=vel[2] if D == 3 else None)
+    s.step()
+    h = 0.5 * s.last["dt"]
+    Cv = 1.0 / (cfg["gamma"] - 1.0)
+    Mf, Mg = s.face_moments()
+    u2 = float(u @ u)
+    dxs = [1.0 / m for m in shape]
+    nf = [0]
+    checked = 0
+    for axis in range(D):
+        fshape = list(shape)
+        fshape[axis] += 1
+        for idx in np.ndindex(*fshape[::-1]):
+            ijk = idx[::-1]  # face index (i, j, k): x fastest
+            lin = 0
+            for a in reversed(range(D)):
+                lin = lin * fshape[a] + ijk[a]
+            f = nf[-1] + lin
+            inside = all((2 <= ijk[a] <= shape[a] - 2) if a == axis else (1 <= ijk[a] <= shape[a] - 2)
+                         for a in range(D))
+            if not inside:
+                continue
+            xb = [(ijk[a] if a == axis else ijk[a] + 0.5) * dxs[a] for a in range(D)]
+            rb = rho_of(xb)
+            gu = float(grad @ u)
+            r_ref = rb - h * gu
+            m_ref = rb * u - h * (T * grad + u * gu)
+            E_ref = rb * (0.5 * u2 + Cv * T) - h * gu * (0.5 * u2 + (0.5 * D + 1.0) * T + (Cv - 0.5 * D) * T)
+            M2 = Mf[f, 1 + D:1 + D + D * D].reshape(D, D)
+            E = 0.5 * np.trace(M2) + Mg[f, 0]
+            assert Mf[f, 0] == pytest.approx(r_ref, rel=1e-12, abs=1e-13)
+            assert np.allclose(Mf[f, 1:1 + D], m_ref, rtol=1e-12, atol=1e-13)
+            assert E == pytest.approx(E_ref, rel=1e-12)
+            checked += 1
+        nf.append(nf[-1] + int(np.prod(fshape)))
+    assert checked >= (12 if D == 2 else 30)

@@ -31,11 +31,35 @@ def test_table1_nodes_and_weights(orc):
     for ci, wi in zip(c, W):
         expect = w_inner if abs(ci * ci - n2[0]) < 1e-12 else w_outer
         assert wi == pytest.approx(expect, abs=1e-15)
-    # D2Q16 weights are products (Sec. II.A)
+    # D2Q16 weights are products (Sec. II.A), and so are those of its 3D analogue D3Q64
     c2, W2 = orc.lattice(2)
     for i in range(16):
         assert W2[i] == pytest.approx(W[i % 4] * W[i // 4], abs=1e-16)
         assert c2[i, 0] == c[i % 4] and c2[i, 1] == c[i // 4]
+    c3, W3 = orc.lattice(3)
+    assert len(W3) == 64
+    for i in range(64):
+        ix, iy, iz = i % 4, (i // 4) % 4, i // 16
+        assert W3[i] == pytest.approx(W[ix] * W[iy] * W[iz], abs=1e-16)
+        assert (c3[i, 0], c3[i, 1], c3[i, 2]) == (c[ix], c[iy], c[iz])
+
+
+def test_d3q64_mixed_moments_are_normal_moments(orc):
+    """D3Q64 integrates every monomial c_x^a c_y^b c_z^c with a, b, c <= 7 like the standard
+    normal distribution in 3D (product of 1D moments, numpy's probabilists' Gauss-Hermite
+    rule as the independent reference); a degree-8 power along one axis is not exact."""
+    c, W = orc.lattice(3)
+    x, w = np.polynomial.hermite_e.hermegauss(4)
+    w = w / w.sum()
+    normal = [1, 0, 1, 0, 3, 0, 15, 0]
+    for a in range(8):
+        for b in range(8 - a):
+            for cc in range(8 - a - b):
+                s = np.sum(W * c[:, 0] ** a * c[:, 1] ** b * c[:, 2] ** cc)
+                assert s == pytest.approx(normal[a] * normal[b] * normal[cc], abs=1e-12)
+                ref = np.sum(w * x ** a) * np.sum(w * x ** b) * np.sum(w * x ** cc)
+                assert s == pytest.approx(ref, abs=1e-12)
+    assert abs(np.sum(W * c[:, 2] ** 8) - 105.0) > 1.0
 
 
 def test_gauss_hermite_exactness(orc):
@@ -65,7 +89,7 @@ def orc_W(dim):
     return _WCACHE[dim]
 
 
-@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2, 3])
 @pytest.mark.parametrize("order", [2, 3])
 def test_grad_moment_invariance(orc, dim, order):
     """Defining condition of the regularized transformation (Sec. II.C): the projected
@@ -85,7 +109,7 @@ def test_grad_moment_invariance(orc, dim, order):
         assert np.abs(M1 - M).max() <= 1e-12 * scale
 
 
-@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2, 3])
 def test_grad_does_not_keep_fourth_moment(orc, dim):
     """A plausible wrong projection keeps all populations (identity). Grad order 2 must
     lose M_3 in general, and order 3 must reproduce only up to M_3."""
@@ -96,9 +120,10 @@ def test_grad_does_not_keep_fourth_moment(orc, dim):
     M3 = orc.moments(dim, 3, f, u, T)
     g2 = orc.grad_project(dim, 2, M3[: orc.nmom(dim, 2)], u, T)
     assert np.abs(orc.moments(dim, 3, g2, u, T) - M3).max() > 1e-3
-    if dim == 2:
+    if dim >= 2:
         g3 = orc.grad_project(dim, 3, M3, u, T)
-        assert np.abs(g3 - f).max() > 1e-4  # 16 populations, 10 moments: not the identity
+        # 16 populations and 10 moments (64 and 20 in 3D): not the identity
+        assert np.abs(g3 - f).max() > 1e-4
 
 
 def test_d1q4_grad_equals_vandermonde_solve(orc):
@@ -118,12 +143,12 @@ def test_d1q4_grad_equals_vandermonde_solve(orc):
         assert np.abs(f - f_ref).max() <= 1e-11 * np.abs(f_ref).max()
 
 
-@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2, 3])
 def test_equilibrium_is_fixed_point(orc, dim):
     """In its own co-moving frame the equilibrium rho W_i (Sec. II.B) has a1 = a2 = a3 = 0,
     so its projection is rho W_i itself."""
     c, W = orc.lattice(dim)
-    rho, u, T = 1.7, np.array([0.4, -0.9])[:dim], 0.6
+    rho, u, T = 1.7, np.array([0.4, -0.9, 0.25])[:dim], 0.6
     f = rho * W
     M = orc.moments(dim, 3, f, u, T)
     a = orc.grad_coefficients(dim, 3, M, u, T)
@@ -132,9 +157,15 @@ def test_equilibrium_is_fixed_point(orc, dim):
     # the equilibrium's moments are those of a Maxwellian: M2 = rho (T I + u u)
     M2 = M[1 + dim: 1 + dim + dim * dim].reshape(dim, dim)
     assert np.allclose(M2, rho * (T * np.eye(dim) + np.outer(u, u)), atol=1e-13)
+    # and M3 = rho (u u u + T (u_a d_bc + u_b d_ac + u_c d_ab))
+    I = np.eye(dim)
+    M3 = M[1 + dim + dim * dim:].reshape(dim, dim, dim)
+    M3_ref = rho * (np.einsum("a,b,c->abc", u, u, u) + T * (np.einsum("a,bc->abc", u, I)
+                    + np.einsum("b,ac->abc", u, I) + np.einsum("c,ab->abc", u, I)))
+    assert np.allclose(M3, M3_ref, atol=1e-13)
 
 
-@pytest.mark.parametrize("dim", [1, 2])
+@pytest.mark.parametrize("dim", [1, 2, 3])
 def test_grad_round_trip_and_idempotence(orc, dim):
     """Projecting Grad-form data back into its own frame returns it unchanged, and a
     round trip lambda -> lambda' -> lambda keeps the moments up to order 3."""
