@@ -209,6 +209,63 @@ def other_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def box3d_workload(args):
+    """The explosion in a closed box on the D3Q64 lattice (n^3 cells, reflecting walls),
+    mixed and FP64 forms from the same state: converged cell-updates per second over the
+    timed steps, the kernels' HIP-event times, and the oracle on a bounded sample."""
+    import oracle
+    from paper_2203_05477_amd import pond
+    from paper_2203_05477_amd import workloads as W
+    import torch
+
+    pond.load()
+    n = args.n3
+    out = {}
+    for prec, tol in (("mixed", W.TOL_FP32), ("fp64", W.TOL_FP64)):
+        if prec == "fp64" and args.no_fp64:
+            continue
+        cfg, fields = W.explosion_box_3d(n, tol=tol)
+        ctx = pond.Context(cfg, fields, precision=prec)
+        if args.warmup:
+            ctx.step(args.warmup, check=False)
+        ctx.enable_timing(True)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = ctx.step(args.steps, check=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        kt = ctx.kernel_times()
+        out[prec] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
+                     "cell_updates": st["cell_updates"], "faces": st["faces"],
+                     "mean_iters": st["iters_total"] / max(st["faces"], 1), "iters_max": st["iters_max"],
+                     "nonconverged": st["nonconverged"], "status": st["status"],
+                     "kernel_ms": {"dt": kt["dt"], "plus_and_faces": kt["face"], "cell": kt["cell"]}}
+        ctx.close()
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = 48
+        cfg, fields = W.explosion_box_3d(m, tol=W.TOL_FP64)
+        sim = oracle.Sim(cfg, fields["rho"], fields["ux"], fields["uy"], fields["p"], uz=fields["uz"])
+        t0 = time.perf_counter()
+        sim.step()
+        el = time.perf_counter() - t0
+        cpu = {"value": m ** 3 / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+               "kind": "oracle", "cpu_model": cpu_model(),
+               "sample": f"one step of the same set-up on {m}^3 cells from t=0 (FP64); {el:.1f} s"}
+    m = out["mixed"]
+    line = {
+        "metric": METRIC, "value": m["value"], "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": f"explosion_box_3d_{n}^3", "lattice": "D3Q64",
+                   "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
+        "roofline": None,
+        "mixed": m, "fp64_plain": out.get("fp64"), "cpu_baseline": cpu,
+    }
+    print(json.dumps(line), flush=True)
+
+
 # Algorithmic HBM bytes of one 1D cell-update with the Hermite-coefficient state (read the
 # state, write it: FP64 U (3 x 8 B) and 4 non-equilibrium coefficients, mixed 4 x 4 B), for a
 # step done in one pass, and the extra of a step split into a face pass and a cell pass (the
@@ -680,6 +737,7 @@ def main():
                     help="skip the single-thread oracle step of the CPU baseline")
     ap.add_argument("--nx", type=int, default=1920)
     ap.add_argument("--ny", type=int, default=480)
+    ap.add_argument("--n3", type=int, default=128, help="box3d: cells per axis")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp64", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
@@ -688,7 +746,7 @@ def main():
                     help="face tile BXxBY for both forms instead of the autotuner's choice")
     ap.add_argument("--workload", default="double_mach",
                     choices=["double_mach", "shocked_interface", "jet", "tubes", "riemann_1d",
-                             "explosion_box"],
+                             "explosion_box", "box3d"],
                     help="the benchmark's workload (default: the headline double Mach reflection)")
     ap.add_argument("--scheme", choices=["fv", "sl"], default="fv",
                     help="1D workloads (tubes, riemann_1d): the finite-volume scheme or the "
@@ -730,6 +788,9 @@ def main():
         sys.exit(2)
     if args.workload == "riemann_1d":
         riemann_workload(args)
+        return
+    if args.workload == "box3d":
+        box3d_workload(args)
         return
     if args.workload != "double_mach":
         other_workload(args)

@@ -15,7 +15,8 @@
  * Conventions for every entry point:
  *   - units with gas constant 1 (p = rho T) and lattice temperature T_L = 1;
  *     C_v = 1/(gamma - 1); tau = mu / p (Prandtl number 1);
- *   - cell fields are plain arrays in x-fastest order (index i + nx*j);
+ *   - cell fields are plain arrays in x-fastest order (index i + nx*j, in 3D
+ *     i + nx*(j + ny*k));
  *   - host pointers are caller-owned and only read or written during the call;
  *   - device memory is owned by the context; no entry point retains a caller pointer;
  *   - on an error the context keeps the state of the last completed step;
@@ -32,7 +33,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 3
+#define POND_ABI_VERSION 4
 
 typedef enum {
     POND_OK = 0,
@@ -46,7 +47,8 @@ typedef enum {
     POND_ESTATE = 7    /* call not valid in the context's state                  */
 } pond_status;
 
-/* boundary kinds, one per side: west, east, south, north (Sec. IV) */
+/* boundary kinds, one per side: west, east, south, north (Sec. IV); in 3D also bottom and
+ * top (bc_z), where only the periodic, outflow and reflecting kinds are taken */
 enum {
     POND_BC_PERIODIC = 0,
     POND_BC_OUTFLOW = 1,             /* zero gradient: ghost = nearest interior cell      */
@@ -85,7 +87,9 @@ enum {
 /* Problem statement (paper Sec. IV: initial fields on a uniform grid, gamma, CFL,
  * viscosity, boundary conditions). Caller-owned, copied by pond_init. */
 typedef struct {
-    int32_t dim;            /* 1 (D1Q4 lattice) or 2 (D2Q16 lattice), Table I          */
+    int32_t dim;            /* 1 (D1Q4 lattice) or 2 (D2Q16 lattice), Table I; 3: the   */
+                            /* D3Q64 tensor product of D1Q4 (Sec. II.A), 20 moments of  */
+                            /* f in the Grad projection (Sec. II.C); pond_init3 only    */
     int32_t nx, ny;         /* cells; in 1D nx is the total over all instances, ny = 1 */
     int32_t n_inst;         /* 1D only: number of independent tubes (>= 1)              */
     const int32_t *len;     /* 1D only: cells per tube (n_inst values, each >= 4), or  */
@@ -104,6 +108,16 @@ typedef struct {
     double bc_state[4][4];  /* per side: rho, ux, uy, p                                 */
     double bc_alt[4][4];    /* second state of the window and moving-shock kinds       */
     double bc_param[4][4];  /* geometry of the window, split and moving-shock kinds     */
+    /* 3D only (read when dim == 3): cells along z, the z extent, and the kinds of the
+     * bottom and top sides. A 3D context takes the periodic, outflow and reflecting kinds
+     * on all six sides, the Grad projection and the finite-volume scheme, the previous
+     * face frame as seed (flags 0 or POND_FLAG_STRICT, seed_mode POND_SEED_PREV), and
+     * gamma <= 5/3 (C_v >= 3/2); the launch-control calls of the 2D face tiles, the tail
+     * hand-over and the resident launch do not apply (POND_EINVAL), pond_autotune leaves a
+     * 3D context unchanged. */
+    int32_t nz;
+    double z0, z1;
+    int32_t bc_z[2];
 } pond_config;
 
 /* Counters of the steps taken by one pond_step call (all instances together). */
@@ -127,7 +141,7 @@ typedef struct {
      * conserved variables), from one extra pass over cells and faces: */
     double rho_min;                 /* smallest cell density                           */
     double T_min;                   /* smallest cell temperature                       */
-    double totals[4];               /* sum over all cells of the conserved variables   */
+    double totals[5];               /* sum over all cells of the conserved variables   */
                                     /* times the cell volume: mass, momentum (dim       */
                                     /* values), energy; unused entries 0                */
     int32_t first_failed_instance;  /* lowest instance that failed in this call, or -1 */
@@ -146,6 +160,10 @@ typedef struct pond_ctx pond_ctx;
  * uy may be NULL in 1D. rho and p must be positive and finite. On error *out = NULL. */
 pond_status pond_init(const pond_config *cfg, const double *rho, const double *ux,
                       const double *uy, const double *p, pond_ctx **out);
+/* The same with the z velocity, for every dimension (uz is read in 3D only and may be
+ * NULL in 1D and 2D); host arrays of nx*ny*nz values in 3D. pond_init refuses dim 3. */
+pond_status pond_init3(const pond_config *cfg, const double *rho, const double *ux,
+                       const double *uy, const double *uz, const double *p, pond_ctx **out);
 
 /* Advance every instance by up to nsteps steps of Sec. III.B.4, each with dt = cfl / max
  * rate of its cells (Sec. IV), the last one clipped so that no instance passes t_end (pass
@@ -159,16 +177,16 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
 pond_status pond_step(pond_ctx *ctx, int32_t nsteps, double t_end, pond_stats *st);
 
 /* Cell fields rho, ux, uy, T computed from the conserved variables (Sec. II.B: u = rho u /
- * rho, T = (E - u^2/2) / C_v); host arrays of nx*ny; uy may be NULL. Synchronizes the
- * stream. */
+ * rho, T = (E - u^2/2) / C_v); host arrays of nx*ny (nx*ny*nz in 3D, whose z velocity is
+ * in pond_conserved); uy may be NULL. Synchronizes the stream. */
 pond_status pond_moments(const pond_ctx *ctx, double *rho, double *ux, double *uy, double *T);
 
 /* Same fields (Sec. II.B) written to a caller-owned device buffer of 4*nx*ny doubles
  * (planes rho, ux, uy, T) on the context's stream; does not synchronize. */
 pond_status pond_moments_device(const pond_ctx *ctx, double *dev_out);
 
-/* Conserved variables (rho, rho u_x[, rho u_y], rho E) of Sec. II.B, the moments the
- * finite-volume update of Sec. III.B.2 conserves: (dim+2) planes of nx*ny. */
+/* Conserved variables (rho, rho u_x[, rho u_y[, rho u_z]], rho E) of Sec. II.B, the moments
+ * the finite-volume update of Sec. III.B.2 conserves: (dim+2) planes of the cell count. */
 pond_status pond_conserved(const pond_ctx *ctx, double *U);
 
 /* Populations f~, g~ (the carried variables of Sec. III.B.1, in the Grad form of
@@ -178,7 +196,10 @@ pond_status pond_populations(const pond_ctx *ctx, double *f, double *g, double *
 
 /* Number of faces x_b (the cell interfaces of Sec. III.B.3): 1D: nx + n_inst; 2D: (nx+1)*ny
  * x-faces followed by nx*(ny+1) y-faces (x-face (i,j) lies between cells (i-1,j) and (i,j);
- * y-face (i,j) between (i,j-1), (i,j)). */
+ * y-face (i,j) between (i,j-1), (i,j)); 3D: (nx+1)*ny*nz x-faces (index i + (nx+1)(j +
+ * ny k)), nx*(ny+1)*nz y-faces (i + nx (j + (ny+1) k)), nx*ny*(nz+1) z-faces
+ * (i + nx (j + ny k)), the face with index i (j, k) along its axis lying between cells
+ * i - 1 and i of that axis. */
 int64_t pond_nfaces(const pond_ctx *ctx);
 
 /* Face frames lambda_b of the last step (Sec. III.B.3; (dim+1) values per face: u..., T)

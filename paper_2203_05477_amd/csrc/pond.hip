@@ -15,6 +15,7 @@
 
 #include "../../include/pond.h"
 #include "pond_kernels.hpp"
+#include "pond_kernels3d.hpp"
 #include "pond_mlp.hpp"
 
 using namespace pond;
@@ -71,6 +72,9 @@ struct pond_ctx {
     void *H2 = nullptr;
     int sl_span = 0;
     int *res_order = nullptr;
+    // 3D: geometry, and the phi-bar-plus records of the cells (NR3 planes, precision R)
+    Geo3 G3;
+    void *rec3 = nullptr;
 };
 
 static void drop_graph(pond_ctx *c)
@@ -379,8 +383,41 @@ hipError_t launch_resident(pond_ctx *c, int nsteps, double t_end)
     return hipGetLastError();
 }
 
+// 3D: dt, the phi-bar-plus records, the faces of each axis, the cells
+template <typename R>
+hipError_t launch_step3(pond_ctx *c, double t_end)
+{
+    State<R> S = state_of<R>(c);
+    R *rec = reinterpret_cast<R *>(c->rec3);
+    const bool tm = c->ev != nullptr;
+    if (tm) (void)hipEventRecord(c->ev[0], c->stream);
+    dt_kernel<3, R><<<1, 64, 0, c->stream>>>(c->P, S, t_end, c->slot);
+    if (tm) (void)hipEventRecord(c->ev[1], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[2], c->stream);
+    plus_kernel_3d<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, rec);
+    const Geo3 &G = c->G3;
+    const bool mm = c->P.limiter == POND_LIM_MINMOD;
+    if (mm) {
+        face_kernel_3d<R, 0, 1><<<blocks(4 * G.nfa[0], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 1, 1><<<blocks(4 * G.nfa[1], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 2, 1><<<blocks(4 * G.nfa[2], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+    } else {
+        face_kernel_3d<R, 0, 0><<<blocks(4 * G.nfa[0], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 1, 0><<<blocks(4 * G.nfa[1], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 2, 0><<<blocks(4 * G.nfa[2], 256), 256, 0, c->stream>>>(c->P, G, S, rec);
+    }
+    if (tm) (void)hipEventRecord(c->ev[3], c->stream);
+    if (tm) (void)hipEventRecord(c->ev[4], c->stream);
+    cell_kernel_3d<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, G, S, c->slot);
+    if (tm) (void)hipEventRecord(c->ev[5], c->stream);
+    c->slot ^= 1;
+    return hipGetLastError();
+}
+
 hipError_t step_once(pond_ctx *c, double t_end)
 {
+    if (c->D == 3)
+        return c->precision == POND_FP64 ? launch_step3<double>(c, t_end) : launch_step3<float>(c, t_end);
     if (c->D == 1)
         return c->precision == POND_FP64 ? launch_step<1, double>(c, t_end) : launch_step<1, float>(c, t_end);
     return c->precision == POND_FP64 ? launch_step<2, double>(c, t_end) : launch_step<2, float>(c, t_end);
@@ -400,6 +437,34 @@ hipError_t face_once(pond_ctx *c, int bx, int by)
         e = hipGetLastError();
     }
     return e;
+}
+
+// 3D: sizes, extents, the three boundary kinds, what the 3D path does not take
+pond_status validate3(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
+                      const double *uz, const double *p)
+{
+    if (!uy || !uz || cfg->nx < 2 || cfg->ny < 2 || cfg->nz < 2) return POND_EINVAL;
+    if (!(cfg->gamma > 1.0) || !(cfg->cfl > 0.0 && cfg->cfl < 1.0) || !(cfg->mu > 0.0)) return POND_EINVAL;
+    if (!(cfg->tol > 0.0) || cfg->max_iter < 1 || cfg->max_iter > 60000) return POND_EINVAL;
+    if (!(cfg->x1 > cfg->x0) || !(cfg->y1 > cfg->y0) || !(cfg->z1 > cfg->z0)) return POND_EINVAL;
+    if (cfg->precision != POND_FP64 && cfg->precision != POND_MIXED) return POND_EINVAL;
+    if (cfg->limiter != POND_LIM_VANLEER && cfg->limiter != POND_LIM_MINMOD) return POND_EINVAL;
+    if (cfg->flags & ~POND_FLAG_STRICT) return POND_EINVAL;
+    if (cfg->seed_mode != POND_SEED_PREV) return POND_EINVAL;
+    if (!(1.0 / (cfg->gamma - 1.0) - 1.5 >= 0.0)) return POND_EINVAL;
+    int kinds[6] = {cfg->bc[0], cfg->bc[1], cfg->bc[2], cfg->bc[3], cfg->bc_z[0], cfg->bc_z[1]};
+    for (int s = 0; s < 6; ++s)
+        if (kinds[s] != POND_BC_PERIODIC && kinds[s] != POND_BC_OUTFLOW && kinds[s] != POND_BC_REFLECT)
+            return POND_EINVAL;
+    for (int a = 0; a < 3; ++a)
+        if ((kinds[2 * a] == POND_BC_PERIODIC) != (kinds[2 * a + 1] == POND_BC_PERIODIC)) return POND_EINVAL;
+    const int64_t n = (int64_t)cfg->nx * cfg->ny * cfg->nz;
+    if (n > (int64_t)INT32_MAX / 4) return POND_EINVAL; // cell indices are 32-bit in the kernels
+    for (int64_t i = 0; i < n; ++i)
+        if (!(rho[i] > 0.0) || !(p[i] > 0.0) || !std::isfinite(rho[i]) || !std::isfinite(p[i]) ||
+            !std::isfinite(ux[i]) || !std::isfinite(uy[i]) || !std::isfinite(uz[i]))
+            return POND_EINVAL;
+    return POND_OK;
 }
 
 pond_status validate(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
@@ -472,7 +537,7 @@ void free_all(pond_ctx *c)
     void *ptrs[] = {c->U, c->H, c->F, c->fiter, c->cell_inst, c->face_inst, c->cell_off, c->pad_off,
                     c->t, c->tstart, c->dt, c->dxk, c->vmax, c->stats, c->err, c->inst_err, c->scratch,
                     c->tail_f, c->tail_s, c->tail_meta, c->tail_count, c->tblock, c->res_order,
-                    c->U2, c->H2};
+                    c->U2, c->H2, c->rec3};
     for (void *q : ptrs)
         if (q) (void)hipFree(q);
     mlp_free(c->mlp);
@@ -495,7 +560,17 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
 {
     if (!out) return POND_EINVAL;
     *out = nullptr;
-    pond_status v = validate(cfg, rho, ux, uy, p);
+    if (cfg && cfg->dim == 3) return POND_EINVAL; // needs the z velocity: pond_init3
+    return pond_init3(cfg, rho, ux, uy, nullptr, p, out);
+}
+
+pond_status pond_init3(const pond_config *cfg, const double *rho, const double *ux, const double *uy,
+                       const double *uz, const double *p, pond_ctx **out)
+{
+    if (!out) return POND_EINVAL;
+    *out = nullptr;
+    if (!cfg || !rho || !ux || !p) return POND_EINVAL;
+    pond_status v = (cfg->dim == 3) ? validate3(cfg, rho, ux, uy, uz, p) : validate(cfg, rho, ux, uy, p);
     if (v != POND_OK) return v;
     int ndev = 0;
     if (hipGetDeviceCount(&ndev) != hipSuccess || ndev < 1) return POND_EDEVICE;
@@ -510,7 +585,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     memset(&P, 0, sizeof(P));
     P.dim = cfg->dim;
     P.nx = cfg->nx;
-    P.ny = (cfg->dim == 2) ? cfg->ny : 1;
+    P.ny = (cfg->dim >= 2) ? cfg->ny : 1;
     P.n_inst = (cfg->dim == 1) ? cfg->n_inst : 1;
     P.x0 = cfg->x0;
     P.y0 = cfg->y0;
@@ -529,7 +604,7 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         }
     }
     // fastest particle speed, per axis, of the states the boundary conditions prescribe
-    for (int s = 0; s < 2 * cfg->dim; ++s) {
+    for (int s = 0; s < 2 * std::min(cfg->dim, 2); ++s) {
         const double *used[2] = {nullptr, nullptr};
         if (P.bc[s] == BC_FIXED || P.bc[s] == BC_SPLIT) used[0] = cfg->bc_state[s];
         if (P.bc[s] == BC_FIXED_WINDOW || P.bc[s] == BC_MOVING) {
@@ -557,15 +632,36 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
         // every tube spans [x0, x1]: its own cell size is kept per instance
         P.dx = (cfg->x1 - cfg->x0) / len[0];
         P.dy = 1.0;
-    } else {
+    } else if (cfg->dim == 2) {
         P.ncell = (int64_t)P.nx * P.ny;
         P.nfx = (int64_t)(P.nx + 1) * P.ny;
         P.nface = P.nfx + (int64_t)P.nx * (P.ny + 1);
         P.dx = (cfg->x1 - cfg->x0) / P.nx;
         P.dy = (cfg->y1 - cfg->y0) / P.ny;
+    } else {
+        Geo3 &G = c->G3;
+        G.nx = cfg->nx;
+        G.ny = cfg->ny;
+        G.nz = cfg->nz;
+        G.dx[0] = (cfg->x1 - cfg->x0) / cfg->nx;
+        G.dx[1] = (cfg->y1 - cfg->y0) / cfg->ny;
+        G.dx[2] = (cfg->z1 - cfg->z0) / cfg->nz;
+        const int kinds[6] = {cfg->bc[0], cfg->bc[1], cfg->bc[2], cfg->bc[3], cfg->bc_z[0], cfg->bc_z[1]};
+        for (int q = 0; q < 6; ++q) G.bc[q] = kinds[q];
+        G.nfa[0] = (int64_t)(G.nx + 1) * G.ny * G.nz;
+        G.nfa[1] = (int64_t)G.nx * (G.ny + 1) * G.nz;
+        G.nfa[2] = (int64_t)G.nx * G.ny * (G.nz + 1);
+        G.foff[0] = 0;
+        G.foff[1] = G.nfa[0];
+        G.foff[2] = G.nfa[0] + G.nfa[1];
+        P.ncell = (int64_t)G.nx * G.ny * G.nz;
+        P.nfx = G.nfa[0];
+        P.nface = G.nfa[0] + G.nfa[1] + G.nfa[2];
+        P.dx = G.dx[0];
+        P.dy = G.dx[1];
     }
-    c->nh = (c->D == 1) ? Layout<1>::NH : Layout<2>::NH;
-    c->nfp = (c->D == 1) ? Layout<1>::NF : Layout<2>::NF;
+    c->nh = (c->D == 1) ? Layout<1>::NH : (c->D == 2) ? Layout<2>::NH : NH3;
+    c->nfp = (c->D == 1) ? Layout<1>::NF : (c->D == 2) ? Layout<2>::NF : NF3;
     if (c->D == 2) { // fastest measured on the double Mach reflection; pond_autotune re-picks
         c->bx = 8;
         c->by = 8;
@@ -590,7 +686,8 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     alloc((void **)&c->err, sizeof(int));
     alloc((void **)&c->inst_err, sizeof(int) * P.n_inst);
     // read-out staging, and the per-block records of the end-of-call summary
-    alloc((void **)&c->scratch, sizeof(double) * std::max<int64_t>(4 * std::max(n, nf), (int64_t)SUM_BLOCKS * SUM_NV));
+    alloc((void **)&c->scratch, sizeof(double) * std::max<int64_t>(4 * std::max(n, nf), (int64_t)SUM_BLOCKS * SUM3_NV));
+    if (c->D == 3) alloc(&c->rec3, c->rsize * NR3 * n);
     if (cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) {
         alloc((void **)&c->U2, sizeof(double) * (c->D + 2) * n);
         alloc(&c->H2, c->rsize * c->nh * n);
@@ -624,16 +721,18 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     }
     c->stream = c->own_stream;
     // upload: primitive fields (staged through scratch), instance tables
-    std::vector<double> prim4((size_t)4 * n, 0.0);
+    const int nprim = (c->D == 3) ? 5 : 4;
+    std::vector<double> prim4((size_t)nprim * n, 0.0);
     for (int64_t i = 0; i < n; ++i) {
         prim4[i] = rho[i];
         prim4[n + i] = ux[i];
-        prim4[2 * n + i] = (c->D == 2) ? uy[i] : 0.0;
-        prim4[3 * n + i] = p[i];
+        prim4[2 * n + i] = (c->D >= 2) ? uy[i] : 0.0;
+        if (c->D == 3) prim4[3 * n + i] = uz[i];
+        prim4[(nprim - 1) * n + i] = p[i];
     }
     std::vector<double> zeros(P.n_inst, 0.0);
     std::vector<unsigned long long> zv((size_t)2 * P.n_inst * P.vslots, 0ull), zs((size_t)ST_N * NSLOT, 0ull);
-    bool up = hip_ok(hipMemcpy(c->scratch, prim4.data(), sizeof(double) * 4 * n, hipMemcpyHostToDevice)) &&
+    bool up = hip_ok(hipMemcpy(c->scratch, prim4.data(), sizeof(double) * prim4.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->cell_off, coff.data(), sizeof(int64_t) * coff.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->pad_off, poff.data(), sizeof(int64_t) * poff.size(), hipMemcpyHostToDevice)) &&
               hip_ok(hipMemcpy(c->t, zeros.data(), sizeof(double) * P.n_inst, hipMemcpyHostToDevice)) &&
@@ -663,8 +762,12 @@ pond_status pond_init(const pond_config *cfg, const double *rho, const double *u
     c->sl_span = compute_cell_span(c, 256);
     if (c->D == 1)
         c->precision == POND_FP64 ? init_launch<1, double>(c, c->scratch) : init_launch<1, float>(c, c->scratch);
-    else
+    else if (c->D == 2)
         c->precision == POND_FP64 ? init_launch<2, double>(c, c->scratch) : init_launch<2, float>(c, c->scratch);
+    else if (c->precision == POND_FP64)
+        init_kernel_3d<double><<<blocks(std::max(n, nf), 256), 256, 0, c->stream>>>(c->P, c->G3, state_of<double>(c), c->scratch);
+    else
+        init_kernel_3d<float><<<blocks(std::max(n, nf), 256), 256, 0, c->stream>>>(c->P, c->G3, state_of<float>(c), c->scratch);
     if (!hip_ok(hipGetLastError()) || !hip_ok(hipStreamSynchronize(c->stream))) {
         pond_free(c);
         return POND_EDEVICE;
@@ -753,11 +856,14 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
     std::vector<double> sum;
     if (st) {
         // summary of the state after the call: one record per block of summary_kernel
-        sum.resize((size_t)SUM_BLOCKS * SUM_NV);
+        const int nv = (c->D == 3) ? SUM3_NV : SUM_NV;
+        sum.resize((size_t)SUM_BLOCKS * nv);
         if (c->D == 1)
             summary_kernel<1><<<SUM_BLOCKS, 256, 0, c->stream>>>(c->P, c->U, c->fiter, c->dxk, c->cell_inst, c->scratch);
-        else
+        else if (c->D == 2)
             summary_kernel<2><<<SUM_BLOCKS, 256, 0, c->stream>>>(c->P, c->U, c->fiter, c->dxk, c->cell_inst, c->scratch);
+        else
+            summary_kernel_3d<<<SUM_BLOCKS, 256, 0, c->stream>>>(c->P, c->G3, c->U, c->fiter, c->scratch);
         HIPCHK(hipGetLastError());
         HIPCHK(hipMemcpyAsync(sum.data(), c->scratch, sizeof(double) * sum.size(), hipMemcpyDeviceToHost, c->stream));
     }
@@ -796,18 +902,20 @@ pond_status pond_step(pond_ctx *c, int32_t nsteps, double t_end, pond_stats *st)
                 st->first_failed_instance = k;
                 break;
             }
-        double rmin = INFINITY, tmin = INFINITY, bad = INFINITY, nonc = INFINITY, tot[4] = {0, 0, 0, 0};
+        // records: rho_min, T_min, the conserved totals (4, or 5 in 3D), bad cell, face
+        const int nv = (c->D == 3) ? SUM3_NV : SUM_NV, nt = nv - 4;
+        double rmin = INFINITY, tmin = INFINITY, bad = INFINITY, nonc = INFINITY, tot[5] = {0, 0, 0, 0, 0};
         for (int b = 0; b < SUM_BLOCKS; ++b) {
-            const double *r = &sum[(size_t)b * SUM_NV];
+            const double *r = &sum[(size_t)b * nv];
             rmin = std::fmin(rmin, r[0]);
             tmin = std::fmin(tmin, r[1]);
-            for (int q = 0; q < 4; ++q) tot[q] += r[2 + q];
-            bad = std::fmin(bad, r[6]);
-            nonc = std::fmin(nonc, r[7]);
+            for (int q = 0; q < nt; ++q) tot[q] += r[2 + q];
+            bad = std::fmin(bad, r[2 + nt]);
+            nonc = std::fmin(nonc, r[3 + nt]);
         }
         st->rho_min = rmin;
         st->T_min = tmin;
-        for (int q = 0; q < 4; ++q) st->totals[q] = tot[q];
+        for (int q = 0; q < 5; ++q) st->totals[q] = tot[q];
         st->first_failed_cell = std::isfinite(bad) ? (int64_t)bad : -1;
         st->first_nonconv_face = std::isfinite(nonc) ? (int64_t)nonc : -1;
     }
@@ -824,8 +932,10 @@ pond_status pond_moments_device(const pond_ctx *c, double *dev_out)
     int64_t n = c->P.ncell;
     if (c->D == 1)
         fields_kernel<1><<<blocks(n, 256), 256, 0, c->stream>>>(n, c->U, c->P.Cv, dev_out);
-    else
+    else if (c->D == 2)
         fields_kernel<2><<<blocks(n, 256), 256, 0, c->stream>>>(n, c->U, c->P.Cv, dev_out);
+    else
+        fields_kernel_3d<<<blocks(n, 256), 256, 0, c->stream>>>(n, c->U, c->P.Cv, dev_out);
     HIPCHK(hipGetLastError());
     return POND_OK;
 }
@@ -989,7 +1099,7 @@ pond_status pond_populations(const pond_ctx *c, double *f, double *g, double *fr
 {
     if (!c || !f || !g || !frame) return POND_EINVAL;
     const int64_t n = c->P.ncell;
-    const int Q = (c->D == 1) ? 4 : 16;
+    const int Q = (c->D == 1) ? 4 : (c->D == 2) ? 16 : 64;
     double *df = nullptr, *dg = nullptr, *dfr = nullptr;
     size_t nb = sizeof(double) * (size_t)n;
     if (hipMalloc(&df, nb * Q) != hipSuccess || hipMalloc(&dg, nb * Q) != hipSuccess ||
@@ -999,7 +1109,12 @@ pond_status pond_populations(const pond_ctx *c, double *f, double *g, double *fr
         return POND_ENOMEM;
     }
     pond_ctx *m = const_cast<pond_ctx *>(c);
-    if (c->D == 1) {
+    if (c->D == 3) {
+        if (c->precision == POND_FP64)
+            pops_kernel_3d<double><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
+        else
+            pops_kernel_3d<float><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), df, dg, dfr);
+    } else if (c->D == 1) {
         if (c->precision == POND_FP64)
             pops_kernel<1, double><<<blocks(n, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), df, dg, dfr);
         else
@@ -1068,7 +1183,7 @@ pond_status pond_face_moments(const pond_ctx *c, double *Mf, double *Mg)
 {
     if (!c || !Mf || !Mg) return POND_EINVAL;
     const int64_t nf = c->P.nface;
-    const int nf3 = (c->D == 1) ? 4 : 15, ng2 = (c->D == 1) ? 3 : 7;
+    const int nf3 = (c->D == 1) ? 4 : (c->D == 2) ? 15 : 40, ng2 = (c->D == 1) ? 3 : (c->D == 2) ? 7 : 13;
     double *dm = nullptr, *dg = nullptr;
     if (hipMalloc(&dm, sizeof(double) * nf3 * nf) != hipSuccess ||
         hipMalloc(&dg, sizeof(double) * ng2 * nf) != hipSuccess) {
@@ -1076,7 +1191,12 @@ pond_status pond_face_moments(const pond_ctx *c, double *Mf, double *Mg)
         return POND_ENOMEM;
     }
     pond_ctx *m = const_cast<pond_ctx *>(c);
-    if (c->D == 1) {
+    if (c->D == 3) {
+        if (c->precision == POND_FP64)
+            face_moments_kernel_3d<double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), dm, dg);
+        else
+            face_moments_kernel_3d<float><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<float>(m), dm, dg);
+    } else if (c->D == 1) {
         if (c->precision == POND_FP64)
             face_moments_kernel<1, double><<<blocks(nf, 256), 256, 0, c->stream>>>(c->P, state_of<double>(m), dm, dg);
         else
@@ -1136,7 +1256,7 @@ pond_status pond_set_stream(pond_ctx *c, void *s)
 
 pond_status pond_set_tiles(pond_ctx *c, int32_t bx, int32_t by, int32_t cell_block)
 {
-    if (!c) return POND_EINVAL;
+    if (!c || c->D == 3) return POND_EINVAL;
     // every kernel is compiled for blocks of at most 256 threads
     if (cell_block < 64 || cell_block > 256 || cell_block % 64) return POND_EINVAL;
     if (c->D == 1) {
@@ -1188,7 +1308,7 @@ pond_status pond_set_resident(pond_ctx *c, int32_t on)
 
 pond_status pond_set_iter_split(pond_ctx *c, int32_t k)
 {
-    if (!c || k < 0) return POND_EINVAL;
+    if (!c || k < 0 || c->D == 3) return POND_EINVAL;
     drop_graph(c);
     if (c->D == 2) c->P.iter_split = k;
     return POND_OK;
@@ -1206,6 +1326,7 @@ pond_status pond_get_tiles(const pond_ctx *c, int32_t *bx, int32_t *by, int32_t 
 pond_status pond_autotune(pond_ctx *c)
 {
     if (!c) return POND_EINVAL;
+    if (c->D == 3) return POND_OK; // one launch shape in 3D
     // the face kernel is the dominant cost; time it on the current state. It only writes
     // face state, which is saved first and restored afterwards (the next step's seeds).
     const size_t fbytes = c->rsize * c->nfp * c->P.nface;
@@ -1586,7 +1707,7 @@ void pond_mlp_free(pond_mlp *m)
 
 pond_status pond_mlp_features(pond_ctx *c, float *X, float *ref)
 {
-    if (!c || !X || !ref) return POND_EINVAL;
+    if (!c || !X || !ref || c->D == 3) return POND_EINVAL;
     const int64_t nf = c->P.nface;
     if (c->D == 1) {
         if (c->precision == POND_FP64)
@@ -1606,7 +1727,7 @@ pond_status pond_mlp_features(pond_ctx *c, float *X, float *ref)
 
 pond_status pond_mlp_targets(pond_ctx *c, const float *X, const float *ref, float *T)
 {
-    if (!c || !X || !ref || !T) return POND_EINVAL;
+    if (!c || !X || !ref || !T || c->D == 3) return POND_EINVAL;
     const int64_t nf = c->P.nface;
     if (c->D == 1) {
         if (c->precision == POND_FP64)
@@ -1626,7 +1747,7 @@ pond_status pond_mlp_targets(pond_ctx *c, const float *X, const float *ref, floa
 
 pond_status pond_load_mlp(pond_ctx *c, const pond_mlp *m, int32_t hard_iters)
 {
-    if (!c || !m || !m->dev.ready || hard_iters < 1) return POND_EINVAL;
+    if (!c || !m || !m->dev.ready || hard_iters < 1 || c->D == 3) return POND_EINVAL;
     drop_graph(c);
     MlpDevice &M = c->mlp;
     if (!M.master) {

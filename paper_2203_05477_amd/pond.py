@@ -44,6 +44,9 @@ class Config(ctypes.Structure):
         ("bc_state", (ctypes.c_double * 4) * 4),
         ("bc_alt", (ctypes.c_double * 4) * 4),
         ("bc_param", (ctypes.c_double * 4) * 4),
+        ("nz", ctypes.c_int32),
+        ("z0", ctypes.c_double), ("z1", ctypes.c_double),
+        ("bc_z", ctypes.c_int32 * 2),
     ]
 
 
@@ -59,7 +62,7 @@ class Stats(ctypes.Structure):
         ("failed_instances", ctypes.c_int32),
         ("tail_faces", ctypes.c_int64), ("tail_iters", ctypes.c_int64),
         ("rho_min", ctypes.c_double), ("T_min", ctypes.c_double),
-        ("totals", ctypes.c_double * 4),
+        ("totals", ctypes.c_double * 5),
         ("first_failed_instance", ctypes.c_int32),
         ("first_failed_cell", ctypes.c_int64), ("first_nonconv_face", ctypes.c_int64),
     ]
@@ -98,6 +101,7 @@ def load(path: str | None = None):
     S = ctypes.c_int
     sig = {
         "pond_init": (S, [ctypes.POINTER(Config), _D, _D, _D, _D, ctypes.POINTER(_P)]),
+        "pond_init3": (S, [ctypes.POINTER(Config), _D, _D, _D, _D, _D, ctypes.POINTER(_P)]),
         "pond_step": (S, [_P, ctypes.c_int32, ctypes.c_double, ctypes.POINTER(Stats)]),
         "pond_moments": (S, [_P, _D, _D, _D, _D]),
         "pond_moments_device": (S, [_P, _P]),
@@ -151,7 +155,7 @@ def load(path: str | None = None):
 
 def exported_symbols():
     """Names the header declares (checked against the library by the CPU tests)."""
-    return ["pond_init", "pond_step", "pond_moments", "pond_moments_device", "pond_conserved",
+    return ["pond_init", "pond_init3", "pond_step", "pond_moments", "pond_moments_device", "pond_conserved",
             "pond_populations", "pond_nfaces", "pond_face_frames", "pond_set_face_frames",
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
@@ -197,7 +201,9 @@ def make_config(cfg: dict, precision="fp64", seed="prev", strict=False) -> tuple
         c.n_inst = 1
         c.len = None
         c.nx = int(cfg["nx"])
-    c.ny = int(cfg.get("ny", 1)) if c.dim == 2 else 1
+    c.ny = int(cfg.get("ny", 1)) if c.dim >= 2 else 1
+    c.nz = int(cfg.get("nz", 1)) if c.dim == 3 else 1
+    c.z0, c.z1 = float(cfg.get("z0", 0.0)), float(cfg.get("z1", 1.0))
     c.x0, c.x1 = float(cfg.get("x0", 0.0)), float(cfg.get("x1", 1.0))
     c.y0, c.y1 = float(cfg.get("y0", 0.0)), float(cfg.get("y1", 1.0))
     c.gamma, c.cfl, c.mu = float(cfg["gamma"]), float(cfg["cfl"]), float(cfg["mu"])
@@ -209,6 +215,8 @@ def make_config(cfg: dict, precision="fp64", seed="prev", strict=False) -> tuple
     c.flags = ((FLAG_STRICT if strict else 0) | (FLAG_REG_EQ if cfg.get("regularization", "grad") == "eq" else 0)
                | (FLAG_SEMI_LAGRANGIAN if cfg.get("scheme", "fv") == "sl" else 0))
     z = [[0.0] * 4] * 4
+    for k in range(2):
+        c.bc_z[k] = BC[cfg["bc"][4 + k]] if len(cfg["bc"]) > 4 else BC["outflow"]
     for k in range(4):
         c.bc[k] = BC[cfg["bc"][k]]
         for q in range(4):
@@ -219,25 +227,27 @@ def make_config(cfg: dict, precision="fp64", seed="prev", strict=False) -> tuple
 
 
 class Context:
-    """A libpond context: one simulation (a 2D grid, one tube or a batch of tubes)."""
+    """A libpond context: one simulation (a 3D box, a 2D grid, one tube or a batch of tubes)."""
 
     def __init__(self, cfg: dict, fields: dict, precision="fp64", seed="prev", strict=False):
         lib = load()
         self.cfg = cfg
         self.dim = int(cfg["dim"])
         self._c, self._keep = make_config(cfg, precision, seed, strict)
-        self.n = int(self._c.nx) * (int(self._c.ny) if self.dim == 2 else 1)
+        self.n = int(self._c.nx) * int(self._c.ny) * int(self._c.nz)
         self.n_inst = int(self._c.n_inst)
         self.Q = 4 ** self.dim
         rho = _f64(fields["rho"], self.n)
         ux = _f64(fields["ux"], self.n)
-        uy = _f64(fields["uy"], self.n) if (self.dim == 2) else None
+        uy = _f64(fields["uy"], self.n) if (self.dim >= 2) else None
+        uz = _f64(fields["uz"], self.n) if (self.dim == 3) else None
         p = _f64(fields["p"], self.n)
         h = _P()
-        st = lib.pond_init(ctypes.byref(self._c), _ptr(rho), _ptr(ux),
-                           _ptr(uy) if uy is not None else None, _ptr(p), ctypes.byref(h))
+        st = lib.pond_init3(ctypes.byref(self._c), _ptr(rho), _ptr(ux),
+                            _ptr(uy) if uy is not None else None,
+                            _ptr(uz) if uz is not None else None, _ptr(p), ctypes.byref(h))
         if st != OK:
-            raise PondError(st, "pond_init")
+            raise PondError(st, "pond_init3")
         self._h = h
         self.nfaces = int(lib.pond_nfaces(h))
         self.last = None
@@ -264,7 +274,7 @@ class Context:
         rc = load().pond_moments(self._h, _ptr(r), _ptr(ux), _ptr(uy), _ptr(T))
         if rc != OK:
             raise PondError(rc, "pond_moments")
-        return r, ux, (uy if self.dim == 2 else None), T
+        return r, ux, (uy if self.dim >= 2 else None), T
 
     def moments_device(self, dev_ptr: int):
         rc = load().pond_moments_device(self._h, ctypes.c_void_p(dev_ptr))
@@ -300,8 +310,8 @@ class Context:
             raise PondError(rc, "pond_set_face_frames")
 
     def face_moments(self):
-        nf3 = 4 if self.dim == 1 else 15
-        ng2 = 3 if self.dim == 1 else 7
+        nf3 = sum(self.dim ** k for k in range(4))
+        ng2 = sum(self.dim ** k for k in range(3))
         Mf = np.zeros((self.nfaces, nf3)); Mg = np.zeros((self.nfaces, ng2))
         rc = load().pond_face_moments(self._h, _ptr(Mf), _ptr(Mg))
         if rc != OK:

@@ -203,6 +203,20 @@ def explosion_box(n=256, cfl=0.2, mu=1e-3, tol=TOL_PARITY, max_iter=32):
     return cfg, {"rho": v.copy(), "ux": np.zeros(v.size), "uy": np.zeros(v.size), "p": v.copy()}
 
 
+def explosion_box_3d(n=128, cfl=0.2, mu=1e-3, tol=TOL_PARITY, max_iter=32):
+    """The explosion in a closed box (Sec. IV.C) carried to three dimensions: [0,1]^3, n^3
+    cells, reflecting walls on all six sides; (rho, u, p) = (5, 0, 5) inside the sphere of
+    radius 0.3 around (0.4, 0.4, 0.4) (cell-centre test), (1, 0, 1) outside; gamma 1.4. The
+    paper's experiments are two-dimensional; this is the same set-up on the D3Q64 lattice."""
+    cfg = base_config_3d(n, n, n, cfl=cfl, mu=mu, tol=tol, max_iter=max_iter, bc=("reflect",) * 6)
+    X, Y, Z = cell_centres_3d(cfg)
+    inside = (X - 0.4) ** 2 + (Y - 0.4) ** 2 + (Z - 0.4) ** 2 < 0.3 ** 2
+    cfg["name"] = "explosion_box_3d"
+    v = np.where(inside, 5.0, 1.0)
+    z = np.zeros(v.size)
+    return cfg, {"rho": v.copy(), "ux": z, "uy": z.copy(), "uz": z.copy(), "p": v.copy()}
+
+
 def double_mach(nx=1920, ny=480, mach=10.0, gamma=1.4, cfl=0.2, mu=1e-3, tol=TOL_PARITY,
                 max_iter=32):
     """Mach-10 shock meeting a 30 degree wall (Sec. IV.C.4): [0,4]x[0,1]; shock through
