@@ -28,9 +28,22 @@
 // and every coefficient of odd degree along the normal reversed) on each of the six sides.
 #pragma once
 
+#include <type_traits>
+
 #include "pond_kernels.hpp"
 
 namespace pond {
+
+// compile-time loop: f(std::integral_constant<int, i>) for i = B .. E-1, so that every index
+// derived from i inside f is a constant expression (tables below are folded, not evaluated)
+template <int B, int E, typename F>
+PD void static_for(F &&f)
+{
+    if constexpr (B < E) {
+        f(std::integral_constant<int, B>{});
+        static_for<B + 1, E>(f);
+    }
+}
 
 struct Geo3 {
     int nx, ny, nz;
@@ -110,23 +123,22 @@ PD void col_shift(R v[4], int L, R d)
 template <typename R, int DEG, int AX, int KIND>
 PD void axis_pass(R *m, R d)
 {
-#pragma unroll
-    for (int p = 0; p <= DEG; ++p) {
-#pragma unroll
-        for (int q = 0; q <= DEG; ++q) {
-            if (p + q > DEG) continue;
-            const int L = DEG - p - q;
+    static_for<0, DEG + 1>([&](auto P) {
+        static_for<0, DEG + 1 - decltype(P)::value>([&](auto Qi) {
+            constexpr int p = decltype(P)::value, q = decltype(Qi)::value, L = DEG - p - q;
             R v[4];
-#pragma unroll
-            for (int e = 0; e < 4; ++e) v[e] = (e <= L) ? m[idx_ax<AX>(e, p, q)] : R(0);
-            if (KIND == 0) col_q2mu(v, L);
-            if (KIND == 1) col_mu2q(v, L);
-            if (KIND == 2) col_shift(v, L, d);
-#pragma unroll
-            for (int e = 1; e < 4; ++e)
-                if (e <= L) m[idx_ax<AX>(e, p, q)] = v[e];
-        }
-    }
+            v[0] = m[idx_ax<AX>(0, p, q)];
+            v[1] = (L >= 1) ? m[idx_ax<AX>(L >= 1 ? 1 : 0, p, q)] : R(0);
+            v[2] = (L >= 2) ? m[idx_ax<AX>(L >= 2 ? 2 : 0, p, q)] : R(0);
+            v[3] = (L >= 3) ? m[idx_ax<AX>(L >= 3 ? 3 : 0, p, q)] : R(0);
+            if constexpr (KIND == 0) col_q2mu(v, L);
+            if constexpr (KIND == 1) col_mu2q(v, L);
+            if constexpr (KIND == 2) col_shift(v, L, d);
+            if constexpr (L >= 1) m[idx_ax<AX>(1, p, q)] = v[1];
+            if constexpr (L >= 2) m[idx_ax<AX>(2, p, q)] = v[2];
+            if constexpr (L >= 3) m[idx_ax<AX>(3, p, q)] = v[3];
+        });
+    });
 }
 
 template <typename R, int DEG>
@@ -149,12 +161,12 @@ PD void mu2q3(R *m)
 template <typename R, int DEG>
 PD void shift3(R *m, R r, R dx, R dy, R dz)
 {
-    const R r2 = r * r;
-#pragma unroll
-    for (int o = 1; o < (DEG == 3 ? 20 : 10); ++o) {
-        const int d = exp3(o, 0) + exp3(o, 1) + exp3(o, 2);
-        m[o] *= (d == 1) ? r : (d == 2) ? r2 : r2 * r;
-    }
+    const R r2 = r * r, r3 = r2 * r;
+    static_for<1, (DEG == 3 ? 20 : 10)>([&](auto O) {
+        constexpr int o = decltype(O)::value;
+        constexpr int d = exp3(o, 0) + exp3(o, 1) + exp3(o, 2);
+        m[o] *= (d == 1) ? r : (d == 2) ? r2 : r3;
+    });
     axis_pass<R, DEG, 0, 2>(m, dx);
     axis_pass<R, DEG, 1, 2>(m, dy);
     axis_pass<R, DEG, 2, 2>(m, dz);
@@ -174,20 +186,19 @@ __host__ __device__ constexpr double hfac(int m, int k)
     return r;
 }
 
-template <typename R, int KMAX>
-PD R moment_of_q(const R *q, int a, int b, int c)
+template <typename R, int KMAX, int A, int B, int C>
+PD R moment_of_q(const R *q)
 {
     R s = R(0);
-#pragma unroll
-    for (int k0 = 3; k0 >= 0; --k0)
-#pragma unroll
-        for (int k1 = 3; k1 >= 0; --k1)
-#pragma unroll
-            for (int k2 = 3; k2 >= 0; --k2) {
-                if (k0 + k1 + k2 > KMAX) continue;
-                const double w = hfac(a, k0) * hfac(b, k1) * hfac(c, k2);
-                if (w != 0.0) s = fma(R(w), q[idx3(k0, k1, k2)], s);
-            }
+    static_for<0, 4>([&](auto K0) {
+        static_for<0, 4>([&](auto K1) {
+            static_for<0, 4>([&](auto K2) {
+                constexpr int k0 = decltype(K0)::value, k1 = decltype(K1)::value, k2 = decltype(K2)::value;
+                constexpr double w = hfac(A, k0) * hfac(B, k1) * hfac(C, k2);
+                if constexpr (k0 + k1 + k2 <= KMAX && w != 0.0) s = fma(R(w), q[idx3(k0, k1, k2)], s);
+            });
+        });
+    });
     return s;
 }
 
@@ -224,17 +235,17 @@ template <typename R, int DEG, int AXIS>
 PD void eval_col3(const R *q, const R hn[4], R p[16])
 {
     R A[10];
-#pragma unroll
-    for (int b = 0; b <= DEG; ++b)
-#pragma unroll
-        for (int c = 0; c <= DEG; ++c) {
-            if (b + c > DEG) continue;
+    static_for<0, DEG + 1>([&](auto Bi) {
+        static_for<0, DEG + 1 - decltype(Bi)::value>([&](auto Ci) {
+            constexpr int b = decltype(Bi)::value, c = decltype(Ci)::value;
             R s = q[idx_ax<AXIS>(0, b, c)];
-#pragma unroll
-            for (int a = 1; a <= DEG; ++a)
-                if (a + b + c <= DEG) s = fma(hn[a], q[idx_ax<AXIS>(a, b, c)], s);
+            static_for<1, DEG + 1 - b - c>([&](auto Ai) {
+                constexpr int a = decltype(Ai)::value;
+                s = fma(hn[a], q[idx_ax<AXIS>(a, b, c)], s);
+            });
             A[idx2(b, c)] = s;
-        }
+        });
+    });
     eval_q_2d(A, p, DEG);
 }
 
@@ -331,17 +342,17 @@ PD void load_coef3(const R *rec, int64_t n, int src, int mir, R *q)
     if (!G) {
         q[0] = rec[R3_RHO * n + src];
         q[1] = q[2] = q[3] = R(0);
-#pragma unroll
-        for (int o = 4; o < 20; ++o) {
+        static_for<4, 20>([&](auto O) {
+            constexpr int o = decltype(O)::value, pm = par3(o);
             const R v = rec[(R3_F + o - 4) * n + src];
-            q[o] = (__popc(mir & par3(o)) & 1) ? -v : v;
-        }
+            q[o] = (__popc(mir & pm) & 1) ? -v : v;
+        });
     } else {
-#pragma unroll
-        for (int o = 0; o < 10; ++o) {
+        static_for<0, 10>([&](auto O) {
+            constexpr int o = decltype(O)::value, pm = par3(o);
             const R v = rec[(R3_G + o) * n + src];
-            q[o] = (__popc(mir & par3(o)) & 1) ? -v : v;
-        }
+            q[o] = (__popc(mir & pm) & 1) ? -v : v;
+        });
     }
 }
 
@@ -371,13 +382,14 @@ PD void col_moments3(const R p[16], int n, R *m)
     moments_2d(p, M2, DEG == 3 ? 10 : 6);
     const R c = node<R>(n), w = weight1<R>(n);
     const R wp[4] = {w, w * c, w * c * c, w * c * c * c};
-#pragma unroll
-    for (int a = 0; a <= DEG; ++a)
-#pragma unroll
-        for (int b = 0; b <= DEG; ++b)
-#pragma unroll
-            for (int cc = 0; cc <= DEG; ++cc)
-                if (a + b + cc <= DEG) m[idx_ax<AXIS>(a, b, cc)] = wp[a] * M2[idx2(b, cc)];
+    static_for<0, DEG + 1>([&](auto Ai) {
+        static_for<0, DEG + 1 - decltype(Ai)::value>([&](auto Bi) {
+            static_for<0, DEG + 1 - decltype(Ai)::value - decltype(Bi)::value>([&](auto Ci) {
+                constexpr int a = decltype(Ai)::value, b = decltype(Bi)::value, cc = decltype(Ci)::value;
+                m[idx_ax<AXIS>(a, b, cc)] = wp[a] * M2[idx2(b, cc)];
+            });
+        });
+    });
 }
 
 // sum over the four lanes of a quad (all four active), then lane 0's sum in every lane:
@@ -792,18 +804,28 @@ PD void side_update3(const Params &P, const Geo3 &G, const State<R> &S, int64_t 
     mu2q3<R, 2>(qg);
     const R kf = (R)(dt / G.dx[AX]) * sgn;
     const R ks = kf * su, ku = kf * uc[AX];
-#pragma unroll
-    for (int o = 0; o < 20; ++o) {
-        const int e = idx3(exp3(o, 0) + (AX == 0), exp3(o, 1) + (AX == 1), exp3(o, 2) + (AX == 2));
-        const R hi = (e < 20) ? mu[e < 20 ? e : 0] : moment_of_q<R, 3>(qc, exp3(e, 0), exp3(e, 1), exp3(e, 2));
+    static_for<0, 20>([&](auto O) {
+        constexpr int o = decltype(O)::value;
+        constexpr int a = exp3(o, 0) + (AX == 0), b = exp3(o, 1) + (AX == 1), c = exp3(o, 2) + (AX == 2);
+        constexpr int e = idx3(a, b, c);
+        R hi;
+        if constexpr (e < 20)
+            hi = mu[e];
+        else
+            hi = moment_of_q<R, 3, a, b, c>(qc);
         mfo[o] -= ks * hi + ku * mu[o];
-    }
-#pragma unroll
-    for (int o = 0; o < 10; ++o) {
-        const int e = idx3(exp3(o, 0) + (AX == 0), exp3(o, 1) + (AX == 1), exp3(o, 2) + (AX == 2));
-        const R hi = (e < 10) ? mg[e < 10 ? e : 0] : moment_of_q<R, 2>(qg, exp3(e, 0), exp3(e, 1), exp3(e, 2));
+    });
+    static_for<0, 10>([&](auto O) {
+        constexpr int o = decltype(O)::value;
+        constexpr int a = exp3(o, 0) + (AX == 0), b = exp3(o, 1) + (AX == 1), c = exp3(o, 2) + (AX == 2);
+        constexpr int e = idx3(a, b, c);
+        R hi;
+        if constexpr (e < 10)
+            hi = mg[e];
+        else
+            hi = moment_of_q<R, 2, a, b, c>(qg);
         mgo[o] -= ks * hi + ku * mg[o];
-    }
+    });
 }
 
 template <typename R>
