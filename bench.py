@@ -67,7 +67,9 @@ CELL_BYTES_2D = {"mixed": 312, "fp64": 560}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "double_mach_1920x480_face_traffic.md")
-KERNEL_SOURCES = ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip")
+# the sources the 2D face kernel is compiled from (host code and the other kernels' headers
+# do not change it)
+KERNEL_SOURCES = ("pond_core.hpp", "pond_kernels.hpp")
 
 
 def measured_traffic(tiles):
@@ -209,6 +211,27 @@ def other_workload(args):
     print(json.dumps(line), flush=True)
 
 
+# Executed FLOPs of one face iteration of the 3D face kernel in the mixed form (FP32
+# populations), from the SQ_INSTS_VALU_FLOPS_FP32 and _FP64 counters (times 64 lanes) over
+# the x-face launches of the 128^3 explosion box, divided by faces x mean iterations; it
+# includes each face's set-up and write (kernel count, not a method count)
+FLOPS_FACE_ITER_3D = 21500
+
+
+def box3d_roofline(m):
+    """ALU roofline of the 3D face kernels (the three launches and the phi-bar-plus pass
+    before them, timed together with HIP events) against the FP32 vector peak."""
+    ms = m["kernel_ms"]["plus_and_faces"]
+    flop = FLOPS_FACE_ITER_3D * m["faces"] / m["steps"] * m["mean_iters"]
+    tf = flop / (ms * 1e-3) / 1e12 if ms > 0 else None
+    return {"bound": "alu", "achieved": tf, "peak": PEAK_FP32_TFLOPS, "unit": "TFLOP/s",
+            "frac": tf / PEAK_FP32_TFLOPS if tf else None, "traffic": None,
+            "kernel": "face_kernel_3d<float> (x, y, z launches) + plus_kernel_3d<float>",
+            "kernel_ms": ms, "flop_per_step": flop,
+            "flop_count": f"{FLOPS_FACE_ITER_3D} per face iteration (kernel count, SQ FLOPS counters) x "
+                          f"{m['faces'] / m['steps']:.0f} faces x {m['mean_iters']:.4f} iterations"}
+
+
 def box3d_workload(args):
     """The explosion in a closed box on the D3Q64 lattice (n^3 cells, reflecting walls),
     mixed and FP64 forms from the same state: converged cell-updates per second over the
@@ -236,7 +259,7 @@ def box3d_workload(args):
         el = time.perf_counter() - t0
         kt = ctx.kernel_times()
         out[prec] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
-                     "cell_updates": st["cell_updates"], "faces": st["faces"],
+                     "steps": args.steps, "cell_updates": st["cell_updates"], "faces": st["faces"],
                      "mean_iters": st["iters_total"] / max(st["faces"], 1), "iters_max": st["iters_max"],
                      "nonconverged": st["nonconverged"], "status": st["status"],
                      "kernel_ms": {"dt": kt["dt"], "plus_and_faces": kt["face"], "cell": kt["cell"]}}
@@ -260,7 +283,7 @@ def box3d_workload(args):
         "data": "synthetic",
         "config": {"workload": f"explosion_box_3d_{n}^3", "lattice": "D3Q64",
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
-        "roofline": None,
+        "roofline": box3d_roofline(m),
         "mixed": m, "fp64_plain": out.get("fp64"), "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)

@@ -26,7 +26,7 @@ def test_traffic_figure_follows_the_source_hash():
     recs = [json.loads(m) for m in re.findall(r"traffic-json: (\{.*\})", txt)]
     assert recs
     src = b"".join(open(os.path.join(ROOT, "paper_2203_05477_amd", "csrc", f), "rb").read()
-                   for f in ("pond_core.hpp", "pond_kernels.hpp", "pond_mlp.hpp", "pond.hip"))
+                   for f in bench.KERNEL_SOURCES)
     for rec in recs:
         same = hashlib.sha256(src).hexdigest() == rec["sources_sha256"]
         got = bench.measured_traffic(rec["tiles"])
