@@ -93,6 +93,26 @@ def measured_traffic(tiles):
     return rec
 
 
+TUBE_TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "tube_batch_4096_traffic.md")
+
+
+def tube_traffic(kernel):
+    """Measured HBM bytes per cell-update of the tube batch's resident kernel or launched
+    passes (committed counter summary), or None once the kernel sources have changed."""
+    import hashlib
+
+    if not os.path.exists(TUBE_TRAFFIC_PROFILE):
+        return None
+    recs = [json.loads(line.split(":", 1)[1]) for line in open(TUBE_TRAFFIC_PROFILE)
+            if line.startswith("traffic-json:")]
+    rec = next((r for r in recs if r["kernel"] == kernel), None)
+    if rec is None:
+        return None
+    csrc = os.path.join(ROOT, "paper_2203_05477_amd", "csrc")
+    h = hashlib.sha256(b"".join(open(os.path.join(csrc, f), "rb").read() for f in KERNEL_SOURCES))
+    return rec["bytes_per_cell_update"] if h.hexdigest() == rec["sources_sha256"] else None
+
+
 def cell_update_hbm(st, kt, steps, precision):
     fused = kt["tail"] > 0.01  # the tail launch (else only event overhead sits there)
     ms = kt["cell"] + (kt["tail"] if fused else 0.0)
@@ -266,15 +286,18 @@ def box3d_workload(args):
         ctx.close()
     cpu = None
     if not args.no_cpu_baseline:
-        m = 48
+        m = 64
         cfg, fields = W.explosion_box_3d(m, tol=W.TOL_FP64)
         sim = oracle.Sim(cfg, fields["rho"], fields["ux"], fields["uy"], fields["p"], uz=fields["uz"])
         t0 = time.perf_counter()
-        sim.step()
+        k = 0
+        while k < 6 and time.perf_counter() - t0 < 12.0:
+            sim.step()
+            k += 1
         el = time.perf_counter() - t0
-        cpu = {"value": m ** 3 / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
+        cpu = {"value": k * m ** 3 / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
                "kind": "oracle", "cpu_model": cpu_model(),
-               "sample": f"one step of the same set-up on {m}^3 cells from t=0 (FP64); {el:.1f} s"}
+               "sample": f"first {k} steps of the same set-up on {m}^3 cells from t=0 (FP64); {el:.1f} s"}
     m = out["mixed"]
     line = {
         "metric": METRIC, "value": m["value"], "unit": "Mcell-updates/s", "n_gpus": 1,
@@ -307,8 +330,11 @@ def tube_roofline(m, steps):
         r = m["resident"]
         alg = BYTES_1D_FUSED["mixed"] * r["cell_updates"]
         gbps = alg / (r["launch_ms"] * 1e-3) / 1e9
+        bpc = tube_traffic("tube_resident_kernel_1d<float, 0, 256>")
         out = {"bound": "hbm", "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-               "frac": gbps / PEAK_HBM_GBPS, "traffic": None,
+               "frac": gbps / PEAK_HBM_GBPS, "traffic": bpc * r["cell_updates"] if bpc else None,
+               "traffic_unit": "B per launch (HBM, rocprofv3 FETCH_SIZE + WRITE_SIZE per cell-update "
+                               "over 16 steps, times the launch's cell-updates)",
                "kernel": "tube_resident_kernel_1d<float, 0, 256>", "kernel_ms": r["launch_ms"],
                "bytes_per_launch": alg,
                "bytes_count": f"{BYTES_1D_FUSED['mixed']} B per cell-update x {r['cell_updates']} "
@@ -316,9 +342,11 @@ def tube_roofline(m, steps):
     ms = m["kernel_ms"]["face"] + m["kernel_ms"]["cell"]
     alg = (BYTES_1D_FUSED["mixed"] + BYTES_1D_SPLIT_EXTRA["mixed"]) * m["cell_updates"] / steps
     gbps = alg / (ms * 1e-3) / 1e9 if ms > 0 else None
+    bpl = tube_traffic("face_kernel_1d<float, 0> + cell_kernel<1, float, 0>")
     launched = {"kernels": "face_kernel_1d + cell_kernel<1>", "ms_per_step": ms, "bytes_per_step": alg,
                 "achieved": gbps, "peak": PEAK_HBM_GBPS, "unit": "GB/s",
-                "frac": gbps / PEAK_HBM_GBPS if gbps else None}
+                "frac": gbps / PEAK_HBM_GBPS if gbps else None,
+                "traffic_per_step": bpl * m["cell_updates"] / steps if bpl else None}
     if out is None:
         return dict(launched, bound="hbm", traffic=None)
     out["launched"] = launched

@@ -35,3 +35,21 @@ def test_traffic_figure_follows_the_source_hash():
         else:
             assert got is None
     assert bench.measured_traffic([7, 3]) is None  # no record for a tile never measured
+
+
+def test_tube_traffic_follows_the_source_hash():
+    sys.path.insert(0, ROOT)
+    import bench
+
+    txt = open(bench.TUBE_TRAFFIC_PROFILE).read()
+    recs = [json.loads(m) for m in re.findall(r"traffic-json: (\{.*\})", txt)]
+    assert len(recs) == 2
+    src = b"".join(open(os.path.join(ROOT, "paper_2203_05477_amd", "csrc", f), "rb").read()
+                   for f in bench.KERNEL_SOURCES)
+    for rec in recs:
+        got = bench.tube_traffic(rec["kernel"])
+        if hashlib.sha256(src).hexdigest() == rec["sources_sha256"]:
+            assert got == rec["bytes_per_cell_update"] > 0
+        else:
+            assert got is None
+    assert bench.tube_traffic("no such kernel") is None
