@@ -498,70 +498,137 @@ PD void frame_of3(const R *mf, const R *mg, R s, double Cv, R &rho, R du[3], R &
     Tn = temperature(rhoe, rho, irho, Cv);
 }
 
+// The stencil rows of a block's faces in LDS. A block takes 64 consecutive faces of one
+// row of faces along x (fixed j, k); their 12-cell stencils lie in a few rows of cells along
+// x, each within x0 - 2 .. x0 + 65 (x0 = the block's first face): 5 rows for the x faces
+// (the face row and its four neighbours across), 8 for the y and z faces (the two cells on
+// each side along the normal, and the L and R rows' neighbours along the other tangential
+// axis). Row r lies at (j + RJ[r], k + RK[r]) relative to the faces' (j, k).
+constexpr int ROW3 = 68; // slots per row: x0 - 2 .. x0 + 65
+
+template <int AXIS>
+struct Rows3 {
+    static constexpr int n = AXIS == 0 ? 5 : 8;
+    static constexpr int rj(int r)
+    {
+        if (AXIS == 0) return r == 1 ? -1 : r == 2 ? 1 : 0;
+        if (AXIS == 1) {
+            constexpr int t[8] = {-1, 0, -2, 1, -1, -1, 0, 0};
+            return t[r];
+        }
+        constexpr int t[8] = {0, 0, 0, 0, -1, 1, -1, 1};
+        return t[r];
+    }
+    static constexpr int rk(int r)
+    {
+        if (AXIS == 0) return r == 3 ? -1 : r == 4 ? 1 : 0;
+        if (AXIS == 1) {
+            constexpr int t[8] = {0, 0, 0, 0, -1, 1, -1, 1};
+            return t[r];
+        }
+        constexpr int t[8] = {-1, 0, -2, 1, -1, -1, 0, 0};
+        return t[r];
+    }
+    // stencil cell q (L, R, L-n, R+n, L-t1, L+t1, R-t1, R+t1, L-t2, L+t2, R-t2, R+t2):
+    // its row and its x offset from the face index i
+    static constexpr int row(int q)
+    {
+        if (AXIS == 0) {
+            constexpr int t[12] = {0, 0, 0, 0, 1, 2, 1, 2, 3, 4, 3, 4};
+            return t[q];
+        }
+        constexpr int t[12] = {0, 1, 2, 3, 0, 0, 1, 1, 4, 5, 6, 7};
+        return t[q];
+    }
+    static constexpr int dx(int q)
+    {
+        if (AXIS == 0) {
+            constexpr int t[12] = {-1, 0, -2, 1, -1, -1, 0, 0, -1, -1, 0, 0};
+            return t[q];
+        }
+        constexpr int t[12] = {0, 0, 0, 0, -1, 1, -1, 1, 0, 0, 0, 0};
+        return t[q];
+    }
+};
+
+// faces per row along x, rows of faces, and the launch's block count for axis AXIS
+PD __host__ int face3_rowlen(const Geo3 &G, int axis) { return axis == 0 ? G.nx + 1 : G.nx; }
+PD __host__ int64_t face3_rows(const Geo3 &G, int axis)
+{
+    return axis == 0 ? (int64_t)G.ny * G.nz : axis == 1 ? (int64_t)(G.ny + 1) * G.nz : (int64_t)G.ny * (G.nz + 1);
+}
+PD __host__ int64_t face3_blocks(const Geo3 &G, int axis)
+{
+    return face3_rows(G, axis) * ((face3_rowlen(G, axis) + 63) / 64);
+}
+
 // Face f of axis AXIS, four lanes (n = lane & 3). The predictor frame is the previous step's
 // face frame (or, before the first step, the frame of the mean conserved variables of L and
 // R); the corrector iterates to tol, with the restart from the mean frame, the two-cycle stop
 // and the first-order fallback of the 2D kernels. Writes the face state of Sec. III.B.3:
 // phi = (phi-bar + (eps/4) phi_eq) / (1 + eps/4) in the final frame, eps = dt p_b / mu.
 template <typename R, int AXIS, int LIM>
-__global__ __launch_bounds__(256) void face_kernel_3d(Params P, Geo3 G, State<R> S, const R *rec)
+__global__ __launch_bounds__(256) void face_kernel_3d(Params P, Geo3 G, State<R> S, const R *grec)
 {
+    constexpr int NROW = Rows3<AXIS>::n, NRW = NROW * ROW3;
+    __shared__ R lds[NR3 * NRW];
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
-    const int64_t gid = (int64_t)xcd_tile((int)blockIdx.x, (int)gridDim.x) * 256 + threadIdx.x;
-    const int64_t fl = gid >> 2;
-    const int n = (int)(gid & 3);
-    const int64_t nc = P.ncell, nf = P.nface;
+    const int len = face3_rowlen(G, AXIS);
+    const int nch = (len + 63) / 64;
+    const int64_t b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
+    const int64_t r = b / nch;
+    const int x0 = (int)(b % nch) * 64;
+    const int rows_j = AXIS == 1 ? G.ny + 1 : G.ny;
+    const int fj = (int)(r % rows_j), fk = (int)(r / rows_j);
+    // fill the LDS rows (mirrored cells stored mirrored); slots past x = nx + 1 are never read
+    const int64_t ncg = P.ncell;
+    for (int e = threadIdx.x; e < NRW; e += 256) {
+        const int row = e / ROW3, x = x0 - 2 + e % ROW3;
+        if (x > G.nx + 1) continue;
+        int rj = 0, rk = 0;
+        static_for<0, NROW>([&](auto Ri) {
+            constexpr int ri = decltype(Ri)::value;
+            if (row == ri) {
+                rj = Rows3<AXIS>::rj(ri);
+                rk = Rows3<AXIS>::rk(ri);
+            }
+        });
+        int mir;
+        const int src = map3(G, x, fj + rj, fk + rk, mir);
+        static_for<0, NR3>([&](auto Pi) {
+            constexpr int pl = decltype(Pi)::value;
+            // planes 0-2: velocity; 6-21: f coefficients 4..19; 22-31: g coefficients 0..9
+            constexpr int pm = pl < 3 ? (1 << pl) : (pl >= R3_F && pl < R3_G) ? par3(pl - R3_F + 4)
+                                                 : pl >= R3_G ? par3(pl - R3_G) : 0;
+            const R v = grec[pl * ncg + src];
+            lds[pl * NRW + e] = (__popc(mir & pm) & 1) ? -v : v;
+        });
+    }
+    __syncthreads();
+    const R *rec = lds;
+    const int64_t nc = NRW;
+    const int fb = threadIdx.x >> 2, n = threadIdx.x & 3;
+    const int i = x0 + fb;
+    const int64_t nf = P.nface;
     FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
     bool counted = false;
-    if (fl < G.nfa[AXIS]) {
+    if (i < len) {
         counted = (n == 0);
         constexpr int T1 = Tan<AXIS>::t1, T2 = Tan<AXIS>::t2;
-        // cell R of the face (L is one step back along the normal)
-        int ci, cj, ck;
-        if (AXIS == 0) {
-            ci = (int)(fl % (G.nx + 1));
-            const int64_t r = fl / (G.nx + 1);
-            cj = (int)(r % G.ny);
-            ck = (int)(r / G.ny);
-        } else if (AXIS == 1) {
-            ci = (int)(fl % G.nx);
-            const int64_t r = fl / G.nx;
-            cj = (int)(r % (G.ny + 1));
-            ck = (int)(r / (G.ny + 1));
-        } else {
-            ci = (int)(fl % G.nx);
-            const int64_t r = fl / G.nx;
-            cj = (int)(r % G.ny);
-            ck = (int)(r / G.ny);
-        }
-        const int64_t f = G.foff[AXIS] + fl;
+        const int64_t f = G.foff[AXIS] + (int64_t)i + (int64_t)len * r;
         int st[12];
-        unsigned long long mr = 0ull;
-        {
-            int e[3] = {0, 0, 0};
-            // offsets (normal, t1, t2) of the stencil cells from R
-            const int on[12] = {-1, 0, -2, 1, -1, -1, 0, 0, -1, -1, 0, 0};
-            const int o1[12] = {0, 0, 0, 0, -1, 1, -1, 1, 0, 0, 0, 0};
-            const int o2[12] = {0, 0, 0, 0, 0, 0, 0, 0, -1, 1, -1, 1};
+        const unsigned long long mr = 0ull;
 #pragma unroll
-            for (int q = 0; q < 12; ++q) {
-                e[AXIS] = on[q];
-                e[T1] = o1[q];
-                e[T2] = o2[q];
-                int mi;
-                st[q] = map3(G, ci + e[0], cj + e[1], ck + e[2], mi);
-                mr |= (unsigned long long)mi << (3 * q);
-            }
-        }
+        for (int q = 0; q < 12; ++q) st[q] = Rows3<AXIS>::row(q) * ROW3 + (i - x0 + 2) + Rows3<AXIS>::dx(q);
         const R hdn = (R)(0.5 * dt / G.dx[AXIS]), hdt1 = (R)(0.5 * dt / G.dx[T1]),
                 hdt2 = (R)(0.5 * dt / G.dx[T2]);
         // mean frame of L and R (restart frame, first seed), as in the 2D kernels
         R um[3], Tm;
         {
             R uL[3], uR[3], sL, sR;
-            load_frame3(rec, nc, st[0], (int)(mr & 7ull), uL, sL);
-            load_frame3(rec, nc, st[1], (int)((mr >> 3) & 7ull), uR, sR);
+            load_frame3(rec, nc, st[0], 0, uL, sL);
+            load_frame3(rec, nc, st[1], 0, uR, sR);
             const R ra = rec[R3_RHO * nc + st[0]], rb = rec[R3_RHO * nc + st[1]];
             const R Sm = ra + rb, iS = (sizeof(R) == 4) ? frcp(Sm) : R(1) / Sm;
             const R wa = ra * iS, wb = rb * iS;
