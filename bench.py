@@ -143,10 +143,19 @@ def other_workload(args):
     else:
         make = lambda tol: W.tube_batch(tol=tol)
     out = {}
-    for prec, tol in (("mixed", W.TOL_FP32), ("fp64", W.TOL_FP64)):
+    forms = [("mixed", "mixed", W.TOL_FP32, "prev"), ("fp64", "fp64", W.TOL_FP64, "prev")]
+    net = None
+    if name == "shocked_interface" and not args.no_learned:
+        # the configuration that names the learned frame guess: the same steps with the seed
+        # network (trained on shock-tube and double Mach frames) on the hard faces
+        net, train_info = train_seed_network()
+        forms.insert(1, ("learned_mixed", "mixed", W.TOL_FP32, "mlp"))
+    for form, prec, tol, seed in forms:
         cfg, fields = make(tol)
         cfg["scheme"] = args.scheme
-        ctx = pond.Context(cfg, fields, precision=prec)
+        ctx = pond.Context(cfg, fields, precision=prec, seed=seed)
+        if seed == "mlp":
+            ctx.load_mlp(net, hard_iters=2)
         if args.warmup:
             ctx.step(args.warmup, check=False)
         ctx.autotune()
@@ -159,11 +168,15 @@ def other_workload(args):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         kt = ctx.kernel_times()
-        out[prec] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
+        out[form] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
                      "cell_updates": st["cell_updates"], "mean_iters": st["iters_total"] / max(st["faces"], 1),
                      "failed_instances": st["failed_instances"], "status": st["status"],
                      "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
-                                   "cell": kt["cell"]}, "tiles": list(ctx.tiles())}
+                                   "cell": kt["cell"], "seed": kt["seed"]}, "tiles": list(ctx.tiles())}
+        if form == "learned_mixed":
+            out[form]["train"] = train_info
+        if net is not None and form in ("mixed", "learned_mixed"):
+            out[form]["U"] = ctx.conserved()
         ctx.close()
         if name == "tubes" and args.scheme == "fv":
             # the same steps with the resident kernel (one block per tube, every step in one
@@ -212,6 +225,10 @@ def other_workload(args):
             n = cfg["nx"] * cfg["ny"]
             cpu = {"value": n * steps / el / 1e6, "unit": "Mcell-updates/s", "cores": oracle.num_threads(),
                    "kind": "oracle", "sample": f"first {steps} steps from t=0 (FP64); {el:.1f} s"}
+    if "learned_mixed" in out:
+        # the learned form against the plain one after the same steps from the same state
+        Ul, Um = out["learned_mixed"].pop("U"), out["mixed"].pop("U")
+        out["learned_mixed"]["rel_l1_vs_plain_mixed"] = rel_l1(Ul, Um)
     m = out["mixed"]
     best = m
     if "resident" in m and m["resident"]["value"] > m["value"]:
@@ -226,7 +243,8 @@ def other_workload(args):
                    "scheme": args.scheme,
                    "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
         "roofline": tube_roofline(m, args.steps) if name == "tubes" and args.scheme == "fv" else None,
-        "mixed": m, "fp64_plain": out["fp64"], "cpu_baseline": cpu,
+        "mixed": m, "fp64_plain": out["fp64"], "learned_mixed": out.get("learned_mixed"),
+        "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
 
@@ -482,6 +500,28 @@ def cpu_model():
     return "unknown"
 
 
+def train_seed_network(nx=1920, ny=480, regularization="grad"):
+    """The seed network trained on face frames the solver produces on the two plain-method
+    workloads: the double Mach reflection on a 4x coarser grid, and the 400-cell shock tube
+    as a y-uniform strip (the network's inputs are 2D stencils)."""
+    from paper_2203_05477_amd import learned_seed as LS
+    from paper_2203_05477_amd import workloads as W
+
+    t0 = time.perf_counter()
+    cfgh, fh = W.double_mach(nx // 4, ny // 4, tol=W.TOL_FP32)
+    cfgh["regularization"] = regularization
+    c1, f1 = W.shock_tube(400, tol=W.TOL_FP32)
+    cs, fs = W.strip_2d(c1, f1, ny=4)
+    data = [LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2),
+            LS.harvest(cs, fs, steps=500, precision="mixed", hard_iters=2)]
+    net, losses, nsamp = LS.train(data, epochs=20, batch=4096, lr=2e-3)
+    info = {"samples": nsamp, "sources": {f"double_mach_{nx // 4}x{ny // 4}_300_steps": int(data[0][0].shape[0]),
+                                          "shock_tube_400_strip_500_steps": int(data[1][0].shape[0])},
+            "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
+            "seconds": time.perf_counter() - t0}
+    return net, info
+
+
 def double_mach_workload(args):
     """The headline: the 1920 x 480 double Mach reflection, every form timed over the same
     windows of K steps, each window started from one state.
@@ -546,23 +586,7 @@ def double_mach_workload(args):
     tiles = tuple(int(v) for v in args.tiles.split("x")) if args.tiles else None
     net, train_info = None, None
     if not args.no_learned:
-        from paper_2203_05477_amd import learned_seed as LS
-
-        t0 = time.perf_counter()
-        # face frames the solver produces on the two plain-method workloads: the double
-        # Mach reflection on a 4x coarser grid, and the 400-cell shock tube as a y-uniform
-        # strip (the network's inputs are 2D stencils)
-        cfgh, fh = W.double_mach(nx // 4, ny // 4, tol=W.TOL_FP32)
-        cfgh["regularization"] = args.regularization
-        c1, f1 = W.shock_tube(400, tol=W.TOL_FP32)
-        cs, fs = W.strip_2d(c1, f1, ny=4)
-        data = [LS.harvest(cfgh, fh, steps=300, precision="mixed", hard_iters=2, every=2),
-                LS.harvest(cs, fs, steps=500, precision="mixed", hard_iters=2)]
-        net, losses, nsamp = LS.train(data, epochs=20, batch=4096, lr=2e-3)
-        train_info = {"samples": nsamp, "sources": {"double_mach_480x120_300_steps": int(data[0][0].shape[0]),
-                                                    "shock_tube_400_strip_500_steps": int(data[1][0].shape[0])},
-                      "loss_first": float(losses[0]), "loss_last": float(losses[-1]),
-                      "seconds": time.perf_counter() - t0}
+        net, train_info = train_seed_network(nx, ny, args.regularization)
 
     forms = [("mixed", "mixed", W.TOL_FP32, "prev"), ("mixed_tol1e-6", "mixed", 1e-6, "prev")]
     if net is not None:
