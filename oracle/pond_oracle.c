@@ -542,7 +542,6 @@ orc_sim *orc_create3(const orc_config *cfg, const double *rho, const double *ux,
     if (cfg->dim >= 2 && cfg->ny < 2) return NULL;
     if (cfg->dim == 3 && cfg->nz < 2) return NULL;
     if (!(cfg->gamma > 1.0)) return NULL;
-    if (cfg->scheme == ORC_SCHEME_SL && cfg->dim != 1) return NULL; /* 1D only */
     if (cfg->dim == 3) {
         /* 3D: Grad projection, finite volumes, and the periodic / outflow / reflecting sides */
         if (cfg->reg != ORC_REG_GRAD || cfg->scheme != ORC_SCHEME_FV) return NULL;
@@ -1044,16 +1043,18 @@ static double time_step(const orc_sim *s, double t_end)
 }
 
 /* ------------------------------------------------------------------------- */
-/* the semi-Lagrangian realization (Sec. III.A), 1D                          */
+/* the semi-Lagrangian realization (Sec. III.A), 1D and 2D                  */
 /* ------------------------------------------------------------------------- */
 
 /* Readings (the paper's interpolation recipe is in a cited thesis, not in the paper):
  *  - collocation points are the cell centres; a population is interpolated at its
- *    departure point from the 4 collocation points around it (2 on each side), all of
- *    them transformed into the current frame by the regularized transformation;
- *  - the 4-point kernel is the interpolating cubic (Catmull-Rom) spline, and the
- *    limiter clips the value into the range of the two collocation points that enclose
- *    the departure point;
+ *    departure point from the 4 collocation points around it along each axis (2 on each
+ *    side: 4 in 1D, the 4 x 4 centres around it in 2D), all of them transformed into the
+ *    current frame by the regularized transformation;
+ *  - the 4-point kernel is the interpolating cubic (Catmull-Rom) spline, in 2D its tensor
+ *    product (the 1D kernel along x, then along y); the limiter clips the value into the
+ *    range of the collocation points that enclose the departure point (the two around it
+ *    in 1D, the four corners of the square of centres around it in 2D);
  *  - the frame iteration starts from the cell's own frame of the previous step (the
  *    paper's seed) and stops as the face iteration does (tolerance, 2-cycle, max_iter);
  *    a cell whose iteration does not converge keeps its last advected populations;
@@ -1069,57 +1070,99 @@ static void catmull_rom(double t, double w[4])
     w[3] = 0.5 * (t3 - t2);
 }
 
-/* one cell: frame iteration of the advection, then the collision; writes the new
- * populations (and their frame) into *out */
-static void sl_cell(const orc_sim *s, int j, double dt, cellrec *out, int *iters, int *conv_out,
+/* one cell (ci, cj): frame iteration of the advection, then the collision; writes the new
+ * populations (and their frame) into *out. The stencil is the 5 (1D) or 5 x 5 (2D) cells
+ * centred on the cell, stencil slot a + 5 b holding cell (ci - 2 + a, cj - 2 + b). */
+static void sl_cell(const orc_sim *s, int ci, int cj, double dt, cellrec *out, int *iters, int *conv_out,
                     long long *depout)
 {
-    const int Q = s->Q;
-    tensors Mf[5], Mg[5];
-    for (int k = 0; k < 5; ++k) {
-        const cellrec *c = &s->plus[cidx(s, j - 2 + k, 0)];
-        moments(&s->L, c->f, c->u, c->T, &Mf[k]);
-        moments(&s->L, c->g, c->u, c->T, &Mg[k]);
-    }
-    const cellrec *own = &s->plus[cidx(s, j, 0)];
-    double lu[MAXD] = {own->u[0], 0.0}, lT = own->T;
-    double pu = 0.0, pT = 1.0;
-    double fa[MAXQ], ga[MAXQ], fu = lu[0], fT = lT;
+    const int Q = s->Q, D = s->D;
+    const int nst = (D == 1) ? 5 : 25;
+    tensors Mf[25], Mg[25];
+    for (int b = 0; b < (D == 1 ? 1 : 5); ++b)
+        for (int a = 0; a < 5; ++a) {
+            const cellrec *c = &s->plus[cidx(s, ci - 2 + a, D == 1 ? 0 : cj - 2 + b)];
+            moments(&s->L, c->f, c->u, c->T, &Mf[a + 5 * b]);
+            moments(&s->L, c->g, c->u, c->T, &Mg[a + 5 * b]);
+        }
+    const cellrec *own = &s->plus[cidx(s, ci, D == 1 ? 0 : cj)];
+    double lu[MAXD] = {own->u[0], D == 2 ? own->u[1] : 0.0, 0.0}, lT = own->T;
+    double pu[MAXD] = {0.0, 0.0, 0.0}, pT = 1.0;
+    double fa[MAXQ], ga[MAXQ], fu[MAXD] = {lu[0], lu[1], 0.0}, fT = lT;
     int it, conv = 0, have_pp = 0;
     for (it = 1; it <= s->cfg.max_iter; ++it) {
-        double Pf[5][MAXQ], Pg[5][MAXQ], v[MAXQ][MAXD];
-        for (int k = 0; k < 5; ++k) {
+        double Pf[25][MAXQ], Pg[25][MAXQ], v[MAXQ][MAXD];
+        for (int k = 0; k < nst; ++k) {
             project_f(&s->L, s->cfg.reg, &Mf[k], lu, lT, Pf[k]);
             grad_project(&s->L, 2, &Mg[k], lu, lT, Pg[k]);
         }
         velocities(&s->L, lu, lT, v);
         for (int i = 0; i < Q; ++i) {
-            /* departure point x_j - v_i dt, in cells: d in (-1, 1) while the CFL rule holds */
-            const double d = -v[i][0] * dt / s->dx[0];
-            if (fabs(d) >= 1.0) ++*depout;
-            const int m = (d < 0.0) ? -1 : 0; /* base cell j + m, fraction d - m in [0, 1) */
-            double w[4];
-            catmull_rom(d - m, w);
-            double vf = 0.0, vg = 0.0;
-            for (int q = 0; q < 4; ++q) {
-                vf += w[q] * Pf[m + 1 + q][i];
-                vg += w[q] * Pg[m + 1 + q][i];
+            /* departure point x_c - v_i dt, in cells along each axis: each component lies in
+             * (-1, 1) while the CFL rule holds; base cell c + m, fraction d - m in [0, 1) */
+            double w[2][4];
+            int m[2] = {0, 0}, out_of_cell = 0;
+            for (int ax = 0; ax < D; ++ax) {
+                const double d = -v[i][ax] * dt / s->dx[ax];
+                if (fabs(d) >= 1.0) out_of_cell = 1;
+                m[ax] = (d < 0.0) ? -1 : 0;
+                catmull_rom(d - m[ax], w[ax]);
             }
-            const double f1 = Pf[m + 2][i], f2 = Pf[m + 3][i];
-            const double g1 = Pg[m + 2][i], g2 = Pg[m + 3][i];
-            fa[i] = fmin(fmax(vf, fmin(f1, f2)), fmax(f1, f2));
-            ga[i] = fmin(fmax(vg, fmin(g1, g2)), fmax(g1, g2));
+            if (out_of_cell) ++*depout;
+            if (D == 1) {
+                const int o = m[0];
+                double vf = 0.0, vg = 0.0;
+                for (int q = 0; q < 4; ++q) {
+                    vf += w[0][q] * Pf[o + 1 + q][i];
+                    vg += w[0][q] * Pg[o + 1 + q][i];
+                }
+                const double f1 = Pf[o + 2][i], f2 = Pf[o + 3][i];
+                const double g1 = Pg[o + 2][i], g2 = Pg[o + 3][i];
+                fa[i] = fmin(fmax(vf, fmin(f1, f2)), fmax(f1, f2));
+                ga[i] = fmin(fmax(vg, fmin(g1, g2)), fmax(g1, g2));
+            } else {
+                /* along x in each of the 4 rows, then along y */
+                double vf = 0.0, vg = 0.0;
+                for (int qy = 0; qy < 4; ++qy) {
+                    double rf = 0.0, rg = 0.0;
+                    for (int qx = 0; qx < 4; ++qx) {
+                        const int k = (m[0] + 1 + qx) + 5 * (m[1] + 1 + qy);
+                        rf += w[0][qx] * Pf[k][i];
+                        rg += w[0][qx] * Pg[k][i];
+                    }
+                    vf += w[1][qy] * rf;
+                    vg += w[1][qy] * rg;
+                }
+                double flo = INFINITY, fhi = -INFINITY, glo = INFINITY, ghi = -INFINITY;
+                for (int cy = 0; cy < 2; ++cy)
+                    for (int cx = 0; cx < 2; ++cx) {
+                        const int k = (m[0] + 2 + cx) + 5 * (m[1] + 2 + cy);
+                        flo = fmin(flo, Pf[k][i]);
+                        fhi = fmax(fhi, Pf[k][i]);
+                        glo = fmin(glo, Pg[k][i]);
+                        ghi = fmax(ghi, Pg[k][i]);
+                    }
+                fa[i] = fmin(fmax(vf, flo), fhi);
+                ga[i] = fmin(fmax(vg, glo), ghi);
+            }
         }
-        fu = lu[0];
+        for (int a = 0; a < D; ++a) fu[a] = lu[a];
         fT = lT;
-        double rho, nu[MAXD] = {0, 0}, nT;
+        double rho, nu[MAXD] = {0, 0, 0}, nT;
         macro(s, fa, ga, lu, lT, &rho, nu, &nT);
         if (!(rho > 0.0) || !(nT > 0.0) || !isfinite(nT)) break; /* the cell fails */
-        double delta = fmax(fabs(nu[0] - lu[0]) / sqrt(nT), fabs(nT - lT) / nT);
-        double delta2 = fmax(fabs(nu[0] - pu) / sqrt(nT), fabs(nT - pT) / nT);
-        pu = lu[0];
+        double du = 0.0, du2 = 0.0;
+        for (int a = 0; a < D; ++a) {
+            du = fmax(du, fabs(nu[a] - lu[a]));
+            du2 = fmax(du2, fabs(nu[a] - pu[a]));
+        }
+        double delta = fmax(du / sqrt(nT), fabs(nT - lT) / nT);
+        double delta2 = fmax(du2 / sqrt(nT), fabs(nT - pT) / nT);
+        for (int a = 0; a < D; ++a) {
+            pu[a] = lu[a];
+            lu[a] = nu[a];
+        }
         pT = lT;
-        lu[0] = nu[0];
         lT = nT;
         if (delta <= s->cfg.tol) {
             conv = 1;
@@ -1136,42 +1179,45 @@ static void sl_cell(const orc_sim *s, int j, double dt, cellrec *out, int *iters
     for (int i = 0; i < Q; ++i) rho += fa[i];
     const double eps = dt * rho * fT / s->cfg.mu;
     const double b2 = 2.0 * eps / (2.0 + eps); /* 2 beta */
-    const double geq = (s->Cv - 0.5 * s->D) * rho * fT;
+    const double geq = (s->Cv - 0.5 * D) * rho * fT;
     for (int i = 0; i < Q; ++i) {
         out->f[i] = fa[i] + b2 * (rho * s->L.W[i] - fa[i]);
         out->g[i] = ga[i] + b2 * (geq * s->L.W[i] - ga[i]);
     }
-    out->u[0] = fu;
-    out->u[1] = 0.0;
+    out->u[0] = fu[0];
+    out->u[1] = fu[1];
     out->T = fT;
     out->rho = rho;
 }
 
 static int sl_step(orc_sim *s, double t_end, orc_stats *st)
 {
-    const int nx = s->nx;
-    for (int i = 0; i < nx; ++i) {
-        cellrec tmp;
-        reframe_cell(s, &s->cell[cidx(s, i, 0)], &tmp);
-        s->cell[cidx(s, i, 0)] = tmp;
-    }
+    const int nx = s->nx, ny = (s->D == 1) ? 1 : s->ny;
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            cellrec tmp;
+            reframe_cell(s, &s->cell[cidx(s, i, j)], &tmp);
+            s->cell[cidx(s, i, j)] = tmp;
+        }
     const double dt = time_step(s, t_end);
-    for (int i = 0; i < nx; ++i) s->plus[cidx(s, i, 0)] = s->cell[cidx(s, i, 0)];
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) s->plus[cidx(s, i, j)] = s->cell[cidx(s, i, j)];
     fill_ghosts(s);
     long long itot = 0, nonc = 0, depout = 0;
     int imax = 0;
-#pragma omp parallel for reduction(+ : itot, nonc, depout) reduction(max : imax) schedule(dynamic, 16)
-    for (int i = 0; i < nx; ++i) {
-        int it, conv;
-        sl_cell(s, i, dt, &s->cell[cidx(s, i, 0)], &it, &conv, &depout);
-        itot += it;
-        if (it > imax) imax = it;
-        if (!conv) ++nonc;
-    }
+#pragma omp parallel for collapse(2) reduction(+ : itot, nonc, depout) reduction(max : imax) schedule(dynamic, 16)
+    for (int j = 0; j < ny; ++j)
+        for (int i = 0; i < nx; ++i) {
+            int it, conv;
+            sl_cell(s, i, j, dt, &s->cell[cidx(s, i, j)], &it, &conv, &depout);
+            itot += it;
+            if (it > imax) imax = it;
+            if (!conv) ++nonc;
+        }
     s->t += dt;
     s->nstep += 1;
     if (st) {
-        st->faces = nx;
+        st->faces = (long long)nx * ny;
         st->iters_total = itot;
         st->iters_max = imax;
         st->nonconverged = nonc;

@@ -36,7 +36,7 @@ enum { ORC_LIM_VANLEER = 0, ORC_LIM_MINMOD = 1 };
 enum { ORC_REG_GRAD = 0, ORC_REG_EQ = 1 };
 
 /* discretization: the finite-volume scheme (Sec. III.B, the paper's main one) or the
- * semi-Lagrangian realization (Sec. III.A; 1D only here) */
+ * semi-Lagrangian realization (Sec. III.A; 1D and 2D here) */
 enum { ORC_SCHEME_FV = 0, ORC_SCHEME_SL = 1 };
 
 typedef struct {

@@ -1,6 +1,6 @@
-"""Pins of the oracle's semi-Lagrangian realization (Sec. III.A, 1D): frame iteration of
-the advection from the departure points, interpolating cubic kernel with a clipping
-limiter over the cell centres, BGK collision."""
+"""Pins of the oracle's semi-Lagrangian realization (Sec. III.A) in 1D (the 2D pins are
+in test_oracle_sl2d.py): frame iteration of the advection from the departure points,
+interpolating cubic kernel with a clipping limiter over the cell centres, BGK collision."""
 import math
 
 import numpy as np
@@ -79,7 +79,7 @@ def test_mirror_symmetry(orc):
     assert np.abs(T - T[::-1]).max() < 1e-13
 
 
-def test_two_dimensions_are_not_built(orc):
-    cfg, f = W.double_mach(16, 8)
+def test_three_dimensions_are_not_built(orc):
+    cfg, f = W.random_smooth_3d(6, 5, 4, seed=1)
     with pytest.raises(Exception):
-        orc.Sim(_sl(cfg), f["rho"], f["ux"], f["uy"], f["p"])
+        orc.Sim(_sl(cfg), f["rho"], f["ux"], f["uy"], f["p"], uz=f["uz"])
