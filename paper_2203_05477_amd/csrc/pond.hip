@@ -320,13 +320,21 @@ hipError_t launch_step(pond_ctx *c, double t_end)
         if (e != hipSuccess) return e;
     }
     if (tm) (void)hipEventRecord(c->ev[2], c->stream);
-    if (D == 1 && semi_lagrangian(c)) {
+    if (semi_lagrangian(c)) {
         // semi-Lagrangian step: every cell into the staging buffers, then committed
-        const size_t lds = (size_t)(256 + 4 + 4 * c->sl_span) * Layout<1>::NL * sizeof(R);
-        sl_kernel_1d<R><<<blocks(c->P.ncell, 256), 256, lds, c->stream>>>(c->P, S, c->sl_span, c->slot);
+        if (D == 1) {
+            const size_t lds = (size_t)(256 + 4 + 4 * c->sl_span) * Layout<1>::NL * sizeof(R);
+            sl_kernel_1d<R><<<blocks(c->P.ncell, 256), 256, lds, c->stream>>>(c->P, S, c->sl_span, c->slot);
+        } else {
+            const int nb = ((c->P.nx + SL2_T - 1) / SL2_T) * ((c->P.ny + SL2_T - 1) / SL2_T);
+            if (reg_of(c))
+                sl_kernel_2d<R, 1><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+            else
+                sl_kernel_2d<R, 0><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+        }
         if (tm) (void)hipEventRecord(c->ev[3], c->stream);
         if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-        sl_commit_kernel<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S);
+        sl_commit_kernel<R><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->nh);
         if (tm) (void)hipEventRecord(c->ev[5], c->stream);
         c->slot ^= 1;
         return hipGetLastError();
@@ -483,7 +491,7 @@ pond_status validate(const pond_config *cfg, const double *rho, const double *ux
     if (cfg->precision != POND_FP64 && cfg->precision != POND_MIXED) return POND_EINVAL;
     if (cfg->limiter != POND_LIM_VANLEER && cfg->limiter != POND_LIM_MINMOD) return POND_EINVAL;
     if (cfg->flags & ~(POND_FLAG_STRICT | POND_FLAG_REG_EQ | POND_FLAG_SEMI_LAGRANGIAN)) return POND_EINVAL;
-    if ((cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) && (cfg->dim != 1 || cfg->seed_mode != POND_SEED_PREV))
+    if ((cfg->flags & POND_FLAG_SEMI_LAGRANGIAN) && (cfg->dim > 2 || cfg->seed_mode != POND_SEED_PREV))
         return POND_EINVAL;
     double Cv = 1.0 / (cfg->gamma - 1.0);
     if (!(Cv - 0.5 * cfg->dim > 0.0)) return POND_EINVAL;
@@ -1329,7 +1337,7 @@ pond_status pond_get_tiles(const pond_ctx *c, int32_t *bx, int32_t *by, int32_t 
 pond_status pond_autotune(pond_ctx *c)
 {
     if (!c) return POND_EINVAL;
-    if (c->D == 3) return POND_OK; // one launch shape in 3D
+    if (c->D == 3 || semi_lagrangian(c)) return POND_OK; // one launch shape in 3D and for the SL kernels
     // the face kernel is the dominant cost; time it on the current state. It only writes
     // face state, which is saved first and restored afterwards (the next step's seeds).
     const size_t fbytes = c->rsize * c->nfp * c->P.nface;

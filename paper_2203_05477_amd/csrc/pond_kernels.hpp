@@ -2105,15 +2105,254 @@ __global__ __launch_bounds__(256) void sl_kernel_1d(Params P, State<R> S, int sp
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
-// the staged state becomes the current one
+
+// 2D: one thread per cell, 16 x 16 cells per 256-thread block. The LDS tile holds the
+// records (at eps = 0: the carried populations themselves) of the block's cells and two
+// layers of neighbours around them, 20 x 20, ghosts through the side rules. Per
+// iteration each of the 25 cells of the 5 x 5 stencil around the cell is transformed
+// into the current frame once; each population takes the tensor product of the cubic
+// kernel along x (the row sums) and along y over the departure point's 4 x 4 centres, and
+// is clipped into the range of the 4 centres around its departure point (the cell's own,
+// and the neighbours on the departure side along x, along y and diagonally). f first,
+// then g: the moments of the advected populations give the next frame. Collision, new
+// state and staging as in 1D.
+constexpr int SL2_T = 16;             // cells per tile side
+constexpr int SL2_W = SL2_T + 4;      // LDS tile side (two neighbours each way)
+constexpr int SL2_NT = SL2_W * SL2_W; // records in the tile
+
+// The interpolating cubic as a kernel of the distance x >= 0 to a centre (the Catmull-Rom
+// spline, cubic convolution with a = -1/2): 1 - 5/2 x^2 + 3/2 x^3 on [0, 1],
+// 2 - 4 x + 5/2 x^2 - 1/2 x^3 on [1, 2], zero beyond. A point at d cells from the middle
+// centre (|d| < 1) takes weight K(|d - o|) from the centre at offset o: the 4 around it.
 template <typename R>
-__global__ void sl_commit_kernel(Params P, State<R> S)
+PD R cubic_kernel(R x)
+{
+    const R x2 = x * x, x3 = x2 * x;
+    const R inner = fma(R(1.5), x3, fma(R(-2.5), x2, R(1)));
+    const R outer = fma(R(-0.5), x3, fma(R(2.5), x2, fma(R(-4), x, R(2))));
+    return x <= R(1) ? inner : (x < R(2) ? outer : R(0));
+}
+
+// advected reduced populations of one kind (f: G = false, g: G = true) in frame (ux, uy,
+// s): node column ix departs dx[ix] cells along x, node row iy dy[iy] along y. The row
+// sums along x of each stencil row, then the sum along y; the clip range is taken over the
+// centres at offsets 0 and -1 (departure on the lower side) or +1 along each axis. One
+// stencil cell at a time (loops not unrolled), so that only one cell's populations are
+// live.
+template <typename R, bool G, int REG>
+PD void sl_advect_2d(const R *L, int base, R ux, R uy, R inv_s, const R dx[4], const R dy[4], R out[16])
+{
+    R acc[16], lo[16], hi[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        acc[i] = R(0);
+        lo[i] = R(INFINITY);
+        hi[i] = R(-INFINITY);
+    }
+#pragma unroll 1
+    for (int b = 0; b < 5; ++b) {
+        R wy[4];
+        bool ry[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            wy[k] = cubic_kernel(fabs(dy[k] - R(b - 2)));
+            ry[k] = (b == 2) || (b == 1 && dy[k] < R(0)) || (b == 3 && !(dy[k] < R(0)));
+        }
+        R row[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) row[i] = R(0);
+#pragma unroll 1
+        for (int a = 0; a < 5; ++a) {
+            R wx[4];
+            bool cx[4];
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                wx[k] = cubic_kernel(fabs(dx[k] - R(a - 2)));
+                cx[k] = (a == 2) || (a == 1 && dx[k] < R(0)) || (a == 3 && !(dx[k] < R(0)));
+            }
+            R p[16];
+            cell_pops_2d<R, G, REG>(L, SL2_NT, base + a + SL2_W * b, ux, uy, inv_s, p);
+#pragma unroll
+            for (int i = 0; i < 16; ++i) {
+                row[i] = fma(wx[i & 3], p[i], row[i]);
+                const bool in = cx[i & 3] && ry[i >> 2];
+                lo[i] = in ? fmin(lo[i], p[i]) : lo[i];
+                hi[i] = in ? fmax(hi[i], p[i]) : hi[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[i] = fma(wy[i >> 2], row[i], acc[i]);
+    }
+#pragma unroll
+    for (int i = 0; i < 16; ++i) out[i] = fmin(fmax(acc[i], lo[i]), hi[i]);
+}
+
+template <typename R, int REG>
+__global__ __launch_bounds__(256) void sl_kernel_2d(Params P, State<R> S, int slot)
+{
+    __shared__ R L[Layout<2>::NL * SL2_NT];
+    const int tx = (int)blockIdx.x % ((P.nx + SL2_T - 1) / SL2_T);
+    const int ty = (int)blockIdx.x / ((P.nx + SL2_T - 1) / SL2_T);
+    const int i0 = tx * SL2_T, j0 = ty * SL2_T;
+    // the tile: cells (i0 - 2 .. i0 + 17, j0 - 2 .. j0 + 17); slots outside the two ghost
+    // layers belong to no stencil of a cell of the grid and are left unset
+    for (int v = threadIdx.x; v < SL2_NT; v += blockDim.x) {
+        const int i = i0 - 2 + v % SL2_W, j = j0 - 2 + v / SL2_W;
+        if (i < -2 || i >= P.nx + 2 || j < -2 || j >= P.ny + 2) continue;
+        const CellRef cr = map2d(P, i, j, S.tstart[0]);
+        plus_record<2, R>(P, S, cr, 0.0, L + v, SL2_NT, 0);
+    }
+    __syncthreads();
+    const int ci = i0 + (int)threadIdx.x % SL2_T, cj = j0 + (int)threadIdx.x / SL2_T;
+    const bool active = ci < P.nx && cj < P.ny;
+    const int64_t c = (int64_t)ci + (int64_t)P.nx * cj;
+    const double dt = S.dt[0];
+    const bool work = active && dt > 0.0;
+    FaceCount cnt{0, 0, 0, 0, 0, 0, 0};
+    unsigned long long bits = 0ull;
+    bool conv = false;
+    if (work) {
+        const int base = (int)threadIdx.x % SL2_T + SL2_W * ((int)threadIdx.x / SL2_T); // slot of (ci-2, cj-2)
+        const int own = base + 2 + 2 * SL2_W;
+        R lux = L[own], luy = L[SL2_NT + own], lT = L[17 * SL2_NT + own];
+        R pux = R(0), puy = R(0), pT = R(1), fux = lux, fuy = luy, fT = lT;
+        R mf[10], mg[10];
+        bool have_pp = false;
+        int it;
+        const R kx = (R)(dt / P.dx), ky = (R)(dt / P.dy);
+        for (it = 1; it <= P.max_iter; ++it) {
+            R s, inv_s;
+            frame_scale(lT, s, inv_s);
+            R dxk[4], dyk[4];
+            int outx = 0, outy = 0;
+#pragma unroll
+            for (int k = 0; k < 4; ++k) {
+                dxk[k] = -fma(s, node<R>(k), lux) * kx; // departure point, in cells
+                dyk[k] = -fma(s, node<R>(k), luy) * ky;
+                outx += fabs(dxk[k]) >= R(1);
+                outy += fabs(dyk[k]) >= R(1);
+            }
+            // populations whose departure point leaves the cell's square along either axis
+            cnt.depout += (unsigned long long)(4 * (outx + outy) - outx * outy);
+            {
+                R pa[16];
+                sl_advect_2d<R, false, REG>(L, base, lux, luy, inv_s, dxk, dyk, pa);
+                moments_2d(pa, mf, 10);
+            }
+            {
+                R ga[16];
+                sl_advect_2d<R, true, 0>(L, base, lux, luy, inv_s, dxk, dyk, ga);
+                moments_2d(ga, mg, 6);
+            }
+            fux = lux;
+            fuy = luy;
+            fT = lT;
+            const R rho = mf[0];
+            const R nux = fma(s, mf[1] / rho, lux), nuy = fma(s, mf[2] / rho, luy);
+            // rho E in frame (lu, s): sum (|v|^2/2) f + sum g, v = lu + s c
+            const R e = R(0.5) * (s * s * (mf[3] + mf[5]) + R(2) * s * (lux * mf[1] + luy * mf[2]) +
+                                  (lux * lux + luy * luy) * mf[0]) +
+                        mg[0];
+            const R nT = (e / rho - R(0.5) * (nux * nux + nuy * nuy)) / (R)P.Cv;
+            if (!(rho > R(0)) || !(nT > R(0)) || !isfinite(nT)) break;
+            const R ns = sqrt(nT);
+            const R delta = fmax(fmax(fabs(nux - lux), fabs(nuy - luy)) / ns, fabs(nT - lT) / nT);
+            const R delta2 = fmax(fmax(fabs(nux - pux), fabs(nuy - puy)) / ns, fabs(nT - pT) / nT);
+            pux = lux;
+            puy = luy;
+            pT = lT;
+            lux = nux;
+            luy = nuy;
+            lT = nT;
+            if (delta <= (R)P.tol) {
+                conv = true;
+                break;
+            }
+            if (have_pp && delta2 <= R(1e-2) * delta) break;
+            have_pp = true;
+        }
+        if (it > P.max_iter) it = P.max_iter;
+        cnt.iters = (unsigned long long)it;
+        cnt.itmax = (unsigned long long)it;
+        cnt.nonconv = conv ? 0ull : 1ull;
+        // collision in frame (fu, fT): p <- p + 2 beta (p_eq - p); the equilibria's moments
+        // in their own frame: rho (f) and g_eq (g) at degrees 00, 20 and 02, zero elsewhere
+        R sf, inv_sf;
+        frame_scale(fT, sf, inv_sf);
+        const double rho = (double)mf[0];
+        const double eps = dt * rho * (double)fT / P.mu;
+        const R b2 = (R)(2.0 * eps / (2.0 + eps));
+        const R geq = (R)((P.Cv - 1.0) * rho * (double)fT);
+#pragma unroll
+        for (int q = 1; q < 10; ++q)
+            if (q != 3 && q != 5) mf[q] = mf[q] - b2 * mf[q];
+        mf[3] = fma(b2, (R)rho - mf[3], mf[3]);
+        mf[5] = fma(b2, (R)rho - mf[5], mf[5]);
+        mg[0] = fma(b2, geq - mg[0], mg[0]);
+        mg[1] = mg[1] - b2 * mg[1];
+        mg[2] = mg[2] - b2 * mg[2];
+        mg[3] = fma(b2, geq - mg[3], mg[3]);
+        mg[4] = mg[4] - b2 * mg[4];
+        mg[5] = fma(b2, geq - mg[5], mg[5]);
+        // conserved variables of the new state and its coefficients in the new co-moving frame
+        const double su = (double)sf, ux = (double)fux, uy = (double)fuy;
+        double Un[4];
+        Un[0] = (double)mf[0];
+        Un[1] = ux * Un[0] + su * (double)mf[1];
+        Un[2] = uy * Un[0] + su * (double)mf[2];
+        Un[3] = 0.5 * (su * su * ((double)mf[3] + (double)mf[5]) +
+                       2.0 * su * (ux * (double)mf[1] + uy * (double)mf[2]) + (ux * ux + uy * uy) * Un[0]) +
+                (double)mg[0];
+        const int64_t n = P.ncell;
+        const double irn = 1.0 / Un[0];
+        const double unx = Un[1] * irn, uny = Un[2] * irn;
+        const double Tn = (Un[3] * irn - 0.5 * (unx * unx + uny * uny)) / P.Cv;
+        const bool ok = (Un[0] > 0.0) && (Tn > 0.0) && isfinite(Tn);
+        if (!ok) {
+            atomicOr(S.err, ERR_NONPHYS);
+            atomicOr(S.inst_err, 1);
+        }
+        const double sn = sqrt(fabs(Tn)), isn = 1.0 / sn;
+        const R r = (R)(su * isn), dxs = (R)((ux - unx) * isn), dys = (R)((uy - uny) * isn);
+        R hh[10];
+        shift_2d(mf, r, dxs, dys, 10);
+        mf[0] = (R)Un[0];
+        mu2h_2d(mf, hh, 10);
+#pragma unroll
+        for (int q = 0; q < 7; ++q) S.H2[q * n + c] = hh[3 + q];
+        shift_2d(mg, r, dxs, dys, 6);
+        mu2h_2d(mg, hh, 6);
+#pragma unroll
+        for (int q = 0; q < 5; ++q) S.H2[(7 + q) * n + c] = hh[1 + q];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) S.U2[q * n + c] = Un[q];
+        double rate = fmax((fabs(unx) + sn * CMAX) / P.dx, (fabs(uny) + sn * CMAX) / P.dy);
+        if (!ok) rate = 0.0;
+        bits = (unsigned long long)__double_as_longlong(rate);
+    } else if (active) {
+        // a finished run keeps its state
+        const int64_t n = P.ncell;
+        for (int q = 0; q < Layout<2>::NH; ++q) S.H2[q * n + c] = S.H[q * n + c];
+        for (int q = 0; q < 4; ++q) S.U2[q * n + c] = S.U[q * n + c];
+    }
+    vmax_update<R>(P, S, slot ^ 1, 0, work, bits);
+    stat_add4(S.stats, ST_FACES, work ? 1u : 0u, ST_NONCONV, (unsigned)cnt.nonconv, ST_CELLS, work ? 1u : 0u,
+              ST_CONV_CELLS, (work && conv) ? 1u : 0u);
+    stat_add32(S.stats, ST_ITERS, (unsigned)cnt.iters);
+    stat_add32(S.stats, ST_DEPOUT, (unsigned)cnt.depout);
+    stat_max32(S.stats, ST_ITMAX, (unsigned)cnt.itmax);
+    if (cnt.depout) atomicOr(S.err, ERR_DEPART);
+}
+
+// the staged state becomes the current one (nh coefficient planes, D + 2 conserved)
+template <typename R>
+__global__ void sl_commit_kernel(Params P, State<R> S, int nh)
 {
     const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const int64_t n = P.ncell;
     if (c >= n) return;
-    for (int q = 0; q < 4; ++q) S.H[q * n + c] = S.H2[q * n + c];
-    for (int q = 0; q < 3; ++q) S.U[q * n + c] = S.U2[q * n + c];
+    for (int q = 0; q < nh; ++q) S.H[q * n + c] = S.H2[q * n + c];
+    for (int q = 0; q < P.dim + 2; ++q) S.U[q * n + c] = S.U2[q * n + c];
 }
 
 // The tail work (blocks [0, 2 * TAIL_BLOCKS): TAIL_BLOCKS per axis) beside the update of
