@@ -268,7 +268,12 @@ pond_status pond_set_resident(pond_ctx *ctx, int32_t on);
  * The tail sums its moments in another order than the face kernel, so different k
  * give results that differ by rounding (tile shapes do not change results at all);
  * pond_autotune therefore leaves k alone. Ignored in 1D.
- * POND_EINVAL for k < 0. */
+ * With POND_FLAG_SEMI_LAGRANGIAN (2D) k applies to the cells' frame iterations
+ * (Sec. III.A): cells still iterating after k iterations continue, from the same state,
+ * in a tail kernel that spreads each cell's 25 stencil cells over 25 lanes (the same
+ * iteration, its sums taken in another order: different k differ by rounding). Default 2
+ * for the semi-Lagrangian step.
+ * POND_EINVAL for k < 0, and in 3D. */
 pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
 
 /* Measurement (no effect on results). Average device time in ms per step of each launch

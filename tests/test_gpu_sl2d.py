@@ -218,3 +218,34 @@ def test_graph_replay_and_resume_are_bitwise(tmp_path):
     assert np.array_equal(a.time(), b.time())
     a.close()
     b.close()
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_iteration_split_gives_the_same_state(precision):
+    """Cells still iterating after k iterations finish in the tail kernel, which builds the
+    stencil records from the state instead of the LDS tile and continues the same
+    iteration from the saved frames: k = 1 (nearly every cell of this case goes to the
+    tail: about 4 iterations per cell), k = 3 and the default give the state of k = 0 (no
+    tail) to rounding: the tail sums each population over the stencil in another order, so
+    a frame may stop one iteration apart at the tolerance (FP64: the parity bar, 1e-12 +
+    0.4 n tol after n steps; the mixed form at tol 1e-4: 1e-5), with iteration totals
+    within 1%."""
+    from paper_2203_05477_amd import pond
+
+    tol = 1e-13 if precision == "fp64" else 1e-4
+    cfg, f = W.random_smooth(2, 37, 21, seed=7, amp=0.25, cfl=0.4, tol=tol)
+    out = {}
+    for k in (0, 1, 3, None):
+        g = pond.Context(_sl(cfg), f, precision=precision)
+        if k is not None:
+            g.set_iter_split(k)
+        st = g.step(5)
+        out[k] = (g.conserved(), st["iters_total"], st["cell_updates"])
+        g.close()
+    bar = _bar(5, tol) if precision == "fp64" else 1e-5
+    for k in (1, 3, None):
+        e = _relerr(out[k][0], out[0][0])
+        _print("sl2d_split", precision=precision, k=k, err=e.max(), iters=out[k][1], iters_nosplit=out[0][1])
+        assert e.max() <= bar, (k, e)
+        assert out[k][2] == out[0][2]
+        assert abs(out[k][1] - out[0][1]) <= 0.01 * out[0][1], k
