@@ -67,11 +67,12 @@ def test_invalid_input_is_rejected(cfg, f):
 
 
 def test_unknown_flag_bits_are_rejected():
-    """Only POND_FLAG_STRICT and POND_FLAG_REG_EQ are defined: any other bit is an error."""
+    """Only POND_FLAG_STRICT, POND_FLAG_REG_EQ and POND_FLAG_SEMI_LAGRANGIAN are defined:
+    any other bit is an error."""
     lib = pond.load()
     cfg, f = W.double_mach(16, 8)
     c, keep = pond.make_config(cfg)
-    c.flags = 4
+    c.flags = 8
     arrs = [np.ascontiguousarray(np.asarray(f[k], dtype=np.float64)) for k in ("rho", "ux", "uy", "p")]
     P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
     h = ctypes.c_void_p()
@@ -121,3 +122,17 @@ def test_null_handles_and_strerror():
     names = [lib.pond_strerror(s).decode() for s in range(8)]
     assert names[0] == "ok" and len(set(names)) == 8
     assert lib.pond_strerror(99) == b"unknown status"
+
+
+def test_semi_lagrangian_is_refused_in_3d():
+    """The semi-Lagrangian step is built in 1D and 2D: pond_init3 refuses the flag."""
+    lib = pond.load()
+    cfg, f = W.random_smooth_3d(6, 5, 4, seed=1)
+    c, keep = pond.make_config(dict(cfg, scheme="sl"))
+    assert c.flags & pond.FLAG_SEMI_LAGRANGIAN
+    arrs = [np.ascontiguousarray(np.asarray(f[k], dtype=np.float64)) for k in ("rho", "ux", "uy", "uz", "p")]
+    P = lambda a: a.ctypes.data_as(ctypes.POINTER(ctypes.c_double))
+    h = ctypes.c_void_p()
+    assert lib.pond_init3(ctypes.byref(c), *[P(a) for a in arrs], ctypes.byref(h)) == EINVAL
+    assert not h.value
+    del keep
