@@ -64,6 +64,9 @@ L1_GATE = 1e-4
 # Algorithmic bytes of one 2D cell update (read U, coefficients and the cell's share of its
 # 4 face states, write U and coefficients), mixed / FP64
 CELL_BYTES_2D = {"mixed": 312, "fp64": 560}
+# the same with the state held as the 32 populations (--layout populations): the 12
+# coefficient planes read and written become 32
+CELL_BYTES_2D_POPS = {"mixed": 472, "fp64": 880}
 
 
 TRAFFIC_PROFILE = os.path.join(ROOT, "profiles", "double_mach_1920x480_face_traffic.md")
@@ -113,10 +116,10 @@ def tube_traffic(kernel):
     return rec["bytes_per_cell_update"] if h.hexdigest() == rec["sources_sha256"] else None
 
 
-def cell_update_hbm(st, kt, steps, precision):
+def cell_update_hbm(st, kt, steps, precision, layout="hermite"):
     fused = kt["tail"] > 0.01  # the tail launch (else only event overhead sits there)
     ms = kt["cell"] + (kt["tail"] if fused else 0.0)
-    alg = CELL_BYTES_2D[precision] * st["cell_updates"] / steps
+    alg = (CELL_BYTES_2D_POPS if layout == "populations" else CELL_BYTES_2D)[precision] * st["cell_updates"] / steps
     gbps = alg / (ms * 1e-3) / 1e9 if ms > 0 else None
     return {"bound": "hbm", "kernels": "tail_cell_kernel_2d + cell_marked_kernel_2d"
             if fused else "cell_kernel<2>", "ms": ms, "algorithmic_bytes": alg,
@@ -609,6 +612,8 @@ def double_mach_workload(args):
             if seed == "mlp":
                 ctx.load_mlp(net, hard_iters=2)
             ctx.load_state(w["ckpt"])
+            if args.layout == "populations":
+                ctx.set_state_layout("populations")
             if chosen:
                 ctx.set_tiles(chosen[0], chosen[1], 256)
             elif not args.no_autotune:
@@ -636,7 +641,7 @@ def double_mach_workload(args):
                 "tail_faces_per_step": st["tail_faces"] / K,
                 "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
                               "cell": kt["cell"], "seed": kt["seed"]},
-                "cell_update_hbm": cell_update_hbm(st, kt, K, prec),
+                "cell_update_hbm": cell_update_hbm(st, kt, K, prec, args.layout),
                 "rel_l1_vs_fp64_reference": dict(zip(("rho", "rho_u", "rho_v", "rho_E"), l1)),
                 "rel_l1_vs_fp64_tol1e-13": dict(zip(("rho", "rho_u", "rho_v", "rho_E"), l1t)),
                 "l1_gate": bool(max(l1) <= L1_GATE),
@@ -676,7 +681,8 @@ def double_mach_workload(args):
     peak = PEAK_FP32_TFLOPS if fp32 else PEAK_FP64_TFLOPS
     it_flops = FLOPS_FACE_ITER_EQ2 if args.regularization == "eq" else FLOPS_FACE_ITER[2]
     flop_kernel = bw["face_kernel_iters"] * it_flops + bw["face_kernel_faces"] * FLOPS_FACE_FINAL[2]
-    traffic = measured_traffic(b["tiles"] or []) if (args.regularization == "grad" and fp32) else None
+    traffic = (measured_traffic(b["tiles"] or [])
+               if (args.regularization == "grad" and fp32 and args.layout == "hermite") else None)
     kname = "face_kernel_2d<" + ("float" if fp32 else "double") + ", 0>"
     line = {
         "metric": METRIC,
@@ -694,7 +700,7 @@ def double_mach_workload(args):
         "config": {"workload": f"double_mach_reflection_{nx}x{ny}", "lattice": "D2Q16",
                    "form": best, "precision": "mixed (f32 populations, f64 conserved)" if fp32 else "fp64",
                    "seed": b["seed"], "tol": b["tol"], "cfl": cfg_ref["cfl"], "mu": cfg_ref["mu"],
-                   "regularization": args.regularization,
+                   "regularization": args.regularization, "state_layout": args.layout,
                    "window": f"steps {Wn}..{Wn + K} from t=0, from the FP64 reference state at step {Wn}",
                    "l1_gate": f"relative L1 <= {L1_GATE:g} per conserved field vs the FP64 form at the "
                               f"same iteration tolerance, after the same window from the same state, "
@@ -988,6 +994,10 @@ def main():
                     help="transformation of the f populations between frames: third-order Grad "
                          "projection (the paper's choice) or the alternative with the fast moments "
                          "at equilibrium (Sec. II.C)")
+    ap.add_argument("--layout", choices=["hermite", "populations"], default="hermite",
+                    help="double Mach: the timed forms hold the cell state as the 12 Hermite "
+                         "coefficients per cell (default) or as the 32 populations (the A/B of "
+                         "the state layout; no learned form)")
     ap.add_argument("--iter-split", type=int, default=None,
                     help="face iterations per face in the face kernel before the tail kernel takes "
                          "over (0: no tail kernel, the cell update is one kernel)")
@@ -1031,6 +1041,8 @@ def main():
     if args.scheme == "sl":
         double_mach_sl_workload(args)
         return
+    if args.layout == "populations":
+        args.no_learned = True  # the learned seed works on the default layout only
     double_mach_workload(args)
 
 

@@ -33,7 +33,7 @@
 extern "C" {
 #endif
 
-#define POND_ABI_VERSION 4
+#define POND_ABI_VERSION 5
 
 typedef enum {
     POND_OK = 0,
@@ -75,13 +75,26 @@ enum {
      * frame's temperature; the populations follow by moment inversion. Default: the
      * third-order Grad projection, the paper's choice. */
     POND_FLAG_REG_EQ = 2,
-    /* 1D only: the semi-Lagrangian realization of Sec. III.A instead of the finite-volume
-     * scheme: every cell iterates its frame with its populations advected from the
-     * departure points x - v_i dt (4-point interpolating cubic kernel over the cell centres,
-     * clipped into the range of the two enclosing cells), then relaxes with the BGK
+    /* 1D and 2D: the semi-Lagrangian realization of Sec. III.A instead of the
+     * finite-volume scheme: every cell iterates its frame with its populations advected
+     * from the departure points x - v_i dt (4-point interpolating cubic kernel over the
+     * cell centres, in 2D its tensor product over the 4 x 4 centres, clipped into the
+     * range of the centres that enclose the departure point), then relaxes with the BGK
      * collision of that section. Not conservative (the paper's point in favour of the
-     * finite-volume scheme). Not with the learned seed or the resident launch (EINVAL). */
+     * finite-volume scheme). Not with the learned seed or the resident launch, not in 3D
+     * (EINVAL). */
     POND_FLAG_SEMI_LAGRANGIAN = 4
+};
+
+/* How a 2D context holds each cell's populations between steps (pond_set_state_layout). */
+enum {
+    /* the non-equilibrium Hermite coefficients of f (7) and g (5) in the cell's own
+     * co-moving frame: the projections of Sec. II.C keep exactly these (f to degree 3, g
+     * to degree 2), so they determine the 2Q populations (default) */
+    POND_LAYOUT_HERMITE = 0,
+    /* the 2Q = 32 populations f_i, g_i themselves (Sec. III.B.4: each cell's populations
+     * in its own frame), one plane per population */
+    POND_LAYOUT_POPULATIONS = 1
 };
 
 /* Problem statement (paper Sec. IV: initial fields on a uniform grid, gamma, CFL,
@@ -275,6 +288,19 @@ pond_status pond_set_resident(pond_ctx *ctx, int32_t on);
  * for the semi-Lagrangian step.
  * POND_EINVAL for k < 0, and in 3D. */
 pond_status pond_set_iter_split(pond_ctx *ctx, int32_t k);
+
+/* 2D finite volumes: store the cell state between steps as the 32 populations
+ * (POND_LAYOUT_POPULATIONS, 32 planes of the population precision beside the FP64
+ * conserved variables) or as the 12 Hermite coefficients (POND_LAYOUT_HERMITE, the
+ * default); the current state is converted on the context's stream (the two are a change
+ * of basis, exact on the Gauss-Hermite nodes: results differ by rounding only). The step
+ * reads and writes the chosen layout; it exists to measure what the smaller state saves.
+ * The population layout is taken with the Van Leer limiter, the Grad projection and the
+ * plain seed only, and pond_save, pond_load, pond_populations and pond_load_mlp refuse it
+ * (POND_EINVAL; set POND_LAYOUT_HERMITE first). POND_EINVAL as well in 1D and 3D, with the
+ * semi-Lagrangian step, and for an unknown layout; POND_ENOMEM if the new planes cannot be
+ * allocated (the state is then unchanged). */
+pond_status pond_set_state_layout(pond_ctx *ctx, int32_t layout);
 
 /* Measurement (no effect on results). Average device time in ms per step of each launch
  * over the last pond_step call,

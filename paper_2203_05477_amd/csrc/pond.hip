@@ -26,6 +26,7 @@ struct pond_ctx {
     int D;
     int precision;
     int nh, nfp; // planes of H and F
+    int layout = POND_LAYOUT_HERMITE; // 2D: the state as coefficients (H) or populations
     size_t rsize;
     hipStream_t stream;
     hipStream_t own_stream;
@@ -193,26 +194,29 @@ size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
 // 1: the alternative regularization of the f populations (2D only; in 1D it changes nothing)
 int reg_of(const pond_ctx *c) { return (c->D == 2 && (c->cfg.flags & POND_FLAG_REG_EQ)) ? 1 : 0; }
 
-template <typename R, int LIM, int REG>
+template <typename R, int LIM, int REG, int LAY = 0>
 void launch_face_2d_reg(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
 {
     dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
     switch (face_nts(bx, by)) {
     case 256:
-        face_kernel_2d<R, LIM, 256, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 256, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         break;
     case 512:
-        face_kernel_2d<R, LIM, 512, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 512, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         break;
     default:
-        face_kernel_2d<R, LIM, 0, REG><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        face_kernel_2d<R, LIM, 0, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
     }
 }
 
+// (the population layout is taken with the Van Leer limiter and the Grad projection only)
 template <typename R, int LIM>
 void launch_face_2d(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
 {
-    if (reg_of(c))
+    if (c->layout == POND_LAYOUT_POPULATIONS)
+        launch_face_2d_reg<R, 0, 0, 1>(c, S, bx, by, lds);
+    else if (reg_of(c))
         launch_face_2d_reg<R, LIM, 1>(c, S, bx, by, lds);
     else
         launch_face_2d_reg<R, LIM, 0>(c, S, bx, by, lds);
@@ -223,7 +227,9 @@ void launch_face_tail_reg(pond_ctx *c, const State<R> &S)
 {
     // per axis, 1,024 blocks of 16 faces take the deferred faces in turn
     dim3 tgrid(NSLOT * 4, 2);
-    if (c->P.limiter == POND_LIM_MINMOD)
+    if (c->layout == POND_LAYOUT_POPULATIONS)
+        face_tail_kernel_2d<R, 0, 0, 1><<<tgrid, 256, 0, c->stream>>>(c->P, S);
+    else if (c->P.limiter == POND_LIM_MINMOD)
         face_tail_kernel_2d<R, 1, REG><<<tgrid, 256, 0, c->stream>>>(c->P, S);
     else
         face_tail_kernel_2d<R, 0, REG><<<tgrid, 256, 0, c->stream>>>(c->P, S);
@@ -234,12 +240,18 @@ template <typename R, int REG>
 void launch_tail_cells_reg(pond_ctx *c, const State<R> &S, hipEvent_t ev_mid)
 {
     const unsigned nb = 2 * TAIL_BLOCKS + (unsigned)blocks(c->P.ncell, 256);
-    if (c->P.limiter == POND_LIM_MINMOD)
+    const bool pops = c->layout == POND_LAYOUT_POPULATIONS;
+    if (pops)
+        tail_cell_kernel_2d<R, 0, 0, 1><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
+    else if (c->P.limiter == POND_LIM_MINMOD)
         tail_cell_kernel_2d<R, 1, REG><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
     else
         tail_cell_kernel_2d<R, 0, REG><<<nb, 256, 0, c->stream>>>(c->P, S, c->slot);
     if (ev_mid) (void)hipEventRecord(ev_mid, c->stream);
-    cell_marked_kernel_2d<R, REG><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
+    if (pops)
+        cell_marked_kernel_2d<R, 0, 1><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
+    else
+        cell_marked_kernel_2d<R, REG><<<blocks(c->P.ncell, 256), 256, 0, c->stream>>>(c->P, S, c->slot);
 }
 
 int compute_span(const pond_ctx *c, int B)
@@ -365,7 +377,9 @@ hipError_t launch_step(pond_ctx *c, double t_end)
             launch_tail_cells_reg<R, 0>(c, S, tm ? c->ev[4] : nullptr);
     } else {
         if (tm) (void)hipEventRecord(c->ev[4], c->stream);
-        if (reg_of(c))
+        if (D == 2 && c->layout == POND_LAYOUT_POPULATIONS)
+            cell_kernel<2, R, 0, 1><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
+        else if (reg_of(c))
             cell_kernel<D, R, 1><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
         else
             cell_kernel<D, R, 0><<<blocks(c->P.ncell, c->cell_block), c->cell_block, 0, c->stream>>>(c->P, S, c->slot);
@@ -1038,7 +1052,7 @@ CkptHeader ckpt_header(const pond_ctx *c)
 
 pond_status pond_save(pond_ctx *c, const char *path)
 {
-    if (!c || !path) return POND_EINVAL;
+    if (!c || !path || c->layout != POND_LAYOUT_HERMITE) return POND_EINVAL;
     FILE *fp = fopen(path, "wb");
     if (!fp) return POND_EINVAL;
     CkptHeader h = ckpt_header(c);
@@ -1060,7 +1074,7 @@ pond_status pond_save(pond_ctx *c, const char *path)
 
 pond_status pond_load(pond_ctx *c, const char *path)
 {
-    if (!c || !path) return POND_EINVAL;
+    if (!c || !path || c->layout != POND_LAYOUT_HERMITE) return POND_EINVAL;
     FILE *fp = fopen(path, "rb");
     if (!fp) return POND_EINVAL;
     CkptHeader h, mine = ckpt_header(c);
@@ -1126,7 +1140,7 @@ pond_status pond_conserved(const pond_ctx *c, double *U)
 
 pond_status pond_populations(const pond_ctx *c, double *f, double *g, double *frame)
 {
-    if (!c || !f || !g || !frame) return POND_EINVAL;
+    if (!c || !f || !g || !frame || c->layout != POND_LAYOUT_HERMITE) return POND_EINVAL;
     const int64_t n = c->P.ncell;
     const int Q = (c->D == 1) ? 4 : (c->D == 2) ? 16 : 64;
     double *df = nullptr, *dg = nullptr, *dfr = nullptr;
@@ -1340,6 +1354,45 @@ pond_status pond_set_iter_split(pond_ctx *c, int32_t k)
     if (!c || k < 0 || c->D == 3) return POND_EINVAL;
     drop_graph(c);
     if (c->D == 2) c->P.iter_split = k;
+    return POND_OK;
+}
+
+pond_status pond_set_state_layout(pond_ctx *c, int32_t layout)
+{
+    if (!c || (layout != POND_LAYOUT_HERMITE && layout != POND_LAYOUT_POPULATIONS)) return POND_EINVAL;
+    if (layout == c->layout) return POND_OK;
+    if (c->D != 2 || semi_lagrangian(c) || reg_of(c) || c->P.limiter != POND_LIM_VANLEER ||
+        c->cfg.seed_mode != POND_SEED_PREV)
+        return POND_EINVAL;
+    drop_graph(c);
+    const int64_t n = c->P.ncell;
+    const int nh = layout == POND_LAYOUT_POPULATIONS ? NPOP2 : Layout<2>::NH;
+    void *dst = nullptr;
+    if (hipMalloc(&dst, c->rsize * nh * n) != hipSuccess) return POND_ENOMEM;
+    const bool to_pops = layout == POND_LAYOUT_POPULATIONS;
+    if (c->precision == POND_FP64) {
+        if (to_pops)
+            coef_to_pops_kernel_2d<double><<<blocks(n, 256), 256, 0, c->stream>>>(
+                c->P, c->U, static_cast<const double *>(c->H), static_cast<double *>(dst));
+        else
+            pops_to_coef_kernel_2d<double><<<blocks(n, 256), 256, 0, c->stream>>>(
+                c->P, static_cast<const double *>(c->H), static_cast<double *>(dst));
+    } else {
+        if (to_pops)
+            coef_to_pops_kernel_2d<float><<<blocks(n, 256), 256, 0, c->stream>>>(
+                c->P, c->U, static_cast<const float *>(c->H), static_cast<float *>(dst));
+        else
+            pops_to_coef_kernel_2d<float><<<blocks(n, 256), 256, 0, c->stream>>>(
+                c->P, static_cast<const float *>(c->H), static_cast<float *>(dst));
+    }
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipFree(dst);
+        return POND_EDEVICE;
+    }
+    (void)hipFree(c->H);
+    c->H = dst;
+    c->nh = nh;
+    c->layout = layout;
     return POND_OK;
 }
 
@@ -1776,7 +1829,8 @@ pond_status pond_mlp_targets(pond_ctx *c, const float *X, const float *ref, floa
 
 pond_status pond_load_mlp(pond_ctx *c, const pond_mlp *m, int32_t hard_iters)
 {
-    if (!c || !m || !m->dev.ready || hard_iters < 1 || c->D == 3) return POND_EINVAL;
+    if (!c || !m || !m->dev.ready || hard_iters < 1 || c->D == 3 || c->layout != POND_LAYOUT_HERMITE)
+        return POND_EINVAL;
     drop_graph(c);
     MlpDevice &M = c->mlp;
     if (!M.master) {

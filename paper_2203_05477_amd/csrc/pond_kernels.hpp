@@ -358,10 +358,66 @@ PD CellRef map2d(const Params &P, int i, int j, double t)
     return r;
 }
 
+// 2D population state (LAY = 1): the 16 f and 16 g populations of each cell in its own
+// co-moving frame, node i = ix + 4 iy, one plane each (f planes 0..15, g planes 16..31).
+// They are the same information as the 12 Hermite coefficients of the default layout (a
+// change of basis, exact with the Gauss-Hermite nodes); these convert between the two.
+constexpr int NPOP2 = 32;
+
+template <typename R>
+PD R inv_weight2(int i)
+{
+    const int ix = i & 3, iy = i >> 2;
+    const double wx = (ix == 1 || ix == 2) ? Lat<double>::wa : Lat<double>::wb;
+    const double wy = (iy == 1 || iy == 2) ? Lat<double>::wa : Lat<double>::wb;
+    return (R)(1.0 / (wx * wy));
+}
+
+template <typename R>
+PD R weight2(int i)
+{
+    return weight1<R>(i & 3) * weight1<R>(i >> 2);
+}
+
+// f's coefficients h20 h11 h02 h30 h21 h12 h03 and g's h10 h01 h20 h11 h02 of cell c
+template <typename R>
+PD void coef_from_pops_2d(const R *Pp, int64_t n, int64_t c, R fh[7], R gh[5])
+{
+    R p[16], mu[10], h[10];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) p[i] = Pp[i * n + c] * inv_weight2<R>(i);
+    moments_2d(p, mu, 10);
+    mu2h_2d(mu, h, 10);
+#pragma unroll
+    for (int k = 0; k < 7; ++k) fh[k] = h[3 + k];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) p[i] = Pp[(16 + i) * n + c] * inv_weight2<R>(i);
+    moments_2d(p, mu, 6);
+    mu2h_2d(mu, h, 6);
+#pragma unroll
+    for (int k = 0; k < 5; ++k) gh[k] = h[1 + k];
+}
+
+// the 32 populations of cell c from its coefficients: f from (rho, 0, 0, fh), g from
+// (b0, gh) with g's zeroth coefficient b0 = (C_v - 1) rho T - T (h20 + h02) (the energy)
+template <typename R>
+PD void pops_from_coef_2d(R *Pp, int64_t n, int64_t c, R rho, R b0, const R fh[7], const R gh[5])
+{
+    R h[10] = {rho, R(0), R(0), fh[0], fh[1], fh[2], fh[3], fh[4], fh[5], fh[6]};
+    R p[16];
+    eval_2d(h, p, 3);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Pp[i * n + c] = weight2<R>(i) * p[i];
+    R hg[10] = {b0, gh[0], gh[1], gh[2], gh[3], gh[4], R(0), R(0), R(0), R(0)};
+    eval_2d(hg, p, 2);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) Pp[(16 + i) * n + c] = weight2<R>(i) * p[i];
+}
+
 // phi-bar-plus of one cell into an LDS record (Sec. III.B.3): phi+ = A f~ + B f_eq with
 // A = (2 - eps/2)/(2 + eps), B = (3 eps/2)/(2 + eps), eps = dt p / mu; f_eq = rho W_i
 // and g_eq = (C_v - D/2) rho T W_i in the co-moving frame (Sec. II.B).
-template <int D, typename R>
+template <int D, typename R, int LAY = 0>
 PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double dt, R *out,
                     int NT, int slot)
 {
@@ -378,10 +434,14 @@ PD void plus_record(const Params &P, const State<R> &S, const CellRef &c, double
         T = st[3] / st[0];
     } else {
         prim<D>(S.U, P.ncell, c.src, rho, u, T, P.Cv);
+        if constexpr (D == 2 && LAY == 1) {
+            coef_from_pops_2d(S.H, P.ncell, c.src, fh, gh);
+        } else {
 #pragma unroll
-        for (int k = 0; k < nfh; ++k) fh[k] = S.H[k * P.ncell + c.src];
+            for (int k = 0; k < nfh; ++k) fh[k] = S.H[k * P.ncell + c.src];
 #pragma unroll
-        for (int k = 0; k < ngh; ++k) gh[k] = S.H[(nfh + k) * P.ncell + c.src];
+            for (int k = 0; k < ngh; ++k) gh[k] = S.H[(nfh + k) * P.ncell + c.src];
+        }
         if (D == 1) {
             if (c.mx) {
                 u[0] = -u[0];
@@ -1299,7 +1359,7 @@ __global__ __launch_bounds__(256) void face_kernel_1d(Params P, State<R> S, int 
 // that the record loads take their plane offsets as immediates; 0: the tile's own size.
 // The FP64 Van Leer kernel is held to 2 waves per SIMD: it then spills a few registers,
 // and still runs 17% faster than with 1 wave (the FP64 minmod kernel does not gain).
-template <typename R, int LIM, int NTS, int REG = 0>
+template <typename R, int LIM, int NTS, int REG = 0, int LAY = 0>
 __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void face_kernel_2d(Params P, State<R> S)
 {
     extern __shared__ unsigned char smem_raw[];
@@ -1320,7 +1380,7 @@ __global__ __launch_bounds__(256, (sizeof(R) == 8 && LIM == 0) ? 2 : 1) void fac
         // faces reference cells in [-2, nx+1] x [-2, ny+1] only
         if (ci > P.nx + 1 || cj > P.ny + 1) continue;
         CellRef c = map2d(P, ci, cj, t);
-        plus_record<2, R>(P, S, c, dt, L + e, NT, 0);
+        plus_record<2, R, LAY>(P, S, c, dt, L + e, NT, 0);
     }
     __syncthreads();
     const int i = i0 + threadIdx.x, j = j0 + threadIdx.y;
@@ -1411,7 +1471,7 @@ PD R group_sum(R v)
 // One face per 16-lane group. Every lane of the wave runs every instruction of the
 // iteration (a group that is done, or has no face, computes and discards), so the cross-lane
 // sums and the LDS exchange never run under a partial execution mask.
-template <typename R, int AXIS, int LIM, int REG = 0>
+template <typename R, int AXIS, int LIM, int REG = 0, int LAY = 0>
 PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e, bool has,
                   int q, double dt, double t, FaceCount &cnt)
 {
@@ -1422,7 +1482,7 @@ PD void tail_face(const Params &P, const State<R> &S, R *rec, R *coef, int64_t e
         int ci, cj;
         tail_cell<AXIS>(P, f, q, ci, cj);
         CellRef c = map2d(P, ci, cj, t);
-        plus_record<2, R>(P, S, c, dt, rec + q, 8, 0);
+        plus_record<2, R, LAY>(P, S, c, dt, rec + q, 8, 0);
     }
     wave_fence();
     const double dn = AXIS ? P.dy : P.dx, dtn = AXIS ? P.dx : P.dy;
@@ -1693,7 +1753,7 @@ struct TailShared {
 };
 
 // block bx of nbx (256 threads) of the tail work of one axis
-template <typename R, int LIM, int REG = 0>
+template <typename R, int LIM, int REG = 0, int LAY = 0>
 PD void tail_block(const Params &P, const State<R> &S, TailShared<R, REG> &sh, int axis, int bx, int nbx)
 {
     R *lds = sh.rec;
@@ -1726,9 +1786,9 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R, REG> &sh, i
         int64_t e = 0;
         if (has) e = tail_entry(P, pre, axis, k);
         if (axis == 0)
-            tail_face<R, 0, LIM, REG>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 0, LIM, REG, LAY>(P, S, rec, coef, e, has, q, dt, t, cnt);
         else
-            tail_face<R, 1, LIM, REG>(P, S, rec, coef, e, has, q, dt, t, cnt);
+            tail_face<R, 1, LIM, REG, LAY>(P, S, rec, coef, e, has, q, dt, t, cnt);
     }
     stat_add4(S.stats, ST_TAIL_FACES, (unsigned)cnt.tail_faces, ST_NONCONV, (unsigned)cnt.nonconv,
               ST_FALLBACK, (unsigned)cnt.fallback, ST_DEPOUT, (unsigned)cnt.depout);
@@ -1738,11 +1798,11 @@ PD void tail_block(const Params &P, const State<R> &S, TailShared<R, REG> &sh, i
     if (cnt.depout) atomicOr(S.err, ERR_DEPART);
 }
 
-template <typename R, int LIM, int REG = 0>
+template <typename R, int LIM, int REG = 0, int LAY = 0>
 __global__ __launch_bounds__(256) void face_tail_kernel_2d(Params P, State<R> S)
 {
     __shared__ TailShared<R, REG> sh;
-    tail_block<R, LIM, REG>(P, S, sh, blockIdx.y, blockIdx.x, gridDim.x);
+    tail_block<R, LIM, REG, LAY>(P, S, sh, blockIdx.y, blockIdx.x, gridDim.x);
 }
 
 // clears n ints (grid-stride)
@@ -1818,13 +1878,13 @@ PD void face_flux(const Params &P, const State<R> &S, int64_t f, int axis, doubl
     }
 }
 
-template <int D, typename R, int REG = 0>
+template <int D, typename R, int REG = 0, int LAY = 0>
 PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
                     unsigned long long &bits, bool &all_conv);
 
 // update of cell c (taken = false: no cell for this lane), with the wave-level CFL maximum
 // and counters; every lane of the wave calls it
-template <int D, typename R, int REG = 0>
+template <int D, typename R, int REG = 0, int LAY = 0>
 PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int slot)
 {
     const bool active = taken && c < P.ncell;
@@ -1833,19 +1893,19 @@ PD void cell_step(const Params &P, const State<R> &S, int64_t c, bool taken, int
     const bool work = active && dt > 0.0;
     unsigned long long bits = 0ull;
     bool all_conv = false;
-    if (work) cell_update<D, R, REG>(P, S, c, k, dt, slot, bits, all_conv);
+    if (work) cell_update<D, R, REG, LAY>(P, S, c, k, dt, slot, bits, all_conv);
     vmax_update<R>(P, S, slot ^ 1, k, work, bits);
     stat_add4(S.stats, ST_CELLS, work ? 1u : 0u, ST_CONV_CELLS, (work && all_conv) ? 1u : 0u, -1, 0u,
               -1, 0u);
 }
 
-template <int D, typename R, int REG = 0>
+template <int D, typename R, int REG = 0, int LAY = 0>
 __global__ __launch_bounds__(256) void cell_kernel(Params P, State<R> S, int slot)
 {
     // contiguous runs of blocks per XCD: the rows above and below, which share y-faces, in
     // the same L2
     const int64_t blk = xcd_tile((int)blockIdx.x, (int)gridDim.x);
-    cell_step<D, R, REG>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
+    cell_step<D, R, REG, LAY>(P, S, blk * blockDim.x + threadIdx.x, true, slot);
 }
 
 // 1D, resident: one block runs every step of a pond_step call for one tube (block b takes
@@ -2553,34 +2613,34 @@ __global__ void sl_commit_kernel(Params P, State<R> S, int nh)
 constexpr int TAIL_BLOCKS = 4 * NSLOT;
 static_assert((2 * TAIL_BLOCKS) % NXCD == 0, "the cell blocks start on XCD 0");
 
-template <typename R, int LIM, int REG = 0>
+template <typename R, int LIM, int REG = 0, int LAY = 0>
 __global__ __launch_bounds__(256) void tail_cell_kernel_2d(Params P, State<R> S, int slot)
 {
     __shared__ TailShared<R, REG> sh;
     if ((int)blockIdx.x < 2 * TAIL_BLOCKS) {
-        tail_block<R, LIM, REG>(P, S, sh, (int)blockIdx.x / TAIL_BLOCKS, (int)blockIdx.x % TAIL_BLOCKS,
-                           TAIL_BLOCKS);
+        tail_block<R, LIM, REG, LAY>(P, S, sh, (int)blockIdx.x / TAIL_BLOCKS, (int)blockIdx.x % TAIL_BLOCKS,
+                                TAIL_BLOCKS);
         return;
     }
     // 2 * TAIL_BLOCKS is a multiple of the XCD count: cell block k runs on XCD k mod 8
     const int64_t blk = xcd_tile((int)blockIdx.x - 2 * TAIL_BLOCKS, (int)gridDim.x - 2 * TAIL_BLOCKS);
     const int64_t c = blk * 256 + threadIdx.x;
-    cell_step<2, R, REG>(P, S, c, c < P.ncell && !S.tblock[c], slot);
+    cell_step<2, R, REG, LAY>(P, S, c, c < P.ncell && !S.tblock[c], slot);
 }
 
 // After the tail: the cells in the stencils of its faces (marked by the face kernel), one
 // thread per cell of the grid; each clears its mark for the next step.
-template <typename R, int REG = 0>
+template <typename R, int REG = 0, int LAY = 0>
 __global__ __launch_bounds__(256) void cell_marked_kernel_2d(Params P, State<R> S, int slot)
 {
     const int64_t c = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const bool marked = c < P.ncell && S.tblock[c] != 0;
     if (!__any(marked)) return;
     if (marked) S.tblock[c] = 0;
-    cell_step<2, R, REG>(P, S, c, marked, slot);
+    cell_step<2, R, REG, LAY>(P, S, c, marked, slot);
 }
 
-template <int D, typename R, int REG>
+template <int D, typename R, int REG, int LAY>
 PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double dt, int slot,
                     unsigned long long &bits_out, bool &all_conv_out)
 {
@@ -2652,10 +2712,17 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
     } else {
         const int i = (int)(c % P.nx), j = (int)(c / P.nx);
         R h[10] = {(R)rho, R(0), R(0)};
-        for (int q = 0; q < 7; ++q) h[3 + q] = S.H[q * n + c];
         R hg[10];
+        if constexpr (LAY == 1) {
+            R fh[7], gh[5];
+            coef_from_pops_2d(S.H, n, c, fh, gh);
+            for (int q = 0; q < 7; ++q) h[3 + q] = fh[q];
+            for (int q = 0; q < 5; ++q) hg[1 + q] = gh[q];
+        } else {
+            for (int q = 0; q < 7; ++q) h[3 + q] = S.H[q * n + c];
+            for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
+        }
         hg[0] = (R)(geq - T * ((double)h[3] + (double)h[5]));
-        for (int q = 0; q < 5; ++q) hg[1 + q] = S.H[(7 + q) * n + c];
         h2mu_2d(h, mfo, 10);
         h2mu_2d(hg, mgo, 6);
 #pragma unroll
@@ -2793,10 +2860,21 @@ PD void cell_update(const Params &P, const State<R> &S, int64_t c, int k, double
         shift_2d(mfo, r, dxs, dys, 10);
         mfo[0] = (R)rn;
         mu2h_2d(mfo, hh, 10);
-        for (int q = 0; q < 7; ++q) S.H[q * n + c] = hh[3 + q];
-        shift_2d(mgo, r, dxs, dys, 6);
-        mu2h_2d(mgo, hh, 6);
-        for (int q = 0; q < 5; ++q) S.H[(7 + q) * n + c] = hh[1 + q];
+        if constexpr (LAY == 1) {
+            R fh[7], gh[5];
+            for (int q = 0; q < 7; ++q) fh[q] = hh[3 + q];
+            shift_2d(mgo, r, dxs, dys, 6);
+            mu2h_2d(mgo, hh, 6);
+            for (int q = 0; q < 5; ++q) gh[q] = hh[1 + q];
+            const double Tp = fabs(Tn);
+            const R b0 = (R)((P.Cv - 1.0) * rn * Tp - Tp * ((double)fh[0] + (double)fh[2]));
+            pops_from_coef_2d(S.H, n, c, (R)rn, b0, fh, gh);
+        } else {
+            for (int q = 0; q < 7; ++q) S.H[q * n + c] = hh[3 + q];
+            shift_2d(mgo, r, dxs, dys, 6);
+            mu2h_2d(mgo, hh, 6);
+            for (int q = 0; q < 5; ++q) S.H[(7 + q) * n + c] = hh[1 + q];
+        }
     }
     for (int q = 0; q < D + 2; ++q) S.U[q * n + c] = Un[q];
     // CFL rate of the new frame: max_a (|u_a| + sqrt(T) c_max) / dx_a
@@ -2961,6 +3039,35 @@ __global__ void pops_kernel(Params P, State<R> S, double *f, double *g, double *
         frame[n + c] = u[1];
         frame[2 * n + c] = T;
     }
+}
+
+// the 2D state between its two layouts (pond_set_state_layout): coefficients H (12 planes)
+// to populations Pp (32 planes), and back
+template <typename R>
+__global__ void coef_to_pops_kernel_2d(Params P, const double *U, const R *H, R *Pp)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.ncell;
+    if (c >= n) return;
+    double rho, u[2], T;
+    prim<2>(U, n, c, rho, u, T, P.Cv);
+    R fh[7], gh[5];
+    for (int q = 0; q < 7; ++q) fh[q] = H[q * n + c];
+    for (int q = 0; q < 5; ++q) gh[q] = H[(7 + q) * n + c];
+    const R b0 = (R)((P.Cv - 1.0) * rho * T - T * ((double)fh[0] + (double)fh[2]));
+    pops_from_coef_2d(Pp, n, c, (R)rho, b0, fh, gh);
+}
+
+template <typename R>
+__global__ void pops_to_coef_kernel_2d(Params P, const R *Pp, R *H)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n = P.ncell;
+    if (c >= n) return;
+    R fh[7], gh[5];
+    coef_from_pops_2d(Pp, n, c, fh, gh);
+    for (int q = 0; q < 7; ++q) H[q * n + c] = fh[q];
+    for (int q = 0; q < 5; ++q) H[(7 + q) * n + c] = gh[q];
 }
 
 // lab-frame moments of the face populations (for comparison with a lab-frame reference)

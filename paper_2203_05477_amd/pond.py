@@ -23,6 +23,7 @@ SEED = {"prev": 0, "mlp": 1}
 FLAG_STRICT = 1
 FLAG_REG_EQ = 2
 FLAG_SEMI_LAGRANGIAN = 4
+LAYOUT = {"hermite": 0, "populations": 1}  # pond_set_state_layout
 
 
 class PondError(RuntimeError):
@@ -120,6 +121,7 @@ def load(path: str | None = None):
                                ctypes.POINTER(ctypes.c_int32)]),
         "pond_autotune": (S, [_P]),
         "pond_set_iter_split": (S, [_P, ctypes.c_int32]),
+        "pond_set_state_layout": (S, [_P, ctypes.c_int32]),
         "pond_set_graph": (S, [_P, ctypes.c_int32]),
         "pond_set_resident": (S, [_P, ctypes.c_int32]),
         "pond_save": (S, [_P, ctypes.c_char_p]),
@@ -159,7 +161,8 @@ def exported_symbols():
             "pond_populations", "pond_nfaces", "pond_face_frames", "pond_set_face_frames",
             "pond_face_moments", "pond_face_iters", "pond_time", "pond_failed_instances",
             "pond_set_stream",
-            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split", "pond_set_graph",
+            "pond_set_tiles", "pond_get_tiles", "pond_autotune", "pond_set_iter_split", "pond_set_state_layout",
+            "pond_set_graph",
             "pond_set_resident",
             "pond_save", "pond_load",
             "pond_enable_timing",
@@ -395,6 +398,13 @@ class Context:
         rc = load().pond_set_iter_split(self._h, int(k))
         if rc != OK:
             raise PondError(rc, "pond_set_iter_split")
+
+    def set_state_layout(self, layout: str):
+        """"hermite" (the default: 12 Hermite coefficients per 2D cell) or "populations" (the
+        32 populations); the current state is converted."""
+        rc = load().pond_set_state_layout(self._h, LAYOUT[layout])
+        if rc != OK:
+            raise PondError(rc, "pond_set_state_layout")
 
 
     # ---- learned seed ----

@@ -50,7 +50,7 @@ def test_library_loads_and_reports_abi_version():
     from paper_2203_05477_amd import pond
 
     lib = pond.load()
-    assert lib.pond_abi_version() == 4
+    assert lib.pond_abi_version() == 5
     assert lib.pond_strerror(1) == b"invalid argument"
     assert lib.pond_mlp_nparams() == 8515
 
