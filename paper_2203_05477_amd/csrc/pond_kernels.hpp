@@ -2234,11 +2234,16 @@ PD void sl_advect_2d(const R *L, int base, R ux, R uy, R inv_s, const R dx[4], c
             R p[16];
             cell_pops_2d<R, G, REG>(L, SL2_NT, base + a + SL2_W * b, ux, uy, inv_s, p);
 #pragma unroll
-            for (int i = 0; i < 16; ++i) {
-                row[i] = fma(wx[i & 3], p[i], row[i]);
-                const bool in = cx[i & 3] && ry[i >> 2];
-                lo[i] = in ? fmin(lo[i], p[i]) : lo[i];
-                hi[i] = in ? fmax(hi[i], p[i]) : hi[i];
+            for (int i = 0; i < 16; ++i) row[i] = fma(wx[i & 3], p[i], row[i]);
+            // only the 3 x 3 centres around the cell can enclose a departure point (a, b
+            // are the same in every lane: a uniform branch)
+            if (a >= 1 && a <= 3 && b >= 1 && b <= 3) {
+#pragma unroll
+                for (int i = 0; i < 16; ++i) {
+                    const bool in = cx[i & 3] && ry[i >> 2];
+                    lo[i] = in ? fmin(lo[i], p[i]) : lo[i];
+                    hi[i] = in ? fmax(hi[i], p[i]) : hi[i];
+                }
             }
         }
 #pragma unroll
@@ -2446,7 +2451,7 @@ PD unsigned long long sl_finish(const Params &P, const State<R> &S, int64_t c, d
 // 6 planes of tail_n R) and it | have_pp << 16 are appended to the list, whose length is
 // tail_count[0] (cleared by dt_kernel); a full list leaves the cell here.
 template <typename R, int REG, bool SPLIT>
-__global__ __launch_bounds__(256) void sl_kernel_2d(Params P, State<R> S, int slot)
+__global__ __launch_bounds__(256, sizeof(R) == 4 ? 3 : 1) void sl_kernel_2d(Params P, State<R> S, int slot)
 {
     __shared__ R L[Layout<2>::NL * SL2_NT];
     const int tx = (int)blockIdx.x % ((P.nx + SL2_T - 1) / SL2_T);
