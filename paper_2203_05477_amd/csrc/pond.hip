@@ -436,16 +436,17 @@ hipError_t launch_step3(pond_ctx *c, double t_end)
     const Geo3 &G = c->G3;
     const bool mm = c->P.limiter == POND_LIM_MINMOD;
     // one block per 64 faces of a row of faces along x (the stencil rows staged in LDS)
-    const unsigned b0 = (unsigned)face3_blocks(G, 0), b1 = (unsigned)face3_blocks(G, 1),
-                   b2 = (unsigned)face3_blocks(G, 2);
+    constexpr int FPB = fpb3<R>(), NTH = 4 * FPB;
+    const unsigned b0 = (unsigned)face3_blocks(G, 0, FPB), b1 = (unsigned)face3_blocks(G, 1, FPB),
+                   b2 = (unsigned)face3_blocks(G, 2, FPB);
     if (mm) {
-        face_kernel_3d<R, 0, 1><<<b0, 256, 0, c->stream>>>(c->P, G, S, rec);
-        face_kernel_3d<R, 1, 1><<<b1, 256, 0, c->stream>>>(c->P, G, S, rec);
-        face_kernel_3d<R, 2, 1><<<b2, 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 0, 1><<<b0, NTH, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 1, 1><<<b1, NTH, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 2, 1><<<b2, NTH, 0, c->stream>>>(c->P, G, S, rec);
     } else {
-        face_kernel_3d<R, 0, 0><<<b0, 256, 0, c->stream>>>(c->P, G, S, rec);
-        face_kernel_3d<R, 1, 0><<<b1, 256, 0, c->stream>>>(c->P, G, S, rec);
-        face_kernel_3d<R, 2, 0><<<b2, 256, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 0, 0><<<b0, NTH, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 1, 0><<<b1, NTH, 0, c->stream>>>(c->P, G, S, rec);
+        face_kernel_3d<R, 2, 0><<<b2, NTH, 0, c->stream>>>(c->P, G, S, rec);
     }
     if (tm) (void)hipEventRecord(c->ev[3], c->stream);
     if (tm) (void)hipEventRecord(c->ev[4], c->stream);

@@ -498,13 +498,16 @@ PD void frame_of3(const R *mf, const R *mg, R s, double Cv, R &rho, R du[3], R &
     Tn = temperature(rhoe, rho, irho, Cv);
 }
 
-// The stencil rows of a block's faces in LDS. A block takes 64 consecutive faces of one
+// The stencil rows of a block's faces in LDS. A block takes FPB consecutive faces of one
 // row of faces along x (fixed j, k); their 12-cell stencils lie in a few rows of cells along
-// x, each within x0 - 2 .. x0 + 65 (x0 = the block's first face): 5 rows for the x faces
-// (the face row and its four neighbours across), 8 for the y and z faces (the two cells on
-// each side along the normal, and the L and R rows' neighbours along the other tangential
-// axis). Row r lies at (j + RJ[r], k + RK[r]) relative to the faces' (j, k).
-constexpr int ROW3 = 68; // slots per row: x0 - 2 .. x0 + 65
+// x, each within x0 - 2 .. x0 + FPB + 1 (x0 = the block's first face): 5 rows for the x
+// faces (the face row and its four neighbours across), 8 for the y and z faces (the two
+// cells on each side along the normal, and the L and R rows' neighbours along the other
+// tangential axis). Row r lies at (j + RJ[r], k + RK[r]) relative to the faces' (j, k).
+// FPB = 64 in FP32; 32 in FP64, whose records take twice the LDS: a block of 128 threads
+// then needs 46 KB (x faces) or 74 KB (y, z), so that two blocks fit a compute unit.
+template <typename R>
+PD __host__ constexpr int fpb3() { return sizeof(R) == 8 ? 32 : 64; }
 
 template <int AXIS>
 struct Rows3 {
@@ -557,9 +560,9 @@ PD __host__ int64_t face3_rows(const Geo3 &G, int axis)
 {
     return axis == 0 ? (int64_t)G.ny * G.nz : axis == 1 ? (int64_t)(G.ny + 1) * G.nz : (int64_t)G.ny * (G.nz + 1);
 }
-PD __host__ int64_t face3_blocks(const Geo3 &G, int axis)
+PD __host__ int64_t face3_blocks(const Geo3 &G, int axis, int fpb)
 {
-    return face3_rows(G, axis) * ((face3_rowlen(G, axis) + 63) / 64);
+    return face3_rows(G, axis) * ((face3_rowlen(G, axis) + fpb - 1) / fpb);
 }
 
 // Face f of axis AXIS, four lanes (n = lane & 3). The predictor frame is the previous step's
@@ -568,22 +571,24 @@ PD __host__ int64_t face3_blocks(const Geo3 &G, int axis)
 // and the first-order fallback of the 2D kernels. Writes the face state of Sec. III.B.3:
 // phi = (phi-bar + (eps/4) phi_eq) / (1 + eps/4) in the final frame, eps = dt p_b / mu.
 template <typename R, int AXIS, int LIM>
-__global__ __launch_bounds__(256) void face_kernel_3d(Params P, Geo3 G, State<R> S, const R *grec)
+__global__ __launch_bounds__(4 * fpb3<R>(), sizeof(R) == 8 ? 2 : 1) void face_kernel_3d(Params P, Geo3 G, State<R> S,
+                                                                                     const R *grec)
 {
+    constexpr int FPB = fpb3<R>(), ROW3 = FPB + 4, NTH = 4 * FPB;
     constexpr int NROW = Rows3<AXIS>::n, NRW = NROW * ROW3;
     __shared__ R lds[NR3 * NRW];
     const double dt = S.dt[0];
     if (!(dt > 0.0)) return;
     const int len = face3_rowlen(G, AXIS);
-    const int nch = (len + 63) / 64;
+    const int nch = (len + FPB - 1) / FPB;
     const int64_t b = xcd_tile((int)blockIdx.x, (int)gridDim.x);
     const int64_t r = b / nch;
-    const int x0 = (int)(b % nch) * 64;
+    const int x0 = (int)(b % nch) * FPB;
     const int rows_j = AXIS == 1 ? G.ny + 1 : G.ny;
     const int fj = (int)(r % rows_j), fk = (int)(r / rows_j);
     // fill the LDS rows (mirrored cells stored mirrored); slots past x = nx + 1 are never read
     const int64_t ncg = P.ncell;
-    for (int e = threadIdx.x; e < NRW; e += 256) {
+    for (int e = threadIdx.x; e < NRW; e += NTH) {
         const int row = e / ROW3, x = x0 - 2 + e % ROW3;
         if (x > G.nx + 1) continue;
         int rj = 0, rk = 0;
