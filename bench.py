@@ -130,7 +130,11 @@ def cell_update_hbm(st, kt, steps, precision, layout="hermite"):
 def other_workload(args):
     """The other workloads, mixed and FP64 forms (plain seed), same JSON line: the shocked
     interface (2048 x 512), the Mach-80 jet (2048 x 2048; it fails within tens of steps, so
-    the default run is short and a failure is reported), or the batch of 4096 shock tubes."""
+    the default run is short and a failure is reported), or the batch of 4096 shock tubes.
+    The mixed form's gate, as on the headline: its relative L1 distance after the warm-up
+    and timed steps from an FP64 run at the same iteration tolerance over the same steps is
+    at most 1e-4 per conserved field; `value` is the mixed rate when it passes, else the
+    FP64 form's."""
     import oracle
     from paper_2203_05477_amd import pond
     from paper_2203_05477_amd import workloads as W
@@ -147,6 +151,9 @@ def other_workload(args):
         make = lambda tol: W.tube_batch(tol=tol)
     out = {}
     forms = [("mixed", "mixed", W.TOL_FP32, "prev"), ("fp64", "fp64", W.TOL_FP64, "prev")]
+    if name != "tubes":
+        # the mixed form at a tighter iteration tolerance, as on the headline
+        forms.insert(1, ("mixed_tol1e-6", "mixed", 1e-6, "prev"))
     net = None
     if name == "shocked_interface" and not args.no_learned:
         # the configuration that names the learned frame guess: the same steps with the seed
@@ -180,6 +187,15 @@ def other_workload(args):
             out[form]["train"] = train_info
         if net is not None and form in ("mixed", "learned_mixed"):
             out[form]["U"] = ctx.conserved()
+        if form in ("mixed", "mixed_tol1e-6"):
+            Um = ctx.conserved()
+            ref = pond.Context(cfg, fields, precision="fp64")
+            ref.step(args.warmup + args.steps, check=False)
+            l1 = rel_l1(Um, ref.conserved())
+            ref.close()
+            keys = ("rho", "rho_u", "rho_E") if name == "tubes" else ("rho", "rho_u", "rho_v", "rho_E")
+            out[form]["rel_l1_vs_fp64_same_tol"] = dict(zip(keys, l1))
+            out[form]["l1_gate"] = bool(np.all(np.isfinite(l1)) and max(l1) <= L1_GATE)
         ctx.close()
         if name == "tubes" and args.scheme == "fv":
             # the same steps with the resident kernel (one block per tube, every step in one
@@ -233,20 +249,28 @@ def other_workload(args):
         Ul, Um = out["learned_mixed"].pop("U"), out["mixed"].pop("U")
         out["learned_mixed"]["rel_l1_vs_plain_mixed"] = rel_l1(Ul, Um)
     m = out["mixed"]
-    best = m
-    if "resident" in m and m["resident"]["value"] > m["value"]:
-        best = m["resident"]
+    passing = [out[k] for k in ("mixed", "mixed_tol1e-6") if k in out and out[k]["l1_gate"]]
+    fp32 = bool(passing)
+    form = max(passing, key=lambda r: r["value"]) if fp32 else out["fp64"]
+    best = form
+    if "resident" in form and form["resident"]["value"] > form["value"]:
+        best = form["resident"]
     line = {
         "metric": METRIC, "value": best["value"], "unit": "Mcell-updates/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": {"shocked_interface": "shocked_interface_2048x512", "jet": "jet_2048x2048",
                                 "tubes": "tube_batch_4096", "explosion_box": "explosion_box_256x256"}[name],
                    "scheme": args.scheme,
-                   "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
-        "roofline": tube_roofline(m, args.steps) if name == "tubes" and args.scheme == "fv" else None,
-        "mixed": m, "fp64_plain": out["fp64"], "learned_mixed": out.get("learned_mixed"),
+                   "precision": "mixed (f32 populations, f64 conserved)" if fp32 else "fp64", "seed": "plain",
+                   "form": next((k for k in ("mixed", "mixed_tol1e-6", "fp64") if out.get(k) is form), None),
+                   "l1_gate": f"relative L1 <= {L1_GATE:g} per conserved field vs an FP64 run at the same "
+                              f"iteration tolerance over the same {args.warmup + args.steps} steps from t = 0"},
+        "roofline": (tube_roofline(m, args.steps) if name == "tubes" and args.scheme == "fv" and fp32
+                     else None),
+        "mixed": m, "mixed_tol1e-6": out.get("mixed_tol1e-6"), "fp64_plain": out["fp64"],
+        "learned_mixed": out.get("learned_mixed"),
         "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
@@ -276,7 +300,10 @@ def box3d_roofline(m):
 def box3d_workload(args):
     """The explosion in a closed box on the D3Q64 lattice (n^3 cells, reflecting walls),
     mixed and FP64 forms from the same state: converged cell-updates per second over the
-    timed steps, the kernels' HIP-event times, and the oracle on a bounded sample."""
+    timed steps, the kernels' HIP-event times, and the oracle on a bounded sample. The
+    mixed form's gate, as on the headline: its relative L1 distance after the warm-up and
+    timed steps from an FP64 run at the same iteration tolerance over the same steps is at
+    most 1e-4 per conserved field; `value` is the mixed rate when it passes, else FP64's."""
     import oracle
     from paper_2203_05477_amd import pond
     from paper_2203_05477_amd import workloads as W
@@ -304,6 +331,14 @@ def box3d_workload(args):
                      "mean_iters": st["iters_total"] / max(st["faces"], 1), "iters_max": st["iters_max"],
                      "nonconverged": st["nonconverged"], "status": st["status"],
                      "kernel_ms": {"dt": kt["dt"], "plus_and_faces": kt["face"], "cell": kt["cell"]}}
+        if prec == "mixed":
+            Um = ctx.conserved()
+            ref = pond.Context(cfg, fields, precision="fp64")
+            ref.step(args.warmup + args.steps, check=False)
+            l1 = rel_l1(Um, ref.conserved())
+            ref.close()
+            out[prec]["rel_l1_vs_fp64_same_tol"] = dict(zip(("rho", "rho_u", "rho_v", "rho_w", "rho_E"), l1))
+            out[prec]["l1_gate"] = bool(max(l1) <= L1_GATE)
         ctx.close()
     cpu = None
     if not args.no_cpu_baseline:
@@ -320,14 +355,18 @@ def box3d_workload(args):
                "kind": "oracle", "cpu_model": cpu_model(),
                "sample": f"first {k} steps of the same set-up on {m}^3 cells from t=0 (FP64); {el:.1f} s"}
     m = out["mixed"]
+    best = m if (m["l1_gate"] or "fp64" not in out) else out["fp64"]
+    fp32 = best is m
     line = {
-        "metric": METRIC, "value": m["value"], "unit": "Mcell-updates/s", "n_gpus": 1,
-        "steps": args.steps, "warmup": args.warmup, "ms_per_step": m["ms_per_step"],
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "metric": METRIC, "value": best["value"], "unit": "Mcell-updates/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": best["ms_per_step"],
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32" if fp32 else "f64",
         "data": "synthetic",
         "config": {"workload": f"explosion_box_3d_{n}^3", "lattice": "D3Q64",
-                   "precision": "mixed (f32 populations, f64 conserved)", "seed": "plain"},
-        "roofline": box3d_roofline(m),
+                   "precision": "mixed (f32 populations, f64 conserved)" if fp32 else "fp64", "seed": "plain",
+                   "l1_gate": f"relative L1 <= {L1_GATE:g} per conserved field vs an FP64 run at the same "
+                              f"iteration tolerance over the same {args.warmup + args.steps} steps from t = 0"},
+        "roofline": box3d_roofline(m) if fp32 else None,
         "mixed": m, "fp64_plain": out.get("fp64"), "cpu_baseline": cpu,
     }
     print(json.dumps(line), flush=True)
