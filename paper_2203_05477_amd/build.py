@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libpond.so")
 SOURCES = ["pond.hip"]
-HEADERS = ["pond_core.hpp", "pond_kernels.hpp", "pond_kernels3d.hpp", "pond_mlp.hpp"]
+HEADERS = ["pond_core.hpp", "pond_kernels.hpp", "pond_kernels3d.hpp", "pond_sl2d.hpp", "pond_mlp.hpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

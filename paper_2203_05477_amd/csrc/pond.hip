@@ -16,6 +16,7 @@
 #include "../../include/pond.h"
 #include "pond_kernels.hpp"
 #include "pond_kernels3d.hpp"
+#include "pond_sl2d.hpp"
 #include "pond_mlp.hpp"
 
 using namespace pond;
