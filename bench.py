@@ -769,10 +769,11 @@ def double_mach_workload(args):
 
 
 # semi-Lagrangian step in 2D (Sec. III.A): FLOPs per cell and frame iteration of the SL
-# kernel (kernel count: SQ FLOPS counters over the whole launch with every iteration in it,
-# the collision and reframe shared out over the iterations, at the double Mach
-# reflection's 1.006 (FP32) and 1.019 (FP64) iterations per cell)
-FLOPS_SL_CELL_ITER_2D = {"f32": 13000, "f64": 13700}
+# kernel (kernel count: SQ FLOPS counters over the whole launch, the collision and reframe
+# shared out over the iterations, at the double Mach reflection's 1.006 (FP32) and 1.019
+# (FP64) iterations per cell; the FP32 kernel computes the x weights once per iteration,
+# the FP64 one per stencil cell)
+FLOPS_SL_CELL_ITER_2D = {"f32": 10300, "f64": 12600}
 # Iteration tolerance of the mixed semi-Lagrangian form: in FP32 the frame iteration of the
 # cells whose iteration contracts slowly stalls at a rounding floor above 1e-5 (about 180
 # of the 921,600 cells a step reach max_iter at 1e-5, 25 at 3e-5, 4 at 1e-4 as in FP64)
