@@ -163,22 +163,25 @@ def other_workload(args):
     for form, prec, tol, seed in forms:
         cfg, fields = make(tol)
         cfg["scheme"] = args.scheme
-        ctx = pond.Context(cfg, fields, precision=prec, seed=seed)
-        if seed == "mlp":
-            ctx.load_mlp(net, hard_iters=2)
-        if args.warmup:
-            ctx.step(args.warmup, check=False)
+
+        def fresh():
+            c = pond.Context(cfg, fields, precision=prec, seed=seed)
+            if seed == "mlp":
+                c.load_mlp(net, hard_iters=2)
+            if args.warmup:
+                c.step(args.warmup, check=False)
+            return c
+
+        ctx = fresh()
         ctx.autotune()
-        ctx.enable_timing(True)
+        twin = fresh()
+        twin.set_tiles(*ctx.tiles())
         import torch
 
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.step(args.steps, check=False)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        kt = ctx.kernel_times()
+        st, el, _, kt, trec = timed_steps(ctx, args.steps, twin, check=False)
+        twin.close()
         out[form] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
+                     "twin": trec,
                      "cell_updates": st["cell_updates"], "mean_iters": st["iters_total"] / max(st["faces"], 1),
                      "failed_instances": st["failed_instances"], "status": st["status"],
                      "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
@@ -317,16 +320,14 @@ def box3d_workload(args):
             continue
         cfg, fields = W.explosion_box_3d(n, tol=tol)
         ctx = pond.Context(cfg, fields, precision=prec)
+        twin = pond.Context(cfg, fields, precision=prec)
         if args.warmup:
             ctx.step(args.warmup, check=False)
-        ctx.enable_timing(True)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        st = ctx.step(args.steps, check=False)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        kt = ctx.kernel_times()
+            twin.step(args.warmup, check=False)
+        st, el, _, kt, trec = timed_steps(ctx, args.steps, twin, check=False)
+        twin.close()
         out[prec] = {"value": st["converged_cell_updates"] / el / 1e6, "ms_per_step": 1e3 * el / args.steps,
+                     "twin": trec,
                      "steps": args.steps, "cell_updates": st["cell_updates"], "faces": st["faces"],
                      "mean_iters": st["iters_total"] / max(st["faces"], 1), "iters_max": st["iters_max"],
                      "nonconverged": st["nonconverged"], "status": st["status"],
@@ -527,6 +528,36 @@ def riemann_workload(args):
     print(json.dumps(line), flush=True)
 
 
+def timed_steps(ctx, K, twin=None, check=True):
+    """K steps of `ctx` timed on the host clock around the whole window, with no per-kernel
+    events on the stream (each HIP event record there costs about 4 us; six a step took
+    0.025 ms of a 0.243 ms double Mach step): the rate. The per-kernel times come from
+    `twin`, a second context in the same state with the same launch parameters, which runs
+    the same K steps with HIP events around every launch; the two must end in the same bits.
+    Returns (stats, seconds, conserved state, kernel times or None, twin record or None)."""
+    import torch
+
+    ctx.enable_timing(False)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = ctx.step(K, check=check)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    U = ctx.conserved()
+    if twin is None:
+        return st, el, U, None, None
+    twin.enable_timing(True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    twin.step(K, check=check)
+    torch.cuda.synchronize()
+    el2 = time.perf_counter() - t1
+    kt = twin.kernel_times()
+    rec = {"same_state": bool(np.array_equal(U, twin.conserved())),
+           "ms_per_step_with_events": 1e3 * el2 / K}
+    return st, el, U, kt, rec
+
+
 def rel_l1(U, R):
     """Relative L1 distance per conserved field, sum |U - R| / sum |R| (uniform cells)."""
     return [float(np.abs(U[k] - R[k]).sum() / np.abs(R[k]).sum()) for k in range(R.shape[0])]
@@ -645,26 +676,27 @@ def double_mach_workload(args):
         r = {"precision": prec, "tol": tol, "seed": "learned" if seed == "mlp" else "plain", "windows": {}}
         chosen = tiles
         for w in windows:
-            ctx = pond.Context(cfg, fields, precision=prec, seed=seed)
-            if args.iter_split is not None:
-                ctx.set_iter_split(args.iter_split)
-            if seed == "mlp":
-                ctx.load_mlp(net, hard_iters=2)
-            ctx.load_state(w["ckpt"])
-            if args.layout == "populations":
-                ctx.set_state_layout("populations")
+            def fresh():
+                c = pond.Context(cfg, fields, precision=prec, seed=seed)
+                if args.iter_split is not None:
+                    c.set_iter_split(args.iter_split)
+                if seed == "mlp":
+                    c.load_mlp(net, hard_iters=2)
+                c.load_state(w["ckpt"])
+                if args.layout == "populations":
+                    c.set_state_layout("populations")
+                return c
+
+            ctx = fresh()
             if chosen:
                 ctx.set_tiles(chosen[0], chosen[1], 256)
             elif not args.no_autotune:
                 chosen = tuple(ctx.autotune()[:2])
-            ctx.enable_timing(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = ctx.step(K)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            kt = ctx.kernel_times()
-            Uf = ctx.conserved()
+            twin = fresh()
+            if chosen:
+                twin.set_tiles(chosen[0], chosen[1], 256)
+            st, el, Uf, kt, trec = timed_steps(ctx, K, twin)
+            twin.close()
             l1 = rel_l1(Uf, w["ref"])
             l1t = rel_l1(Uf, next(x["ref"] for x in tight if x["name"] == w["name"]))
             main_iters = (st["iters_total"] - st["tail_iters"]) / K
@@ -680,6 +712,8 @@ def double_mach_workload(args):
                 "tail_faces_per_step": st["tail_faces"] / K,
                 "kernel_ms": {"dt": kt["dt"], "face": kt["face"], "tail_with_cells": kt["tail"],
                               "cell": kt["cell"], "seed": kt["seed"]},
+                "kernel_ms_from": "instrumented twin window (same state, same steps)",
+                "twin": trec,
                 "cell_update_hbm": cell_update_hbm(st, kt, K, prec, args.layout),
                 "rel_l1_vs_fp64_reference": dict(zip(("rho", "rho_u", "rho_v", "rho_E"), l1)),
                 "rel_l1_vs_fp64_tol1e-13": dict(zip(("rho", "rho_u", "rho_v", "rho_E"), l1t)),
@@ -858,14 +892,10 @@ def double_mach_sl_workload(args):
         for w in refs[tol]:
             ctx = pond.Context(cfg, fields, precision=prec)
             ctx.load_state(w["ckpt"])
-            ctx.enable_timing(True)
-            torch.cuda.synchronize()
-            t0 = time.perf_counter()
-            st = ctx.step(K)
-            torch.cuda.synchronize()
-            el = time.perf_counter() - t0
-            kt = ctx.kernel_times()
-            Uf = ctx.conserved()
+            twin = pond.Context(cfg, fields, precision=prec)
+            twin.load_state(w["ckpt"])
+            st, el, Uf, kt, trec = timed_steps(ctx, K, twin)
+            twin.close()
             l1 = rel_l1(Uf, w["ref"])
             keys = ("rho", "rho_u", "rho_v", "rho_E")
             r["windows"][w["name"]] = {
@@ -878,6 +908,7 @@ def double_mach_sl_workload(args):
                 "rel_l1_vs_fp64_sl_reference": dict(zip(keys, l1)),
                 "rel_l1_vs_fv_fp64_tol1e-13_same_time": dict(zip(keys, rel_l1(Uf, fv[w["name"]]))),
                 "l1_gate": bool(max(l1) <= L1_GATE), "status": st["status"], "t_end": st["t_max"],
+                "twin": trec,
             }
             ctx.close()
         r["l1_gate"] = all(v["l1_gate"] for v in r["windows"].values())
