@@ -179,16 +179,24 @@ bool ensure_tail(pond_ctx *c, int bx, int by)
 
 // plane stride of the 2D face kernel's LDS tile: 256 or 512 (compiled in), else the tile's
 // own size
-int face_nts(int bx, int by)
+// LDS plane stride of the 2D face kernel's record tile (a compile-time constant, so that every
+// record load takes its plane offset as an immediate): the smallest of 256, 384 (FP64 only)
+// and 512 that holds the tile's records, else 0 (a run-time stride). The byte offset of a
+// plane must fit the LDS instruction's 16-bit offset field: 18 planes of 512 doubles do not
+// (the last two planes then need an address register, and the FP64 kernel spills), 18 of 384
+// do, and a 16 x 16 tile needs 361 records.
+int face_nts(int bx, int by, size_t rsize)
 {
     const int n = (bx + 3) * (by + 3);
-    return n <= 256 ? 256 : (n <= 512 ? 512 : 0);
+    if (n <= 256) return 256;
+    if (rsize == 8 && n <= 384) return 384;
+    return n <= 512 ? 512 : 0;
 }
 
 size_t face_lds_bytes(const pond_ctx *c, int bx, int by, int span)
 {
     if (c->D == 1) return (size_t)(bx + 3 + 3 * span) * Layout<1>::NL * c->rsize;
-    const int nts = face_nts(bx, by);
+    const int nts = face_nts(bx, by, c->rsize);
     return (size_t)(nts ? nts : (bx + 3) * (by + 3)) * Layout<2>::NL * c->rsize;
 }
 
@@ -199,9 +207,13 @@ template <typename R, int LIM, int REG, int LAY = 0>
 void launch_face_2d_reg(pond_ctx *c, const State<R> &S, int bx, int by, size_t lds)
 {
     dim3 grid(blocks(c->P.nx + 1, bx), blocks(c->P.ny + 1, by));
-    switch (face_nts(bx, by)) {
+    switch (face_nts(bx, by, sizeof(R))) {
     case 256:
         face_kernel_2d<R, LIM, 256, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
+        break;
+    case 384:
+        if constexpr (sizeof(R) == 8)
+            face_kernel_2d<R, LIM, 384, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
         break;
     case 512:
         face_kernel_2d<R, LIM, 512, REG, LAY><<<grid, dim3(bx, by), lds, c->stream>>>(c->P, S);
