@@ -1,6 +1,7 @@
-"""bench.py's command line on a machine without a GPU: more than one GPU is refused with a
-message, and the HBM traffic figure is read from the committed counter summary only while
-the kernel sources still hash to the value recorded there."""
+"""bench.py on a machine without a GPU: more than one GPU is refused with a message, the HBM
+traffic figure is read from the committed counter summary only while the kernel sources still
+hash to the value recorded there, and a timed window runs without per-kernel events while its
+twin takes the kernel times"""
 import hashlib
 import json
 import os
@@ -53,3 +54,49 @@ def test_tube_traffic_follows_the_source_hash():
         else:
             assert got is None
     assert bench.tube_traffic("no such kernel") is None
+
+
+class _FakeContext:
+    """Stands in for pond.Context in timed_steps: steps advance a counter, the state is that
+    counter (or a planted difference), and kernel times exist only while timing is on."""
+
+    def __init__(self, offset=0.0):
+        self.n, self.offset, self.timing, self.calls = 0, offset, None, []
+
+    def enable_timing(self, on=True):
+        self.timing = bool(on)
+        self.calls.append(("timing", bool(on)))
+
+    def step(self, k, check=True):
+        self.calls.append(("step", k))
+        self.n += k
+        return {"converged_cell_updates": 10 * k, "cell_updates": 10 * k}
+
+    def conserved(self):
+        import numpy as np
+
+        return np.full((4, 3), float(self.n) + self.offset)
+
+    def kernel_times(self):
+        assert self.timing, "kernel times asked of a context without events"
+        return {"dt": 0.001, "face": 0.1, "tail": 0.05, "cell": 0.01, "seed": 0.0}
+
+
+def test_timed_window_runs_without_events_and_its_twin_with_them(monkeypatch):
+    """The rate comes from a window with the per-kernel events off; the kernel times from a
+    twin with them on, which must end in the same state (a twin that does not is reported)."""
+    sys.path.insert(0, ROOT)
+    import bench
+    import torch
+
+    monkeypatch.setattr(torch.cuda, "synchronize", lambda *a, **k: None)
+    ctx, twin = _FakeContext(), _FakeContext()
+    st, el, U, kt, rec = bench.timed_steps(ctx, 7, twin)
+    assert ctx.calls[0] == ("timing", False) and ("step", 7) in ctx.calls
+    assert twin.calls[0] == ("timing", True) and ("step", 7) in twin.calls
+    assert st["cell_updates"] == 70 and el >= 0.0 and U[0, 0] == 7.0
+    assert kt["face"] == 0.1 and rec["same_state"] is True and rec["ms_per_step_with_events"] >= 0.0
+    _, _, _, _, rec = bench.timed_steps(_FakeContext(), 3, _FakeContext(offset=1e-12))
+    assert rec["same_state"] is False
+    _, _, _, kt, rec = bench.timed_steps(_FakeContext(), 3)
+    assert kt is None and rec is None
