@@ -1,7 +1,7 @@
 """bench.py on a machine without a GPU: more than one GPU is refused with a message, the HBM
 traffic figure is read from the committed counter summary only while the kernel sources still
 hash to the value recorded there, and a timed window runs without per-kernel events while its
-twin takes the kernel times"""
+twin takes the kernel times."""
 import hashlib
 import json
 import os
