@@ -172,14 +172,19 @@ def test_periodic_conservation_with_tail(precision):
     assert np.all(np.abs(U1 - U0) <= 1e-13 * scale)
 
 
-def test_2d_tiles_bitwise_identical(orc):
-    """Every 2D tile shape gives bitwise-identical FP64 results (the LDS halo is complete)."""
+@pytest.mark.parametrize("layout", ["hermite", "populations"])
+def test_2d_tiles_bitwise_identical(orc, layout):
+    """Every 2D tile shape gives bitwise-identical FP64 results (the LDS halo is complete),
+    with the state held as coefficients or as populations; the tiles cover every LDS plane
+    stride of the FP64 face kernel (256: 8 x 8, 32 x 2; 384: 16 x 16; 512: 32 x 8, 64 x 4)."""
     from paper_2203_05477_amd import pond
 
     cfg, f = W.double_mach(70, 30)
     outs = []
-    for bx, by in ((8, 8), (16, 16), (32, 2), (64, 4)):
+    for bx, by in ((8, 8), (16, 16), (32, 2), (64, 4), (32, 8)):
         g = pond.Context(cfg, f, precision="fp64")
+        if layout == "populations":
+            g.set_state_layout("populations")
         g.set_tiles(bx, by, 256)
         g.step(12)
         outs.append((g.conserved(), g.face_frames()))
