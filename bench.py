@@ -46,7 +46,7 @@ FLOPS_FACE_ITER = {1: 330, 2: 2236}
 FLOPS_FACE_ITER_EQ2 = 2776
 FLOPS_FACE_FINAL = {1: 60, 2: 330}
 # Peaks of MI355X: FP64 vector 78.6 TFLOP/s, FP32 vector 157.3 TFLOP/s (the FP32 figure
-# counts packed FP32 issue; this build does not emit packed FP32 instructions, so 78.6 is
+# counts packed FP32 issue; the library is compiled without packed FP32 instructions, so 78.6 is
 # also what non-packed FP32 code can reach and is reported beside it); HBM 8 TB/s
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3

@@ -114,7 +114,7 @@ def test_shocked_interface_full_size_fp64(orc):
 
 def test_jet_full_size_fp64(orc):
     """2048 x 2048 Mach-80 jet. Encodes a KNOWN DEPARTURE from Sec. IV.C.5, where the paper
-    runs the jet (on [1000,500] cells); under this build's readings it loses positivity (the
+    runs the jet (on [1000,500] cells); under the readings adopted here it loses positivity (the
     oracle's expected-failure test asserts the paper's outcome on a small grid). Tested here:
     the first step element-wise; in the second, the front of the jet one cell inside the
     inflow boundary reaches T < 0, in the oracle as on the GPU, and the same cells fail on

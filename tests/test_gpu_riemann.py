@@ -118,7 +118,7 @@ def test_riemann_problem_mixed_error_matches_fp64(orc, name):
 
 def test_double_rarefaction_failure_detected_in_the_same_step(orc):
     """Encodes a KNOWN DEPARTURE from Sec. IV.B (the paper runs this case to t = 0.1; under
-    this build's readings the step loses positivity next to the centre, see the oracle's
+    the readings adopted here the step loses positivity next to the centre, see the oracle's
     expected-failure test). What is tested here is failure detection parity: the GPU keeps
     parity with the oracle up to the step whose update leaves a cell with T <= 0, reports
     POND_ENONPHYS for that very step and freezes the tube."""

@@ -85,7 +85,7 @@ def test_conservation_with_exact_boundary_fluxes(orc, name):
 def test_double_rarefaction_symmetric_up_to_known_departure(orc):
     """KNOWN DEPARTURE from Sec. IV.B: the paper reports the printed double rarefaction
     (p = 0.1 on both sides, u = -2 | 2) in good agreement with the exact solution at
-    t = 0.1 on 800 cells; under the readings of this build the step cannot hold it (every
+    t = 0.1 on 800 cells; under the readings adopted here the step cannot hold it (every
     reading tried is listed in the design notes with its failing step). This test pins how
     the case departs, not what the paper shows: the exact solution opens a true vacuum
     (2 (c_L + c_R)/(gamma - 1) < u_R - u_L); the step keeps the mirror symmetry exactly
@@ -121,7 +121,7 @@ def test_double_rarefaction_symmetric_up_to_known_departure(orc):
 def test_double_rarefaction_reaches_the_printed_time(orc):
     """The paper's outcome (Sec. IV.B): the run reaches t = 0.1 on 200 cells with positive
     density and temperature everywhere, and its density is within 10% (relative L1) of the
-    exact solution. Expected to fail under this build's readings."""
+    exact solution. Expected to fail under the readings adopted here."""
     from exact_riemann import sample
 
     cfg, f = W.riemann_case("double_rarefaction", nx=200, tol=1e-10)

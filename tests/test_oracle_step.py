@@ -249,7 +249,7 @@ def test_explosion_box_setup_and_invariants(orc):
 def test_jet_on_the_paper_domain_keeps_running(orc):
     """The paper's 2D jet (Sec. IV.C.5) on its own domain [0,2] x [-0.5,0.5], here on a
     100 x 50 grid: the run keeps positive density and temperature for 300 steps while the
-    bow shock moves into the ambient gas. Expected to fail under this build's readings (the
+    bow shock moves into the ambient gas. Expected to fail under the readings adopted here (the
     shear layer where the jet edge meets the fixed inflow boundary reaches T <= 0 within
     about 50 steps at this resolution)."""
     cfg, f = W.jet(100, 50, x1=2.0, tol=1e-10)
